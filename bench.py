@@ -1,0 +1,248 @@
+"""Benchmark: batched zero-tree OMP on one MI355X.
+
+One step is one cspd_omp_cross_scale call over the whole batch (every scale:
+proxy, argmax, incremental Cholesky, projection, residue updates, output
+and x-hat), with inputs already resident in device memory.  The default
+workload is the 65,536-patch compressive inpainting set (8x8 patches, 4x4
+coarse scale, D_high 64 x 1024, D_low 16 x 128, Q = 8, K = (4, 8), per-patch
+50 % pixel masks, FP32).  The same batch is also solved with full OMP over
+D_high for comparison, and the FP64 oracle is timed on the host cores.
+
+Prints one JSON line.  --gpus above 1 is refused: this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X, published FP32 vector rate
+PEAK_FP32_MATRIX_TFLOPS = 157.3
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def scale_flops(m: int, t_c: int, k: int, norms: bool) -> int:
+    """Algorithmic FLOPs of K OMP iterations over t_c candidates of length m,
+    with incremental least squares (the per-iteration cost model of the
+    paper's Section III-D: proxy O(m t_c), argmax, least squares), plus the
+    per-patch column norms when the operator differs per patch."""
+    f = 0
+    for n in range(1, k + 1):
+        f += 2 * m * t_c + 2 * m * (n - 1) + (n - 1) ** 2 + 2 * m + 2 * n * n + 2 * m * n
+    if norms:
+        f += 2 * m * t_c
+    return f
+
+
+def kernel_flops(w, k_scales):
+    """FLOPs per patch of each per-scale kernel of the cross-scale call and of
+    the full-OMP call, keyed by the kernel role used in the profile labels."""
+    S = w.n_scales
+    mask = w.phi_kind == "mask"
+    out = {}
+    kprev = None
+    for s in range(S):
+        m = w.m if w.phi_kind == "dense" else w.dims[s]
+        t_c = w.atoms[s] if s == 0 else min(w.atoms[s], (w.atoms[s] // w.atoms[s - 1]) * kprev)
+        k = min(k_scales[s], t_c)
+        out[f"s{s}"] = scale_flops(m, t_c, k, mask)
+        kprev = k
+    m = w.m if w.phi_kind == "dense" else w.dims[-1]
+    out["full"] = scale_flops(m, w.atoms[-1], min(k_scales[-1], w.atoms[-1]), mask)
+    return out
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1511_05174_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, kernel_role: str, launches_per_step: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    ent = d.get("kernels", {}).get(kernel_role)
+    return None if ent is None else ent.get("hbm_bytes_per_launch")
+
+
+def psnr_db(x, xhat):
+    err = np.mean((x - xhat) ** 2)
+    peak = np.max(np.abs(x))
+    return float(10 * np.log10(peak * peak / err))
+
+
+def snr_db(x, xhat):
+    return float(20 * np.log10(np.linalg.norm(x) / np.linalg.norm(x - xhat)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=65536,
+                    help="patches of the workload the oracle is timed on")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(every patch is independent: the batch would be split across GPUs, see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1511_05174_amd import cspd
+
+    w = synth.make(args.workload)
+    B = w.batch
+    ks = list(w.k_scales)
+    plan = cspd.plan_from_workload(w)
+    tdt = torch.float64 if w.dtype == "f64" else torch.float32
+    ndt = np.float64 if w.dtype == "f64" else np.float32
+    dev = torch.device("cuda", 0)
+    y = torch.from_numpy(np.ascontiguousarray(w.y.astype(ndt))).to(dev)
+    mask = None if w.mask is None else torch.from_numpy(w.mask).to(dev)
+    kf = None if w.k_fine is None else torch.from_numpy(w.k_fine.astype(np.int32)).to(dev)
+    sup = torch.empty((B, plan.k_max), dtype=torch.int32, device=dev)
+    coef = torch.empty((B, plan.k_max), dtype=tdt, device=dev)
+    ku = torch.empty((B,), dtype=torch.int32, device=dev)
+    xh = torch.empty((B, w.n), dtype=tdt, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def cross_step():
+        cspd.cspd_omp_cross_scale(plan, y, mask, ks[:-1], kf, ks[-1], support=sup, coef=coef,
+                                  k_used=ku, xhat=xh, stream=stream)
+
+    def full_step():
+        cspd.cspd_omp_full(plan, y, mask, kf, ks[-1], support=sup, coef=coef, k_used=ku, xhat=xh,
+                           stream=stream)
+
+    def timed(step, steps, warmup):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        cspd.cspd_profile_reset()
+        cspd.cspd_profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cspd.cspd_profile_enable(False)
+        prof = cspd.cspd_profile_read()
+        return (t1 - t0) / steps, prof
+
+    print(f"[bench] workload {args.workload}: B={B} dims={w.dims} atoms={w.atoms} K={ks} "
+          f"phi={w.phi_kind} dtype={w.dtype}", file=sys.stderr, flush=True)
+    t_cross, prof = timed(cross_step, args.steps, args.warmup)
+    x_cross = xh.double().cpu().numpy()
+    print(f"[bench] cross-scale: {t_cross * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+
+    flops = kernel_flops(w, ks)
+    # dominant kernel = largest summed duration over the timed region
+    label, (launches, tot_ms) = max(prof.items(), key=lambda kv: kv[1][1])
+    role = label.split(":")[-1]
+    avg_ms = tot_ms / max(launches, 1)
+    per_patch = flops.get(role)
+    achieved = per_patch * B / (avg_ms * 1e-3) / 1e12 if per_patch else None
+    traffic = load_traffic(args.workload, role, 1)
+    peak = PEAK_FP32_VECTOR_TFLOPS if w.dtype == "f32" else PEAK_FP64_VECTOR_TFLOPS
+    roofline = {
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": None if achieved is None else achieved / peak,
+        "traffic": traffic,
+        "kernel": label,
+        "kernel_ms": avg_ms,
+        "flops_per_patch": per_patch,
+        "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in prof.items()},
+    }
+
+    full = None
+    x_full = None
+    if not args.no_full:
+        try:
+            t_full, prof_full = timed(full_step, max(1, args.steps // 4), 1)
+            x_full = xh.double().cpu().numpy()
+            full = {"value": B / t_full, "ms_per_step": t_full * 1e3,
+                    "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)}
+                                for k, v in prof_full.items()}}
+            print(f"[bench] full OMP: {t_full * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+        except cspd.CspdError as e:
+            print(f"[bench] full OMP unavailable: {e}", file=sys.stderr, flush=True)
+
+    quality = {"psnr_db_cross": psnr_db(w.x, x_cross), "snr_db_cross": snr_db(w.x, x_cross)}
+    if x_full is not None:
+        quality["psnr_db_full"] = psnr_db(w.x, x_full)
+        quality["snr_db_full"] = snr_db(w.x, x_full)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import synth as _s
+        import oracle
+        oracle.build()
+        n = min(args.cpu_sample, B)
+        sub = _s.subset(w, np.arange(n))
+        threads = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        oracle.omp_cross_scale(sub, n_threads=threads)
+        t1 = time.perf_counter()
+        cpu = {"value": n / (t1 - t0), "unit": "patches/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {n} patches of the workload, zero-tree OMP, FP64, {t1 - t0:.2f} s wall"}
+        print(f"[bench] oracle: {n} patches in {t1 - t0:.2f} s on {threads} threads",
+              file=sys.stderr, flush=True)
+
+    line = {
+        "metric": "patches/sec cross-scale vs full OMP at equal PSNR; p50/p99 job latency",
+        "value": B / t_cross,
+        "unit": "patches/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_cross * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if w.dtype == "f32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {B} patches, dims {w.dims}, atoms {w.atoms}, "
+                               f"K {ks}, phi {w.phi_kind}, {w.dtype}",
+                   "patches": B, "parallelism": "none (1 GPU)"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "full_omp": full,
+        "quality": quality,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

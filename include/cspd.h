@@ -1,0 +1,267 @@
+/*
+ * cspd -- batched cross-scale (zero-tree) orthogonal matching pursuit on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The problem every call solves, per patch (Section III-C of Saragadam, Li,
+ * Sankaranarayanan, "Cross-Scale Predictive Dictionaries"):
+ *
+ *     y = Phi x + e,   x = D_high s_high,   ||s_high||_0 <= K_high,
+ *
+ * with a chain of S dictionaries D_0 (coarsest) ... D_{S-1} = D_high in
+ * which fine atom j is a child of atom floor(j / Q_s) one scale up (the
+ * non-overlapping child blocks of Section III-B, 0-based).  Scale 0 is
+ * problem (P_low): OMP against the effective dictionary Phi U D_0, where U
+ * replicates a coarse sample over its block (nearest-neighbour upsampler,
+ * W U = I for the box-average down-sampler W).  Every finer scale is
+ * problem (P_high): OMP restarted from y over the children of the previous
+ * scale's support only (Algorithm 2, chained down the tree of Fig. 2).
+ * cspd_omp_full is Algorithm 1 over every atom of D_high.
+ *
+ * Conventions for every entry point:
+ *   - "host" pointers are read during the call only; "device" pointers are
+ *     device memory of the plan's device, owned by the caller, and must stay
+ *     valid until the stream passed to the call has completed the work.
+ *   - Compute calls are stream-ordered: they enqueue kernels on `hip_stream`
+ *     (a hipStream_t; NULL = the default stream) and return without waiting.
+ *   - Matrices are dense; "column-major R x C" means element (r, c) at
+ *     c * R + r; "row-major R x C" means element (r, c) at r * C + c.
+ *   - Floating-point device buffers have the plan's dtype (double for
+ *     CSPD_F64, float for CSPD_F32).
+ *   - Errors are returned as negative cspd_status codes; nothing aborts or
+ *     throws across this interface.  On error the outputs are undefined.  A
+ *     message for the last error on the calling thread is available from
+ *     cspd_last_error().
+ *   - Early termination of one patch (its candidates ran out, or the picked
+ *     atom is numerically dependent on the atoms already chosen) is not an
+ *     error: it shows as k_used < K and -1 padding in the support.
+ */
+#ifndef CSPD_H
+#define CSPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSPD_MAX_SCALES 4
+
+typedef int32_t cspd_status;
+enum {
+    CSPD_OK = 0,
+    CSPD_E_INVALID = -1,     /* null pointer, bad enum, negative size */
+    CSPD_E_SHAPE = -2,       /* inconsistent dimensions (e.g. T_s != Q T_{s-1}, K > k_max) */
+    CSPD_E_NOMEM = -3,       /* device or host allocation failed */
+    CSPD_E_DEVICE = -4,      /* a HIP runtime call or kernel launch failed */
+    CSPD_E_BUSY = -5,        /* serving: the job has not finished yet */
+    CSPD_E_NOTFOUND = -6,    /* serving: unknown job id */
+    CSPD_E_CAPACITY = -7,    /* serving: the job can never fit the HBM budget */
+    CSPD_E_UNSUPPORTED = -8  /* a shape this build has no kernel for */
+};
+
+/* Measurement operator Phi (Section III-C). */
+enum {
+    CSPD_PHI_IDENTITY = 0,   /* Phi = I (denoising); M = N */
+    CSPD_PHI_DENSE = 1,      /* one dense M x N matrix shared by all patches */
+    CSPD_PHI_MASK = 2        /* Phi = diag(mask_b) per patch (inpainting); M = N */
+};
+
+enum { CSPD_F64 = 0, CSPD_F32 = 1 };
+
+/* How the full-dictionary proxy is evaluated (not in the paper: a precision
+ * option).  NATIVE computes correlations in the plan's dtype; the two
+ * RESCORE modes compute them with bf16 / fp16 matrix cores and FP32
+ * accumulation, keep the rescore_m best candidates per patch and re-score
+ * those in FP32 before the argmax. */
+enum { CSPD_CORR_NATIVE = 0, CSPD_CORR_BF16_RESCORE = 1, CSPD_CORR_F16_RESCORE = 2 };
+
+/*
+ * Plan description (Section III-A's model, Section III-B's map, Section
+ * III-C's operators).
+ *   n_scales   S, 1 <= S <= CSPD_MAX_SCALES (S = 1 is plain OMP).
+ *   dim[s]     N_s, signal dimension at scale s (coarse -> fine); N = dim[S-1].
+ *   atoms[s]   T_s; must satisfy T_s = Q_s T_{s-1} with integer Q_s >= 1.
+ *   dict[s]    host, column-major dim[s] x atoms[s], FP64 (converted on the
+ *              device to the plan's dtype).
+ *   up_map[s]  host, s < S-1: length dim[s+1]; entry j is the scale-s
+ *              coordinate that fine coordinate j copies under U (and that W
+ *              averages it into).  Must be onto [0, dim[s]).
+ *   phi_kind   CSPD_PHI_*.
+ *   m          M, rows of Phi (must equal N unless CSPD_PHI_DENSE).
+ *   phi        host, row-major M x N, FP64 (CSPD_PHI_DENSE only, else NULL).
+ *   dtype      CSPD_F32 or CSPD_F64.
+ *   corr_mode  CSPD_CORR_* (RESCORE modes need CSPD_F32).
+ *   rescore_m  candidates re-scored per patch in RESCORE modes (1..16; 0 = 8).
+ *   k_max      largest sparsity any call will ask for at any scale; the
+ *              row stride of the support / coef outputs.
+ *   device     HIP device ordinal the plan lives on.
+ */
+typedef struct cspd_plan_desc {
+    int32_t n_scales;
+    int32_t dim[CSPD_MAX_SCALES];
+    int32_t atoms[CSPD_MAX_SCALES];
+    const double *dict[CSPD_MAX_SCALES];
+    const int32_t *up_map[CSPD_MAX_SCALES];
+    int32_t phi_kind;
+    int32_t m;
+    const double *phi;
+    int32_t dtype;
+    int32_t corr_mode;
+    int32_t rescore_m;
+    int32_t k_max;
+    int32_t device;
+} cspd_plan_desc;
+
+typedef struct cspd_plan_s *cspd_plan_t;
+
+/*
+ * Build a plan: validate the description, upload the dictionaries and Phi,
+ * and compute on the device the effective dictionaries A_s = Phi U D_s
+ * (Section III-C, (P_low) / (P_high)) with their column norms, plus the
+ * block tables of U.  Blocks until the plan is resident.  The plan owns all
+ * of its device memory; release it with cspd_plan_destroy.
+ * Errors: E_INVALID, E_SHAPE, E_NOMEM, E_DEVICE.
+ */
+cspd_status cspd_plan(const cspd_plan_desc *desc, cspd_plan_t *out);
+
+/* Release a plan (waits for the device; NULL is ignored). */
+void cspd_plan_destroy(cspd_plan_t plan);
+
+/* Bytes of device memory the plan holds (dictionaries, tables). */
+int64_t cspd_plan_device_bytes(cspd_plan_t plan);
+
+/*
+ * Algorithm 1 (orthogonal matching pursuit) over every atom of D_high, for B
+ * independent patches.
+ *   B          number of patches (0 is allowed: nothing is launched).
+ *   y          device, row-major B x M measurements.
+ *   mask       device, row-major B x N uint8 (nonzero = observed), required
+ *              for CSPD_PHI_MASK and ignored otherwise.
+ *   k          device int32[B] per-patch sparsity, or NULL to use k_uniform.
+ *              Each K must lie in [0, k_max]; K is capped at T and at M.
+ *   support    device, row-major B x k_max int32 out: indices into D_high in
+ *              selection order, -1 padded.
+ *   coef       device, row-major B x k_max out: coefficients of those
+ *              columns of D_high (least-squares solution on the support).
+ *   k_used     device int32[B] out: atoms actually selected.
+ *   xhat       device, row-major B x N out (may be NULL): D_high s_high.
+ * Errors: E_INVALID, E_SHAPE, E_UNSUPPORTED, E_DEVICE, E_NOMEM.
+ */
+cspd_status cspd_omp_full(cspd_plan_t plan, int64_t B, const void *y, const uint8_t *mask,
+                          const int32_t *k, int32_t k_uniform, int32_t *support, void *coef,
+                          int32_t *k_used, void *xhat, void *hip_stream);
+
+/*
+ * Zero-tree OMP (Algorithm 2, chained over the S scales of the plan).
+ *   k_scale        host int32[S-1]: sparsity of scales 0..S-2 (each capped
+ *                  at the number of candidates, Q_s times the previous k).
+ *   k_fine         device int32[B] per-patch sparsity of the finest scale,
+ *                  or NULL to use k_fine_uniform (capped at Q k_{S-2}).
+ *   support_coarse device, row-major B x (k_scale[0] + ... + k_scale[S-2])
+ *                  int32 out (may be NULL): each coarser scale's support in
+ *                  selection order, -1 padded, scales concatenated.
+ *   other arguments as for cspd_omp_full.  With S = 1 this is cspd_omp_full.
+ */
+cspd_status cspd_omp_cross_scale(cspd_plan_t plan, int64_t B, const void *y, const uint8_t *mask,
+                                 const int32_t *k_scale, const int32_t *k_fine,
+                                 int32_t k_fine_uniform, int32_t *support, void *coef,
+                                 int32_t *k_used, void *xhat, int32_t *support_coarse,
+                                 void *hip_stream);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of reconstruction jobs on one device.      */
+/* (Not in the paper: a request loop around the calls above.)             */
+/* ---------------------------------------------------------------------- */
+typedef struct cspd_server_s *cspd_server_t;
+
+/*
+ * One reconstruction job.  Inputs and outputs are HOST buffers, read and
+ * written by the server's copy engine; they must stay valid until
+ * cspd_serve_poll has returned CSPD_OK for the job.
+ *   plan      a resident plan (jobs of several plans may be in flight).
+ *   B         patches; y: B x M; mask: B x N or NULL; k_fine: int32[B] or
+ *             NULL (then k_fine_uniform); k_scale: int32[S-1] (copied at
+ *             submit).
+ *   full      nonzero: Algorithm 1 over D_high instead of zero-tree OMP.
+ *   outputs   support / k_used required, coef / xhat optional (NULL).
+ */
+typedef struct cspd_job {
+    cspd_plan_t plan;
+    int64_t B;
+    const void *y;
+    const uint8_t *mask;
+    const int32_t *k_fine;
+    int32_t k_fine_uniform;
+    int32_t k_scale[CSPD_MAX_SCALES];
+    int32_t full;
+    int32_t *support;
+    void *coef;
+    int32_t *k_used;
+    void *xhat;
+} cspd_job;
+
+/* Timestamps (CLOCK_MONOTONIC nanoseconds) of one finished job. */
+typedef struct cspd_job_stats {
+    int64_t submit_ns;   /* cspd_serve_submit called */
+    int64_t admit_ns;    /* device memory and a slot granted */
+    int64_t start_ns;    /* its first launch was enqueued */
+    int64_t finish_ns;   /* its results were back in host memory */
+    int64_t patches;
+    int32_t batched_with; /* other jobs that shared its launch */
+    int32_t status;      /* CSPD_OK or the error that failed the job */
+} cspd_job_stats;
+
+/*
+ * Create a server on `device` with an HBM budget for job buffers (bytes,
+ * > 0) and at most `max_slots` (1..64) launches in flight, each on its own
+ * stream.  A background thread admits queued jobs in arrival order when
+ * their buffers fit in the budget, packs waiting jobs of the same plan and
+ * kind into one launch, copies in, launches, copies out and retires them.
+ * Errors: E_INVALID, E_DEVICE, E_NOMEM.
+ */
+cspd_status cspd_serve_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slots,
+                              cspd_server_t *out);
+
+/* Queue a job (non-blocking).  E_CAPACITY if it can never fit the budget;
+ * E_INVALID / E_SHAPE for a malformed job. */
+cspd_status cspd_serve_submit(cspd_server_t server, const cspd_job *job, uint64_t *job_id);
+
+/* Wait up to timeout_us (0 = just look, < 0 = forever) for a job.  Returns
+ * CSPD_OK and fills *stats when it has finished (the job is then forgotten),
+ * E_BUSY if still pending, E_NOTFOUND for an unknown id, or the job's own
+ * error code if it failed. */
+cspd_status cspd_serve_poll(cspd_server_t server, uint64_t job_id, int64_t timeout_us,
+                            cspd_job_stats *stats);
+
+/* Drain the queue, stop the thread and free everything. */
+void cspd_serve_destroy(cspd_server_t server);
+
+/* ---------------------------------------------------------------------- */
+/* Kernel timing (measurement tools; not in the paper).                    */
+/* ---------------------------------------------------------------------- */
+/*
+ * cspd_profile_enable(1) makes every kernel launch of the compute calls
+ * record a pair of HIP events on the stream it is launched on, labelled with
+ * the kernel's name; 0 stops recording.  cspd_profile_read synchronizes the
+ * recorded events and reports entry `idx` (0-based, in order of first
+ * appearance): its label (copied into `name`, at most name_len bytes with the
+ * terminator), the number of launches and their summed duration in
+ * milliseconds.  It returns the number of entries, or a negative status.
+ * cspd_profile_reset drops every record.  Recording costs two events per
+ * launch; leave it off outside measurements.
+ */
+cspd_status cspd_profile_enable(int32_t on);
+int32_t cspd_profile_read(int32_t idx, char *name, int32_t name_len, int64_t *launches,
+                          double *total_ms);
+void cspd_profile_reset(void);
+
+/* Message for the last error raised on the calling thread ("" if none). */
+const char *cspd_last_error(void);
+
+/* Library version string. */
+const char *cspd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSPD_H */

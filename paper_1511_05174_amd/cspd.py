@@ -1,0 +1,312 @@
+"""Thin Python binding of the cspd C-ABI (include/cspd.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory and streams.  If the compiled
+library is missing, importing the functions raises -- there is no fallback.
+
+Names follow the C entry points:
+  cspd_plan, cspd_plan_destroy, cspd_plan_device_bytes,
+  cspd_omp_full, cspd_omp_cross_scale,
+  cspd_serve_create, cspd_serve_submit, cspd_serve_poll, cspd_serve_destroy,
+  cspd_last_error, cspd_version.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcspd.so")
+MAX_SCALES = 4
+
+OK, E_INVALID, E_SHAPE, E_NOMEM, E_DEVICE, E_BUSY, E_NOTFOUND, E_CAPACITY, E_UNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+PHI = {"identity": 0, "dense": 1, "mask": 2}
+DTYPES = {"f64": 0, "f32": 1}
+CORR = {"native": 0, "bf16": 1, "f16": 2}
+
+
+class CspdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"cspd error {code}: {msg}")
+        self.code = code
+
+
+class PlanDesc(C.Structure):
+    _fields_ = [
+        ("n_scales", C.c_int32),
+        ("dim", C.c_int32 * MAX_SCALES),
+        ("atoms", C.c_int32 * MAX_SCALES),
+        ("dict", C.c_void_p * MAX_SCALES),
+        ("up_map", C.c_void_p * MAX_SCALES),
+        ("phi_kind", C.c_int32),
+        ("m", C.c_int32),
+        ("phi", C.c_void_p),
+        ("dtype", C.c_int32),
+        ("corr_mode", C.c_int32),
+        ("rescore_m", C.c_int32),
+        ("k_max", C.c_int32),
+        ("device", C.c_int32),
+    ]
+
+
+class Job(C.Structure):
+    _fields_ = [
+        ("plan", C.c_void_p),
+        ("B", C.c_int64),
+        ("y", C.c_void_p),
+        ("mask", C.c_void_p),
+        ("k_fine", C.c_void_p),
+        ("k_fine_uniform", C.c_int32),
+        ("k_scale", C.c_int32 * MAX_SCALES),
+        ("full", C.c_int32),
+        ("support", C.c_void_p),
+        ("coef", C.c_void_p),
+        ("k_used", C.c_void_p),
+        ("xhat", C.c_void_p),
+    ]
+
+
+class JobStats(C.Structure):
+    _fields_ = [
+        ("submit_ns", C.c_int64),
+        ("admit_ns", C.c_int64),
+        ("start_ns", C.c_int64),
+        ("finish_ns", C.c_int64),
+        ("patches", C.c_int64),
+        ("batched_with", C.c_int32),
+        ("status", C.c_int32),
+    ]
+
+
+# Every symbol the header declares, with its ctypes signature.
+SIGNATURES = {
+    "cspd_plan": (C.c_int32, [C.POINTER(PlanDesc), C.POINTER(C.c_void_p)]),
+    "cspd_plan_destroy": (None, [C.c_void_p]),
+    "cspd_plan_device_bytes": (C.c_int64, [C.c_void_p]),
+    "cspd_omp_full": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cspd_omp_cross_scale": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cspd_serve_create": (C.c_int32, [C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_void_p)]),
+    "cspd_serve_submit": (C.c_int32, [C.c_void_p, C.POINTER(Job), C.POINTER(C.c_uint64)]),
+    "cspd_serve_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64, C.POINTER(JobStats)]),
+    "cspd_serve_destroy": (None, [C.c_void_p]),
+    "cspd_profile_enable": (C.c_int32, [C.c_int32]),
+    "cspd_profile_read": (C.c_int32, [C.c_int32, C.c_char_p, C.c_int32, C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_double)]),
+    "cspd_profile_reset": (None, []),
+    "cspd_last_error": (C.c_char_p, []),
+    "cspd_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libcspd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"cspd: {path} is missing; build it with paper_1511_05174_amd/build.py")
+    # PyTorch ships its own HIP runtime.  Importing torch first makes the
+    # library bind to that instance (same soname), so the process holds one
+    # runtime and torch's device pointers and streams are valid here.
+    import torch  # noqa: F401
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise CspdError(rc, load().cspd_last_error().decode())
+
+
+def cspd_last_error() -> str:
+    return load().cspd_last_error().decode()
+
+
+def cspd_version() -> str:
+    return load().cspd_version().decode()
+
+
+class Plan:
+    """Owns a cspd_plan_t; destroyed with the object."""
+
+    def __init__(self, handle: int, dims, atoms, m, phi_kind, dtype, k_max, device):
+        self.handle = handle
+        self.dims = list(dims)
+        self.atoms = list(atoms)
+        self.m = m
+        self.phi_kind = phi_kind
+        self.dtype = dtype
+        self.k_max = k_max
+        self.device = device
+
+    @property
+    def n_scales(self):
+        return len(self.dims)
+
+    @property
+    def n(self):
+        return self.dims[-1]
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.cspd_plan_destroy(h)
+
+
+def cspd_plan(dims: Sequence[int], atoms: Sequence[int], dicts, up_maps, phi_kind: str, m: int,
+              phi=None, dtype: str = "f32", corr_mode: str = "native", rescore_m: int = 0,
+              k_max: int = 16, device: int = 0) -> Plan:
+    """Build a resident plan.  dicts[s] is a (T_s, N_s) float64 array (the
+    column-major N_s x T_s dictionary); up_maps[s] an int32 array of length
+    N_{s+1}; phi a (M, N) float64 array for the dense operator."""
+    lib = load()
+    S = len(dims)
+    d = PlanDesc()
+    d.n_scales = S
+    keep = []
+    for s in range(S):
+        d.dim[s] = int(dims[s])
+        d.atoms[s] = int(atoms[s])
+        a = np.ascontiguousarray(dicts[s], dtype=np.float64)
+        keep.append(a)
+        d.dict[s] = a.ctypes.data
+        if s < S - 1:
+            u = np.ascontiguousarray(up_maps[s], dtype=np.int32)
+            keep.append(u)
+            d.up_map[s] = u.ctypes.data
+    d.phi_kind = PHI[phi_kind]
+    d.m = int(m)
+    if phi is not None:
+        p = np.ascontiguousarray(phi, dtype=np.float64)
+        keep.append(p)
+        d.phi = p.ctypes.data
+    d.dtype = DTYPES[dtype]
+    d.corr_mode = CORR[corr_mode]
+    d.rescore_m = int(rescore_m)
+    d.k_max = int(k_max)
+    d.device = int(device)
+    h = C.c_void_p()
+    _check(lib.cspd_plan(C.byref(d), C.byref(h)))
+    return Plan(h.value, dims, atoms, m, phi_kind, dtype, k_max, device)
+
+
+def plan_from_workload(w, dtype: Optional[str] = None, corr_mode: str = "native", k_max: int = 16,
+                       device: int = 0) -> Plan:
+    return cspd_plan(w.dims, w.atoms, w.dicts, w.up_maps, w.phi_kind, w.m, w.phi,
+                     dtype=dtype or w.dtype, corr_mode=corr_mode, k_max=k_max, device=device)
+
+
+def cspd_plan_destroy(plan: Plan):
+    h, plan.handle = plan.handle, None
+    if h:
+        load().cspd_plan_destroy(h)
+
+
+def cspd_plan_device_bytes(plan: Plan) -> int:
+    return int(load().cspd_plan_device_bytes(plan.handle))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _tdtype(plan: Plan):
+    torch = _torch()
+    return torch.float64 if plan.dtype == "f64" else torch.float32
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _outputs(plan, B, support, coef, k_used, xhat, want_xhat):
+    torch = _torch()
+    dev = torch.device("cuda", plan.device)
+    if support is None:
+        support = torch.empty((B, plan.k_max), dtype=torch.int32, device=dev)
+    if coef is None:
+        coef = torch.empty((B, plan.k_max), dtype=_tdtype(plan), device=dev)
+    if k_used is None:
+        k_used = torch.empty((B,), dtype=torch.int32, device=dev)
+    if xhat is None and want_xhat:
+        xhat = torch.empty((B, plan.n), dtype=_tdtype(plan), device=dev)
+    return support, coef, k_used, xhat
+
+
+def _check_inputs(plan, y, mask, k):
+    torch = _torch()
+    if y.dim() != 2 or y.shape[1] != plan.m or not y.is_contiguous() or y.dtype != _tdtype(plan):
+        raise ValueError(f"y must be a contiguous ({'{B}'}, {plan.m}) {_tdtype(plan)} tensor")
+    if mask is not None and (mask.dtype != torch.uint8 or tuple(mask.shape) != (y.shape[0], plan.n)
+                             or not mask.is_contiguous()):
+        raise ValueError("mask must be a contiguous (B, N) uint8 tensor")
+    if k is not None and (k.dtype != torch.int32 or tuple(k.shape) != (y.shape[0],) or not k.is_contiguous()):
+        raise ValueError("k must be a contiguous (B,) int32 tensor")
+
+
+def cspd_omp_full(plan: Plan, y, mask=None, k=None, k_uniform: int = 0, support=None, coef=None,
+                  k_used=None, xhat=None, want_xhat: bool = True, stream=None):
+    """Algorithm 1 over D_high; returns (support, coef, k_used, xhat)."""
+    _check_inputs(plan, y, mask, k)
+    B = y.shape[0]
+    support, coef, k_used, xhat = _outputs(plan, B, support, coef, k_used, xhat, want_xhat)
+    _check(load().cspd_omp_full(plan.handle, B, _ptr(y), _ptr(mask), _ptr(k), int(k_uniform),
+                                _ptr(support), _ptr(coef), _ptr(k_used), _ptr(xhat), _stream(stream)))
+    return support, coef, k_used, xhat
+
+
+def cspd_omp_cross_scale(plan: Plan, y, mask=None, k_scale: Sequence[int] = (), k_fine=None,
+                         k_fine_uniform: int = 0, support=None, coef=None, k_used=None, xhat=None,
+                         support_coarse=None, want_xhat: bool = True, stream=None):
+    """Zero-tree OMP over all scales; returns (support, coef, k_used, xhat)."""
+    _check_inputs(plan, y, mask, k_fine)
+    B = y.shape[0]
+    support, coef, k_used, xhat = _outputs(plan, B, support, coef, k_used, xhat, want_xhat)
+    ks = (C.c_int32 * MAX_SCALES)(*([int(v) for v in k_scale] + [0] * (MAX_SCALES - len(k_scale))))
+    _check(load().cspd_omp_cross_scale(plan.handle, B, _ptr(y), _ptr(mask), ks, _ptr(k_fine),
+                                       int(k_fine_uniform), _ptr(support), _ptr(coef), _ptr(k_used),
+                                       _ptr(xhat), _ptr(support_coarse), _stream(stream)))
+    return support, coef, k_used, xhat
+
+
+def cspd_profile_enable(on: bool = True):
+    _check(load().cspd_profile_enable(1 if on else 0))
+
+
+def cspd_profile_reset():
+    load().cspd_profile_reset()
+
+
+def cspd_profile_read():
+    """{label: (launches, total_ms)} for every kernel recorded since the last reset."""
+    lib = load()
+    out = {}
+    n = lib.cspd_profile_read(-1, None, 0, None, None)
+    for i in range(n):
+        buf = C.create_string_buffer(128)
+        cnt = C.c_int64()
+        ms = C.c_double()
+        lib.cspd_profile_read(i, buf, 128, C.byref(cnt), C.byref(ms))
+        out[buf.value.decode()] = (int(cnt.value), float(ms.value))
+    return out

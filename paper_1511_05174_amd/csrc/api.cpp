@@ -1,0 +1,333 @@
+// C-ABI entry points: argument validation, plan construction and dispatch of
+// the per-scale kernels.  Validation happens before any HIP call.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cspd_internal.h"
+
+namespace cspd {
+
+static thread_local std::string g_err;
+
+cspd_status set_error(cspd_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+void clear_error() { g_err.clear(); }
+
+bool scale_vec_fits(int lp, int max_cand);
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+cspd_status validate_desc(const cspd_plan_desc *d)
+{
+    if (!d) return set_error(CSPD_E_INVALID, "desc is NULL");
+    const int S = d->n_scales;
+    if (S < 1 || S > CSPD_MAX_SCALES) return set_error(CSPD_E_INVALID, "n_scales %d outside 1..%d", S, CSPD_MAX_SCALES);
+    for (int s = 0; s < S; ++s) {
+        if (d->dim[s] <= 0 || d->atoms[s] <= 0)
+            return set_error(CSPD_E_SHAPE, "scale %d: dim %d atoms %d must be positive", s, d->dim[s], d->atoms[s]);
+        if (!d->dict[s]) return set_error(CSPD_E_INVALID, "dict[%d] is NULL", s);
+        if (s > 0 && d->atoms[s] % d->atoms[s - 1] != 0)
+            return set_error(CSPD_E_SHAPE, "atoms[%d] = %d is not a multiple of atoms[%d] = %d", s,
+                             d->atoms[s], s - 1, d->atoms[s - 1]);
+    }
+    for (int s = 0; s + 1 < S; ++s) {
+        if (!d->up_map[s]) return set_error(CSPD_E_INVALID, "up_map[%d] is NULL", s);
+        std::vector<char> seen(d->dim[s], 0);
+        for (int j = 0; j < d->dim[s + 1]; ++j) {
+            const int v = d->up_map[s][j];
+            if (v < 0 || v >= d->dim[s])
+                return set_error(CSPD_E_SHAPE, "up_map[%d][%d] = %d outside [0, %d)", s, j, v, d->dim[s]);
+            seen[v] = 1;
+        }
+        for (int t = 0; t < d->dim[s]; ++t)
+            if (!seen[t]) return set_error(CSPD_E_SHAPE, "up_map[%d] does not reach coarse sample %d", s, t);
+    }
+    const int N = d->dim[S - 1];
+    if (d->phi_kind != CSPD_PHI_IDENTITY && d->phi_kind != CSPD_PHI_DENSE && d->phi_kind != CSPD_PHI_MASK)
+        return set_error(CSPD_E_INVALID, "phi_kind %d unknown", d->phi_kind);
+    if (d->phi_kind == CSPD_PHI_DENSE) {
+        if (!d->phi) return set_error(CSPD_E_INVALID, "dense phi is NULL");
+        if (d->m <= 0) return set_error(CSPD_E_SHAPE, "m = %d must be positive", d->m);
+    } else if (d->m != N) {
+        return set_error(CSPD_E_SHAPE, "m = %d must equal N = %d for this phi_kind", d->m, N);
+    }
+    if (d->dtype != CSPD_F32 && d->dtype != CSPD_F64) return set_error(CSPD_E_INVALID, "dtype %d unknown", d->dtype);
+    if (d->corr_mode < CSPD_CORR_NATIVE || d->corr_mode > CSPD_CORR_F16_RESCORE)
+        return set_error(CSPD_E_INVALID, "corr_mode %d unknown", d->corr_mode);
+    if (d->corr_mode != CSPD_CORR_NATIVE && d->dtype != CSPD_F32)
+        return set_error(CSPD_E_INVALID, "reduced-precision proxy needs an FP32 plan");
+    if (d->rescore_m < 0 || d->rescore_m > 16) return set_error(CSPD_E_INVALID, "rescore_m %d outside 0..16", d->rescore_m);
+    if (d->k_max < 1) return set_error(CSPD_E_SHAPE, "k_max %d must be >= 1", d->k_max);
+    if (d->k_max > kMaxK) return set_error(CSPD_E_UNSUPPORTED, "k_max %d above the supported %d", d->k_max, kMaxK);
+    for (int s = 0; s < S; ++s) {
+        const int l = d->phi_kind == CSPD_PHI_DENSE ? d->m : d->dim[s];
+        if (l > 256) return set_error(CSPD_E_UNSUPPORTED, "scale %d: vector length %d above 256", s, l);
+    }
+    if (d->device < 0) return set_error(CSPD_E_INVALID, "device %d", d->device);
+    return CSPD_OK;
+}
+
+void free_plan(cspd_plan_s *p)
+{
+    if (!p) return;
+    for (int s = 0; s < CSPD_MAX_SCALES; ++s) {
+        ScalePlan &sc = p->sc[s];
+        if (sc.v) (void)hipFree(sc.v);
+        if (sc.v_lo) (void)hipFree(sc.v_lo);
+        if (sc.nu2) (void)hipFree(sc.nu2);
+        if (sc.gram) (void)hipFree(sc.gram);
+        if (sc.blk_off) (void)hipFree(sc.blk_off);
+        if (sc.blk_idx) (void)hipFree(sc.blk_idx);
+    }
+    if (p->d_high) (void)hipFree(p->d_high);
+    delete p;
+}
+
+size_t elem_size(const cspd_plan_s *p) { return p->dtype == CSPD_F64 ? sizeof(double) : sizeof(float); }
+
+// Arguments common to every scale of one call.
+ScaleArgs base_args(const cspd_plan_s *p, int s, int64_t B, const void *y, const uint8_t *mask)
+{
+    const ScalePlan &sc = p->sc[s];
+    ScaleArgs a{};
+    a.b = B;
+    a.y = y;
+    a.y_stride = p->m;
+    a.mask = p->phi_kind == CSPD_PHI_MASK ? mask : nullptr;
+    a.n = p->n;
+    a.v = sc.v;
+    a.gram = sc.gram;
+    a.t = sc.t;
+    a.l = sc.l;
+    a.lp = sc.lp;
+    a.fold = sc.fold;
+    a.m_dense = p->m;
+    a.blk_off = sc.blk_off;
+    a.blk_idx = sc.blk_idx;
+    a.q = sc.q;
+    a.d_high = p->d_high;
+    return a;
+}
+
+// Largest candidate count of scale s when it is searched in full (first) or
+// restricted to the children of k_prev atoms.
+int max_candidates(const cspd_plan_s *p, int s, bool first, int k_prev)
+{
+    if (first) return p->sc[s].t;
+    const long v = (long)p->sc[s].q * k_prev;
+    return (int)(v < p->sc[s].t ? v : p->sc[s].t);
+}
+
+}  // namespace
+}  // namespace cspd
+
+using namespace cspd;
+
+extern "C" {
+
+const char *cspd_last_error(void) { return cspd::g_err.c_str(); }
+
+const char *cspd_version(void) { return "cspd 0.1 (gfx950)"; }
+
+cspd_status cspd_plan(const cspd_plan_desc *d, cspd_plan_t *out)
+{
+    clear_error();
+    if (!out) return set_error(CSPD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    cspd_status rc = validate_desc(d);
+    if (rc != CSPD_OK) return rc;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return set_error(CSPD_E_DEVICE, "no HIP device available");
+    if (d->device >= ndev) return set_error(CSPD_E_INVALID, "device %d of %d", d->device, ndev);
+    DeviceGuard g(d->device);
+    if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", d->device);
+    cspd_plan_s *p = new (std::nothrow) cspd_plan_s();
+    if (!p) return set_error(CSPD_E_NOMEM, "host allocation failed");
+    p->s = d->n_scales;
+    p->n = d->dim[d->n_scales - 1];
+    p->m = d->m;
+    p->phi_kind = d->phi_kind;
+    p->dtype = d->dtype;
+    p->corr_mode = d->corr_mode;
+    p->rescore_m = d->rescore_m ? d->rescore_m : 8;
+    p->k_max = d->k_max;
+    p->device = d->device;
+    hipStream_t st;
+    if (hipStreamCreate(&st) != hipSuccess) {
+        free_plan(p);
+        return set_error(CSPD_E_DEVICE, "hipStreamCreate failed");
+    }
+    rc = plan_effective(p, d, st);
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    if (rc != CSPD_OK) {
+        free_plan(p);
+        return rc;
+    }
+    *out = p;
+    return CSPD_OK;
+}
+
+void cspd_plan_destroy(cspd_plan_t p)
+{
+    if (!p) return;
+    DeviceGuard g(p->device);
+    (void)hipDeviceSynchronize();
+    free_plan(p);
+}
+
+int64_t cspd_plan_device_bytes(cspd_plan_t p) { return p ? p->bytes : 0; }
+
+cspd_status cspd_omp_full(cspd_plan_t p, int64_t B, const void *y, const uint8_t *mask,
+                          const int32_t *k, int32_t k_uniform, int32_t *support, void *coef,
+                          int32_t *k_used, void *xhat, void *hip_stream)
+{
+    clear_error();
+    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+    if (B < 0) return set_error(CSPD_E_INVALID, "B = %lld", (long long)B);
+    if (!k && (k_uniform < 0 || k_uniform > p->k_max))
+        return set_error(CSPD_E_SHAPE, "k_uniform %d outside [0, k_max = %d]", k_uniform, p->k_max);
+    if (B == 0) return CSPD_OK;
+    if (!y || !support || !coef || !k_used) return set_error(CSPD_E_INVALID, "y / support / coef / k_used is NULL");
+    if (p->phi_kind == CSPD_PHI_MASK && !mask) return set_error(CSPD_E_INVALID, "mask plan needs a mask");
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int s = p->s - 1;
+    const ScalePlan &sc = p->sc[s];
+    ScaleArgs a = base_args(p, s, B, y, mask);
+    a.first = 1;
+    a.scale = s;
+    a.kvec = k;
+    a.kuni = k_uniform;
+    a.last = 1;
+    a.sup_out = support;
+    a.sup_stride = p->k_max;
+    a.sup_count = p->k_max;
+    a.kused_out = k_used;
+    a.coef_out = coef;
+    a.xhat = xhat;
+    const int cand = sc.t;
+    cspd_status rc;
+    if (scale_vec_fits(sc.lp, cand) || sc.gram) rc = launch_scale(p->dtype, a, cand, !scale_vec_fits(sc.lp, cand), st);
+    else rc = launch_full_mfma(p, B, y, mask, k, k_uniform, support, coef, k_used, xhat, st);
+    if (rc == CSPD_E_UNSUPPORTED && cspd::g_err.empty())
+        return set_error(rc, "no full-search kernel for T = %d, length %d", sc.t, sc.l);
+    return rc;
+}
+
+cspd_status cspd_omp_cross_scale(cspd_plan_t p, int64_t B, const void *y, const uint8_t *mask,
+                                 const int32_t *k_scale, const int32_t *k_fine,
+                                 int32_t k_fine_uniform, int32_t *support, void *coef,
+                                 int32_t *k_used, void *xhat, int32_t *support_coarse,
+                                 void *hip_stream)
+{
+    clear_error();
+    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+    if (p->s == 1)
+        return cspd_omp_full(p, B, y, mask, k_fine, k_fine_uniform, support, coef, k_used, xhat, hip_stream);
+    if (B < 0) return set_error(CSPD_E_INVALID, "B = %lld", (long long)B);
+    if (!k_scale) return set_error(CSPD_E_INVALID, "k_scale is NULL");
+    int ksum = 0;
+    for (int s = 0; s + 1 < p->s; ++s) {
+        if (k_scale[s] < 0 || k_scale[s] > p->k_max)
+            return set_error(CSPD_E_SHAPE, "k_scale[%d] = %d outside [0, k_max = %d]", s, k_scale[s], p->k_max);
+        ksum += k_scale[s];
+    }
+    if (!k_fine && (k_fine_uniform < 0 || k_fine_uniform > p->k_max))
+        return set_error(CSPD_E_SHAPE, "k_fine_uniform %d outside [0, k_max = %d]", k_fine_uniform, p->k_max);
+    if (B == 0) return CSPD_OK;
+    if (!y || !support || !coef || !k_used) return set_error(CSPD_E_INVALID, "y / support / coef / k_used is NULL");
+    if (p->phi_kind == CSPD_PHI_MASK && !mask) return set_error(CSPD_E_INVALID, "mask plan needs a mask");
+    // candidate counts per scale must have kernels before anything is launched
+    std::vector<int> cand(p->s);
+    std::vector<char> gram(p->s, 0);
+    for (int s = 0; s < p->s; ++s) {
+        const int kprev = s == 0 ? 0 : k_scale[s - 1];
+        cand[s] = max_candidates(p, s, s == 0, kprev);
+        if (!scale_vec_fits(p->sc[s].lp, cand[s])) {
+            if (s == 0 && p->sc[s].gram) gram[s] = 1;
+            else return set_error(CSPD_E_UNSUPPORTED, "scale %d: no kernel for %d candidates of length %d",
+                                  s, cand[s], p->sc[s].l);
+        }
+    }
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    // coarse supports: the caller's buffer, or a stream-ordered temporary
+    int32_t *work = nullptr;
+    int32_t *coarse = support_coarse;
+    const int64_t nk = (int64_t)B * (p->s - 1);
+    size_t wbytes = sizeof(int32_t) * (size_t)(nk + (support_coarse ? 0 : (int64_t)B * ksum));
+    if (hipMallocAsync((void **)&work, wbytes, st) != hipSuccess)
+        return set_error(CSPD_E_NOMEM, "workspace of %zu bytes", wbytes);
+    int32_t *kused_c = work;
+    if (!coarse) coarse = work + nk;
+    cspd_status rc = CSPD_OK;
+    int off = 0;
+    for (int s = 0; s < p->s && rc == CSPD_OK; ++s) {
+        ScaleArgs a = base_args(p, s, B, y, mask);
+        a.first = s == 0;
+        a.scale = s;
+        if (s > 0) {
+            a.prev_sup = coarse + (off - k_scale[s - 1]);
+            a.prev_stride = ksum;
+            a.prev_kused = kused_c + (int64_t)B * (s - 1);
+        }
+        if (s + 1 < p->s) {
+            a.kvec = nullptr;
+            a.kuni = k_scale[s];
+            a.last = 0;
+            a.sup_out = coarse + off;
+            a.sup_stride = ksum;
+            a.sup_count = k_scale[s];
+            a.kused_out = kused_c + (int64_t)B * s;
+            off += k_scale[s];
+        } else {
+            a.kvec = k_fine;
+            a.kuni = k_fine_uniform;
+            a.last = 1;
+            a.sup_out = support;
+            a.sup_stride = p->k_max;
+            a.sup_count = p->k_max;
+            a.kused_out = k_used;
+            a.coef_out = coef;
+            a.xhat = xhat;
+        }
+        rc = launch_scale(p->dtype, a, cand[s], gram[s], st);
+    }
+    (void)hipFreeAsync(work, st);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// Internal declarations shared by the cspd HIP sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+
+#include "cspd.h"
+
+namespace cspd {
+
+// Largest sparsity per scale the per-patch kernels keep state for.
+constexpr int kMaxK = 16;
+// Per-patch Gram tables are precomputed for shared operators up to this size.
+constexpr int kMaxGramAtoms = 1024;
+// Patches (waves) per workgroup of the per-patch kernels.
+constexpr int kWavesPerBlock = 4;
+
+cspd_status set_error(cspd_status code, const char *fmt, ...);
+void clear_error();
+
+#define CSPD_HIP_CHECK(expr)                                                        \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return ::cspd::set_error(CSPD_E_DEVICE, "%s failed: %s (%s:%d)", #expr,  \
+                                     hipGetErrorString(e_), __FILE__, __LINE__);    \
+    } while (0)
+
+// How the kernel forms the candidate vectors of one scale.
+//  kFold  : identity or mask operator; candidates are D_s columns in the
+//           scale's own coordinates, weighted per patch by the square root of
+//           the number of observed fine samples in each block (the Gram of
+//           Phi U D_s restricted to the block structure), so that plain dot
+//           products of the weighted vectors equal those of Phi U D_s.
+//  kDense : shared dense operator; candidates are the columns of
+//           A_s = Phi U D_s, precomputed by the plan.
+enum FoldKind { kFold = 0, kDense = 1 };
+
+struct ScalePlan {
+    int n_s = 0;         // signal dimension at this scale
+    int t = 0;           // atoms
+    int q = 1;           // children per parent atom (1 at scale 0)
+    int l = 0;           // candidate vector length (N_s folded, M dense)
+    int lp = 0;          // padded row stride of `v` (multiple of 4)
+    int fold = kFold;
+    void *v = nullptr;        // t x lp, atom-contiguous, zero padded, plan dtype
+    void *v_lo = nullptr;     // t x lp, 16-bit copy for the reduced-precision proxy (or null)
+    void *nu2 = nullptr;      // t, squared effective norms (null for mask plans)
+    void *gram = nullptr;     // t x t effective Gram (null unless precomputed)
+    int *blk_off = nullptr;   // l + 1 (fold only): fine samples of each coarse sample
+    int *blk_idx = nullptr;   // N (fold only)
+};
+
+}  // namespace cspd
+
+struct cspd_plan_s {
+    int s = 0;           // scales
+    int n = 0;           // finest dimension
+    int m = 0;           // measurement dimension
+    int phi_kind = 0;
+    int dtype = 0;
+    int corr_mode = 0;
+    int rescore_m = 8;
+    int k_max = 0;
+    int device = 0;
+    int64_t bytes = 0;
+    cspd::ScalePlan sc[CSPD_MAX_SCALES];
+    void *d_high = nullptr;   // T_high x N atom-contiguous (plan dtype), for x-hat
+    std::mutex mu;
+};
+
+namespace cspd {
+
+// Arguments of one per-patch OMP pass over one scale (a launch).
+struct ScaleArgs {
+    int64_t b;                  // patches
+    const void *y;              // b x y_stride
+    int y_stride;
+    const uint8_t *mask;        // b x n or null
+    int n;                      // finest dimension
+    const void *v;              // candidate vectors (t x lp)
+    const void *gram;           // t x t (gram mode)
+    int t;                      // atoms at this scale
+    int l;                      // candidate vector length
+    int lp;                     // row stride of v
+    int fold;                   // FoldKind
+    int m_dense;                // measurement dim when dense (rank bound)
+    const int *blk_off;
+    const int *blk_idx;
+    int first;                  // 1: every atom is a candidate
+    const int *prev_sup;        // b x prev_stride (first == 0)
+    int prev_stride;
+    const int *prev_kused;      // b
+    int q;                      // children per parent
+    const int *kvec;            // b or null
+    int kuni;                   // uniform k
+    int last;                   // 1: write coefficients / x-hat
+    int scale;                  // scale index (labels only)
+    int *sup_out;               // row-major, row stride sup_stride
+    int sup_stride;
+    int sup_count;              // entries written per row (and the cap on k)
+    int *kused_out;             // b
+    void *coef_out;             // b x sup_stride (last)
+    void *xhat;                 // b x n (last, may be null)
+    const void *d_high;         // T_high x n (last)
+};
+
+// Selects and launches the per-scale kernel; returns CSPD_E_UNSUPPORTED when
+// no instantiation fits.
+cspd_status launch_scale(int dtype, const ScaleArgs &a, int max_candidates, bool gram_mode,
+                         hipStream_t stream);
+
+// Full-dictionary proxy on matrix cores (large T).
+cspd_status launch_full_mfma(const cspd_plan_s *p, int64_t b, const void *y, const uint8_t *mask,
+                             const int *kvec, int kuni, int *support, void *coef, int *k_used,
+                             void *xhat, hipStream_t stream);
+
+// Optional per-launch event timing (cspd_profile_enable).  Returns a token
+// to pass to profile_end after the launch; null when recording is off.
+struct ProfileToken;
+ProfileToken *profile_begin(const char *label, hipStream_t stream);
+void profile_end(ProfileToken *tok, hipStream_t stream);
+
+// Plan-time kernels.
+cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t stream);
+
+}  // namespace cspd
