@@ -1,0 +1,35 @@
+// Instantiations of the per-scale OMP kernel: double, up to 16 atoms per scale.
+#include "omp_scale_impl.h"
+
+namespace cspd {
+
+cspd_status dispatch_scale_f64_k16(const ScaleArgs &a, int lp, int nc, int ppw, bool gram,
+                                     hipStream_t st)
+{
+    using namespace scale_impl;
+    if (gram) {
+        switch (nc) {
+            case 1: return launch_one<double, 0, 1, 1, 16, true>(a, st);
+            case 2: return launch_one<double, 0, 2, 1, 16, true>(a, st);
+            case 4: return launch_one<double, 0, 4, 1, 16, true>(a, st);
+            case 8: return launch_one<double, 0, 8, 1, 16, true>(a, st);
+            case 16: return launch_one<double, 0, 16, 1, 16, true>(a, st);
+            default: return CSPD_E_UNSUPPORTED;
+        }
+    }
+    if (lp == 16 && nc == 1 && ppw == 2) return launch_one<double, 16, 1, 2, 16, false>(a, st);
+    if (lp == 16 && nc == 2 && ppw == 2) return launch_one<double, 16, 2, 2, 16, false>(a, st);
+    if (lp == 16 && nc == 4 && ppw == 2) return launch_one<double, 16, 4, 2, 16, false>(a, st);
+    if (lp == 16 && nc == 4 && ppw == 1) return launch_one<double, 16, 4, 1, 16, false>(a, st);
+    if (lp == 32 && nc == 1 && ppw == 2) return launch_one<double, 32, 1, 2, 16, false>(a, st);
+    if (lp == 32 && nc == 2 && ppw == 2) return launch_one<double, 32, 2, 2, 16, false>(a, st);
+    if (lp == 32 && nc == 2 && ppw == 1) return launch_one<double, 32, 2, 1, 16, false>(a, st);
+    if (lp == 32 && nc == 4 && ppw == 1) return launch_one<double, 32, 4, 1, 16, false>(a, st);
+    if (lp == 64 && nc == 1 && ppw == 2) return launch_one<double, 64, 1, 2, 16, false>(a, st);
+    if (lp == 64 && nc == 1 && ppw == 1) return launch_one<double, 64, 1, 1, 16, false>(a, st);
+    if (lp == 64 && nc == 2 && ppw == 1) return launch_one<double, 64, 2, 1, 16, false>(a, st);
+    if (lp == 128 && nc == 1 && ppw == 1) return launch_one<double, 128, 1, 1, 16, false>(a, st);
+    return CSPD_E_UNSUPPORTED;
+}
+
+}  // namespace cspd

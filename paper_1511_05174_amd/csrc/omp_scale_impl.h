@@ -1,0 +1,593 @@
+// Per-patch OMP over one scale of the cross-scale model (template body).
+//
+// A group of G = 64 / PPW lanes of one wavefront owns one patch (PPW patches
+// per wavefront).  Lanes own candidate atoms: slot s of group lane l holds
+// candidate s*G + l.  At scale 0 every atom of D_0 is a candidate (problem
+// (P_low) of Section III-C); at finer scales the candidates are the child
+// blocks f(Omega) of the previous scale's support (Section III-B, problem
+// (P_high), Algorithm 2), in ascending atom order.
+//
+// Each OMP iteration (Algorithm 1: proxy, support merge, projection, residue)
+// is carried in candidate coordinates with an incremental Cholesky factor L of
+// the support's Gram matrix:
+//   u_i = L^{-1} A_Omega^T a_i      row n of L is [u_k^T, sqrt(e_k)] when k joins
+//   c_i = <a_i, r> = h_i - u_i^T z   z = L^{-1} A_Omega^T y
+//   e_i = ||(I - P_Omega) a_i||^2 = ||a_i||^2 - ||u_i||^2
+// so a step costs one Gram column <a_i, a_k> per candidate plus rank-1 updates
+// of c, e and u; the residue is carried as its correlations with the
+// candidates.  Group lane j also carries column j of L^{-1}, so that the
+// coefficients alpha = L^{-T} z and a condition estimate of the Gram matrix
+// come out lane-parallel at the end.
+//
+// Candidate vectors live in VGPRs (vec mode) or, for small dictionaries under
+// a shared operator, the Gram column is read from the plan (gram mode).
+// Cross-lane steps use DPP and the gfx950 permlane swaps; the selected atom's
+// data reaches the group through one LDS broadcast per iteration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdio>
+
+#include "cspd_internal.h"
+
+namespace cspd {
+namespace scale_impl {
+
+constexpr int W = kWavesPerBlock;
+constexpr int KX = kMaxK;        // FP64 rare-path table size
+constexpr int LP_GRAM = 256;     // LDS row length for gram-mode kernels
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <typename T> __device__ __forceinline__ T dep_tol();
+template <> __device__ __forceinline__ double dep_tol<double>() { return 1e-10; }
+template <> __device__ __forceinline__ float dep_tol<float>() { return 1e-5f; }
+
+// ---- cross-lane primitives (groups of 16, 32 or 64 lanes) -----------------
+enum { DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_ROW_HALF_MIRROR = 0x141, DPP_ROW_MIRROR = 0x140 };
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) { return __int_as_float(dpp_i<CTRL>(__float_as_int(v))); }
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// The two values a lane sees across a 16-row pair (WIDTH 16) or a 32-lane
+// half pair (WIDTH 32): its own row's and the partner row's.
+template <int WIDTH>
+__device__ __forceinline__ void swap_pair_i(int v, int &a, int &b)
+{
+    if constexpr (WIDTH == 16) {
+        auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        a = r[0]; b = r[1];
+    } else {
+        auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        a = r[0]; b = r[1];
+    }
+}
+
+template <int WIDTH>
+__device__ __forceinline__ void swap_pair(float v, float &a, float &b)
+{
+    int x, y;
+    swap_pair_i<WIDTH>(__float_as_int(v), x, y);
+    a = __int_as_float(x); b = __int_as_float(y);
+}
+
+template <int WIDTH>
+__device__ __forceinline__ void swap_pair(double v, double &a, double &b)
+{
+    const long long bits = __double_as_longlong(v);
+    int l0, l1, h0, h1;
+    swap_pair_i<WIDTH>((int)bits, l0, l1);
+    swap_pair_i<WIDTH>((int)(bits >> 32), h0, h1);
+    a = __longlong_as_double(((long long)h0 << 32) | (unsigned)l0);
+    b = __longlong_as_double(((long long)h1 << 32) | (unsigned)l1);
+}
+
+template <typename T, int CTRL>
+__device__ __forceinline__ void argmax_step(T &s, int &i)
+{
+    const T os = dpp<CTRL>(s);
+    const int oi = dpp_i<CTRL>(i);
+    const bool take = os > s || (os == s && oi < i);
+    s = take ? os : s;
+    i = take ? oi : i;
+}
+
+template <typename T>
+__device__ __forceinline__ void argmax_merge(T s0, int i0, T s1, int i1, T &s, int &i)
+{
+    const bool take1 = s1 > s0 || (s1 == s0 && i1 < i0);
+    s = take1 ? s1 : s0;
+    i = take1 ? i1 : i0;
+}
+
+// Group-wide argmax with ties to the lowest index; every lane of the group
+// ends with the result.
+template <int G, typename T>
+__device__ __forceinline__ void group_argmax(T &s, int &i)
+{
+    argmax_step<T, DPP_QUAD_XOR1>(s, i);
+    argmax_step<T, DPP_QUAD_XOR2>(s, i);
+    argmax_step<T, DPP_ROW_HALF_MIRROR>(s, i);
+    argmax_step<T, DPP_ROW_MIRROR>(s, i);
+    if constexpr (G >= 32) {
+        T s0, s1;
+        int i0, i1;
+        swap_pair<16>(s, s0, s1);
+        swap_pair_i<16>(i, i0, i1);
+        argmax_merge(s0, i0, s1, i1, s, i);
+    }
+    if constexpr (G >= 64) {
+        T s0, s1;
+        int i0, i1;
+        swap_pair<32>(s, s0, s1);
+        swap_pair_i<32>(i, i0, i1);
+        argmax_merge(s0, i0, s1, i1, s, i);
+    }
+}
+
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v)
+{
+    v += dpp<DPP_QUAD_XOR1>(v);
+    v += dpp<DPP_QUAD_XOR2>(v);
+    v += dpp<DPP_ROW_HALF_MIRROR>(v);
+    v += dpp<DPP_ROW_MIRROR>(v);
+    if constexpr (G >= 32) {
+        T a, b;
+        swap_pair<16>(v, a, b);
+        v = a + b;
+    }
+    if constexpr (G >= 64) {
+        T a, b;
+        swap_pair<32>(v, a, b);
+        v = a + b;
+    }
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ int group_count(bool pred, int lane)
+{
+    const unsigned long long m = __ballot(pred);
+    if constexpr (G == 64) return __popcll(m);
+    const int g = lane / G;
+    return __popcll((m >> (g * G)) & ((1ull << G) - 1ull));
+}
+
+// ---- LDS layout: one record per patch group --------------------------------
+template <typename T, int LPA, int KM>
+struct GroupLds {
+    T yhat[LPA];
+    T sqw[LPA];
+    T vk[LPA];
+    T uk[KM];
+    T alpha[KX];
+    T sc[4];
+    int sup[KX];
+    int par[KX];
+};
+
+// FP64 Gram matrix and right-hand side of atoms ids[0..n-1] of one group,
+// accumulated in FP64 from the stored vectors (all 64 lanes split the dot
+// products), then on lane 0 an FP64 Cholesky in place (pivots kept in
+// piv[0..n)) and, when `solve`, the two triangular solves (solution in h64).
+template <typename T, int LPA, int KM>
+__device__ void gram64_chol(const GroupLds<T, LPA, KM> &w, const ScaleArgs &a, const int *ids, int n,
+                            int lane, double *g64, double *h64, double *piv, double *gdiag, bool solve)
+{
+    const T *v = (const T *)a.v;
+    const int np = n * (n + 1) / 2;
+    for (int pidx = lane; pidx < np + n; pidx += 64) {
+        double s = 0.0;
+        if (pidx < np) {
+            int i = 0, rem = pidx;
+            while (rem > i) { rem -= i + 1; ++i; }
+            const int j = rem;  // j <= i
+            const T *vi = v + (int64_t)ids[i] * a.lp;
+            const T *vj = v + (int64_t)ids[j] * a.lp;
+            for (int t = 0; t < a.l; ++t) {
+                const double wt = (double)w.sqw[t];
+                s += ((double)vi[t] * wt) * ((double)vj[t] * wt);
+            }
+            g64[i * KX + j] = s;
+            g64[j * KX + i] = s;
+        } else {
+            const int i = pidx - np;
+            const T *vi = v + (int64_t)ids[i] * a.lp;
+            for (int t = 0; t < a.l; ++t) s += (double)vi[t] * (double)w.sqw[t] * (double)w.yhat[t];
+            h64[i] = s;
+        }
+    }
+    wave_sync();
+    if (lane == 0) {
+        for (int j = 0; j < n; ++j) gdiag[j] = g64[j * KX + j];
+        for (int j = 0; j < n; ++j) {
+            double d = g64[j * KX + j];
+            for (int k = 0; k < j; ++k) d -= g64[j * KX + k] * g64[j * KX + k];
+            piv[j] = d;
+            const double r = d > 0.0 ? sqrt(d) : 0.0;
+            for (int i = j + 1; i < n; ++i) {
+                double t = g64[i * KX + j];
+                for (int k = 0; k < j; ++k) t -= g64[i * KX + k] * g64[j * KX + k];
+                g64[i * KX + j] = r > 0.0 ? t / r : 0.0;
+            }
+            g64[j * KX + j] = r;
+        }
+        if (solve) {
+            for (int i = 0; i < n; ++i) {
+                double t = h64[i];
+                for (int k = 0; k < i; ++k) t -= g64[i * KX + k] * h64[k];
+                h64[i] = g64[i * KX + i] > 0.0 ? t / g64[i * KX + i] : 0.0;
+            }
+            for (int i = n - 1; i >= 0; --i) {
+                double t = h64[i];
+                for (int k = i + 1; k < n; ++k) t -= g64[k * KX + i] * h64[k];
+                h64[i] = g64[i * KX + i] > 0.0 ? t / g64[i * KX + i] : 0.0;
+            }
+        }
+    }
+    wave_sync();
+}
+
+template <typename T, int LP, int NC, int PPW, int KM, bool GRAM>
+__global__ __launch_bounds__(64 * W) void k_omp_scale(ScaleArgs a)
+{
+    constexpr int G = 64 / PPW;
+    constexpr int LPA = GRAM ? LP_GRAM : LP;
+    constexpr int VL = GRAM ? 1 : LP;       // per-slot vector registers
+    __shared__ GroupLds<T, LPA, KM> lds[W * PPW];
+    __shared__ double lds64[W][KX * KX + 4 * KX];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int gi = lane / G;
+    const int gl = lane % G;
+    const int64_t wave_first = ((int64_t)blockIdx.x * W + wv) * PPW;
+    if (wave_first >= a.b) return;          // the whole wavefront leaves together
+    const int64_t b = wave_first + gi;
+    const bool valid = b < a.b;
+    GroupLds<T, LPA, KM> &w = lds[wv * PPW + gi];
+    const T *y = (const T *)a.y + (valid ? b : 0) * (int64_t)a.y_stride;
+    const int lp = GRAM ? a.lp : LP;
+
+    // ---- measurement in the scale's coordinates -------------------------
+    int rank_bound = 0;
+    for (int t0 = 0; t0 < lp; t0 += G) {
+        const int t = t0 + gl;
+        bool nz = false;
+        if (t < lp) {
+            T yh = 0, sq = 0;
+            if (valid && t < a.l) {
+                if (a.fold == kFold) {
+                    T cnt = 0, acc = 0;
+                    const int j0 = a.blk_off[t], j1 = a.blk_off[t + 1];
+                    for (int jj = j0; jj < j1; ++jj) {
+                        const int j = a.blk_idx[jj];
+                        const bool obs = a.mask ? a.mask[b * (int64_t)a.n + j] != 0 : true;
+                        if (obs) { cnt += T(1); acc += y[j]; }
+                    }
+                    sq = sqrt(cnt);
+                    yh = cnt > T(0) ? acc / sq : T(0);
+                    nz = cnt > T(0);
+                } else {
+                    yh = y[t];
+                    sq = T(1);
+                    nz = true;
+                }
+            }
+            w.yhat[t] = yh;
+            w.sqw[t] = sq;
+        }
+        rank_bound += group_count<G>(nz, lane);
+    }
+    if (a.fold != kFold) rank_bound = a.m_dense;
+
+    // ---- candidate set ---------------------------------------------------
+    int nc = 0;
+    if (valid) {
+        if (a.first) {
+            nc = a.t;
+        } else {
+            const int kp = a.prev_kused[b];
+            const int *ps = a.prev_sup + b * (int64_t)a.prev_stride;
+            if (gl < kp) {
+                const int pi = ps[gl];
+                int rank = 0;
+                for (int j = 0; j < kp; ++j) rank += ps[j] < pi;
+                w.par[rank] = pi;
+            }
+            nc = kp * a.q;
+        }
+    }
+    int K = 0;
+    if (valid) {
+        const int kreq = a.kvec ? a.kvec[b] : a.kuni;
+        K = kreq < nc ? kreq : nc;
+        K = K < KM ? K : KM;
+        K = K < a.sup_count ? K : a.sup_count;
+        K = K > 0 ? K : 0;
+    }
+    // iterations the wavefront runs: the largest K of its groups
+    int kwave = K;
+    if constexpr (PPW == 2) {
+        int o0, o1;
+        swap_pair_i<32>(K, o0, o1);
+        kwave = o0 > o1 ? o0 : o1;
+    }
+    kwave = __builtin_amdgcn_readfirstlane(kwave);
+    wave_sync();
+
+    // ---- per-candidate state --------------------------------------------
+    T v[NC][VL];
+    T c[NC], e[NC], e0[NC], nu[NC];
+    T u[NC][KM];
+    int atom[NC];
+    bool live[NC];
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        const int ci = s * G + gl;
+        live[s] = ci < nc;
+        atom[s] = INT_MAX;
+        if (live[s]) atom[s] = a.first ? ci : w.par[ci / a.q] * a.q + ci % a.q;
+#pragma unroll
+        for (int m = 0; m < KM; ++m) u[s][m] = T(0);
+        T h = 0, ee = 0;
+        if constexpr (!GRAM) {
+            const T *src = (const T *)a.v + (int64_t)(live[s] ? atom[s] : 0) * LP;
+            if constexpr (sizeof(T) == 4) {
+#pragma unroll
+                for (int j = 0; j < LP; j += 4) {
+                    const float4 q = *reinterpret_cast<const float4 *>(src + j);
+                    v[s][j] = q.x; v[s][j + 1] = q.y; v[s][j + 2] = q.z; v[s][j + 3] = q.w;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < LP; j += 2) {
+                    const double2 q = *reinterpret_cast<const double2 *>(src + j);
+                    v[s][j] = q.x; v[s][j + 1] = q.y;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < LP; ++j) {
+                const T x = live[s] ? v[s][j] * w.sqw[j] : T(0);
+                v[s][j] = x;
+                h += x * w.yhat[j];
+                ee += x * x;
+            }
+        } else {
+            if (live[s]) {
+                const T *src = (const T *)a.v + (int64_t)atom[s] * lp;
+                for (int j = 0; j < lp; ++j) {
+                    const T x = src[j] * w.sqw[j];
+                    h += x * w.yhat[j];
+                    ee += x * x;
+                }
+            }
+        }
+        c[s] = h;
+        e[s] = ee;
+        e0[s] = ee;
+        nu[s] = sqrt(ee);
+        if (!(ee > T(0))) live[s] = false;  // an effective column of zero is never picked
+    }
+
+    // ---- OMP iterations (Algorithm 1), unrolled so u / x / z stay in VGPRs
+    T x[KM];          // column gl of L^{-1}
+    T z[KM];          // L^{-1} A_Omega^T y (group-uniform)
+#pragma unroll
+    for (int m = 0; m < KM; ++m) { x[m] = T(0); z[m] = T(0); }
+    bool active = K > 0;
+    int nsel = 0;
+    T trg = 0;        // trace of the support's Gram matrix
+    T lmax = 0, lmin = 0;
+#pragma unroll
+    for (int n = 0; n < KM; ++n) {
+        if (n >= kwave) break;
+        bool act = active && n < K;
+        // proxy: |<a_i, r>| / ||a_i||, lowest atom index on ties
+        T best = T(-1);
+        int bidx = INT_MAX;
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            if (live[s]) {
+                const T sc = fabs(c[s]) / nu[s];
+                if (sc > best) { best = sc; bidx = atom[s]; }
+            }
+        }
+        if (!act) { best = T(-1); bidx = INT_MAX; }
+        group_argmax<G>(best, bidx);
+        act = act && best >= T(0);          // candidates exhausted otherwise
+        // the owning lane publishes its vector, its u row and its scalars
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            if (act && live[s] && atom[s] == bidx) {
+                if constexpr (!GRAM) {
+#pragma unroll
+                    for (int j = 0; j < LP; ++j) w.vk[j] = v[s][j];
+                }
+#pragma unroll
+                for (int m = 0; m < KM; ++m) w.uk[m] = u[s][m];
+                w.sc[0] = c[s];
+                w.sc[1] = e[s];
+                w.sc[2] = e0[s];
+            }
+        }
+        wave_sync();
+        T ck = 0, ek = 0, e0k = 0;
+        if (act) { ck = w.sc[0]; ek = w.sc[1]; e0k = w.sc[2]; }
+        act = act && n < rank_bound;        // support already spans the space
+        T lnn = T(1);
+        bool need64 = false;
+        if constexpr (sizeof(T) == 4) {
+            // the pivot's own condition estimate: ratio of squared diagonals of L
+            const T hi = n == 0 ? ek : (lmax * lmax > ek ? lmax * lmax : ek);
+            const T lo = n == 0 ? ek : (lmin * lmin < ek ? lmin * lmin : ek);
+            need64 = act && (!(lo > T(0)) || hi > T(1e6) * lo);
+        }
+        if (act && !need64) {
+            if (!(ek > dep_tol<T>() * e0k)) act = false;  // picked atom is dependent
+            else lnn = sqrt(ek);
+        }
+        if constexpr (sizeof(T) == 4) {
+            // FP64 pivot: Cholesky of the FP64 Gram of Omega + {k}, one group at a time
+            const unsigned long long m64 = __ballot(need64);
+            if (m64) {
+#pragma unroll
+                for (int g = 0; g < PPW; ++g) {
+                    if ((m64 >> (g * G)) & 1ull) {
+                        GroupLds<T, LPA, KM> &wg = lds[wv * PPW + g];
+                        if (lane == g * G) wg.sup[n] = bidx;
+                        wave_sync();
+                        double *g64 = lds64[wv];
+                        double *h64 = g64 + KX * KX;
+                        double *pv = h64 + KX;
+                        double *gd = pv + KX;
+                        gram64_chol<T, LPA, KM>(wg, a, wg.sup, n + 1, lane, g64, h64, pv, gd, false);
+                        if (gi == g) {
+                            const double piv = pv[n], gkk = gd[n];
+                            if (!(piv > 1e-10 * gkk)) act = false;  // dependent in FP64 as well
+                            else lnn = (T)sqrt(piv);
+                        }
+                        wave_sync();
+                    }
+                }
+            }
+        }
+        if (!act) active = false;
+        if (act) {
+            const T inv = T(1) / lnn;
+            const T zn = ck * inv;
+#pragma unroll
+            for (int s = 0; s < NC; ++s) {
+                T g = 0;
+                if constexpr (!GRAM) {
+#pragma unroll
+                    for (int j = 0; j < LP; ++j) g += v[s][j] * w.vk[j];
+                } else {
+                    if (atom[s] != INT_MAX) g = ((const T *)a.gram)[(int64_t)bidx * a.t + atom[s]];
+                }
+                T dot = 0;
+#pragma unroll
+                for (int m = 0; m < n; ++m) dot += w.uk[m] * u[s][m];
+                const T un = (g - dot) * inv;
+                u[s][n] = un;
+                c[s] -= un * zn;
+                e[s] -= un * un;
+                if (atom[s] == bidx) live[s] = false;
+            }
+            // column gl of L^{-1}: new entry of the appended row
+            T xd = gl == n ? T(1) : T(0);
+#pragma unroll
+            for (int m = 0; m < n; ++m) xd -= w.uk[m] * x[m];
+            x[n] = xd * inv;
+            z[n] = zn;
+            if (gl == 0) w.sup[n] = bidx;
+            trg += e0k;
+            lmax = n == 0 ? lnn : (lnn > lmax ? lnn : lmax);
+            lmin = n == 0 ? lnn : (lnn < lmin ? lnn : lmin);
+            nsel = n + 1;
+        }
+    }
+    wave_sync();
+
+    // ---- outputs ---------------------------------------------------------
+    if (valid && gl == 0) a.kused_out[b] = nsel;
+    int *sup_out = a.sup_out + (valid ? b : 0) * (int64_t)a.sup_stride;
+    if (!a.last) {
+        if (valid)
+            for (int i = gl; i < a.sup_count; i += G) sup_out[i] = i < nsel ? w.sup[i] : -1;
+        return;
+    }
+    // coefficients: alpha_j = sum_i (L^{-1})_{ij} z_i, lane j of the group
+    T al = 0, col2 = 0;
+#pragma unroll
+    for (int i = 0; i < KM; ++i) {
+        al += x[i] * z[i];
+        col2 += x[i] * x[i];
+    }
+    if (gl < nsel) w.alpha[gl] = al;
+    if constexpr (sizeof(T) == 4) {
+        // FP64 back-substitution when the FP32 normal equations would miss the
+        // coefficient tolerance: their error grows like kappa(G) * 2^-24, and
+        // tr(G) tr(G^{-1}) / n estimates kappa(G) within a factor n.
+        const T trinv = group_sum<G>(col2);
+        const bool ill = nsel > 1 && (double)trg * (double)trinv / nsel > 1e2;
+        const unsigned long long mi = __ballot(ill);
+        wave_sync();
+        if (mi) {
+#pragma unroll
+            for (int g = 0; g < PPW; ++g) {
+                if ((mi >> (g * G)) & 1ull) {
+                    GroupLds<T, LPA, KM> &wg = lds[wv * PPW + g];
+                    const int ng = __builtin_amdgcn_readlane(nsel, g * G);
+                    double *g64 = lds64[wv];
+                    double *h64 = g64 + KX * KX;
+                    double *pv = h64 + KX;
+                    double *gd = pv + KX;
+                    gram64_chol<T, LPA, KM>(wg, a, wg.sup, ng, lane, g64, h64, pv, gd, true);
+                    if (lane == g * G)
+                        for (int i = 0; i < ng; ++i) wg.alpha[i] = (T)h64[i];
+                    wave_sync();
+                }
+            }
+        }
+    }
+    wave_sync();
+    if (!valid) return;
+    T *coef = (T *)a.coef_out + b * (int64_t)a.sup_stride;
+    for (int i = gl; i < a.sup_count; i += G) {
+        sup_out[i] = i < nsel ? w.sup[i] : -1;
+        coef[i] = i < nsel ? w.alpha[i] : T(0);
+    }
+    if (a.xhat) {
+        const T *dh = (const T *)a.d_high;
+        T *xh = (T *)a.xhat + b * (int64_t)a.n;
+        for (int j = gl; j < a.n; j += G) {
+            T acc = 0;
+            for (int i = 0; i < nsel; ++i) acc += w.alpha[i] * dh[(int64_t)w.sup[i] * a.n + j];
+            xh[j] = acc;
+        }
+    }
+}
+
+template <typename T, int LP, int NC, int PPW, int KM, bool GRAM>
+cspd_status launch_one(const ScaleArgs &a, hipStream_t st)
+{
+    const int64_t waves = (a.b + PPW - 1) / PPW;
+    const unsigned grid = (unsigned)((waves + W - 1) / W);
+    char label[112];
+    if (a.first && a.last)
+        snprintf(label, sizeof(label), "omp_scale<%s,%s,lp%d,nc%d,ppw%d,k%d>:full", sizeof(T) == 8 ? "f64" : "f32",
+                 GRAM ? "gram" : "vec", GRAM ? a.lp : LP, NC, PPW, KM);
+    else
+        snprintf(label, sizeof(label), "omp_scale<%s,%s,lp%d,nc%d,ppw%d,k%d>:s%d", sizeof(T) == 8 ? "f64" : "f32",
+                 GRAM ? "gram" : "vec", GRAM ? a.lp : LP, NC, PPW, KM, a.scale);
+    ProfileToken *tok = profile_begin(label, st);
+    hipLaunchKernelGGL((k_omp_scale<T, LP, NC, PPW, KM, GRAM>), dim3(grid), dim3(64 * W), 0, st, a);
+    profile_end(tok, st);
+    CSPD_HIP_CHECK(hipGetLastError());
+    return CSPD_OK;
+}
+
+}  // namespace scale_impl
+}  // namespace cspd
