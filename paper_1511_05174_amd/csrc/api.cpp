@@ -104,6 +104,7 @@ void free_plan(cspd_plan_s *p)
         if (sc.v) (void)hipFree(sc.v);
         if (sc.v_lo) (void)hipFree(sc.v_lo);
         if (sc.nu2) (void)hipFree(sc.nu2);
+        if (sc.inv_nu) (void)hipFree(sc.inv_nu);
         if (sc.gram) (void)hipFree(sc.gram);
         if (sc.blk_off) (void)hipFree(sc.blk_off);
         if (sc.blk_idx) (void)hipFree(sc.blk_idx);

@@ -49,6 +49,7 @@ struct ScalePlan {
     void *v = nullptr;        // t x lp, atom-contiguous, zero padded, plan dtype
     void *v_lo = nullptr;     // t x lp, 16-bit copy for the reduced-precision proxy (or null)
     void *nu2 = nullptr;      // t, squared effective norms (null for mask plans)
+    void *inv_nu = nullptr;   // t, FP32 reciprocal effective norms (null for mask plans)
     void *gram = nullptr;     // t x t effective Gram (null unless precomputed)
     int *blk_off = nullptr;   // l + 1 (fold only): fine samples of each coarse sample
     int *blk_idx = nullptr;   // N (fold only)

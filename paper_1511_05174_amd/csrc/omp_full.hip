@@ -1,17 +1,401 @@
-// Full-dictionary OMP for dictionaries too large for the per-patch kernels.
+// Full-dictionary OMP (Algorithm 1 over every atom of D_high) for
+// dictionaries too large for the per-patch register kernels.
+//
+// A workgroup of four wavefronts owns 32 patches.  Each iteration:
+//  1. proxy: C = A^T R for all T atoms and the 32 residuals on FP32 matrix
+//     cores (v_mfma_f32_32x32x2f32, one 32-atom tile per step, the tiles
+//     dealt round-robin to the four wavefronts); under a per-patch mask the
+//     masked column norms are formed the same way, (A o A)^T M, since
+//     T x 32 of them do not fit in LDS.  Scores |c| / ||a|| are fused on the
+//     accumulators and reduced to a per-patch argmax (lowest index on ties,
+//     atoms already in the support excluded through an LDS bit mask);
+//  2. support merge, projection and residue: eight threads per patch form
+//     the Gram column of the new atom against the support and <a_k, y>,
+//     append a row to the Cholesky factor, solve for the coefficients and
+//     recompute the residual r = y - A_Omega alpha in the patch's LDS row.
+// The MFMA operands use a coordinate permutation shared by both sides: lane
+// half h of an operand supplies coordinate h*LP/2 + s at step s, so every lane
+// reads a contiguous half row of A and of the residual.
 #include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdio>
 
 #include "cspd_internal.h"
 
 namespace cspd {
+namespace full_impl {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int P = 32;          // patches per workgroup
+constexpr int NW = 4;          // wavefronts per workgroup
+constexpr int TPP = 8;         // threads per patch in the update phase
+constexpr int KX = kMaxK;
+constexpr int SELW = 128;      // selection bit-mask words per patch (T <= 4096)
+
+struct FullArgs {
+    int64_t b;
+    const float *y;            // b x y_stride
+    int y_stride;
+    const uint8_t *mask;       // b x n or null
+    int n;
+    const float *v;            // t x lp
+    const float *inv_nu;       // t (null under a mask)
+    int t;
+    int l;
+    int lp;
+    int rank;                  // rank bound of the measurement space (dense: M)
+    const int *kvec;
+    int kuni;
+    int kcap;                  // = k_max: row stride and cap of k
+    int *support;
+    float *coef;
+    int *k_used;
+    float *xhat;
+    const float *d_high;       // T x n
+};
+
+__device__ __forceinline__ void sync() { __syncthreads(); }
+
+// sum over the 8 consecutive lanes of a patch (DPP within a half row)
+__device__ __forceinline__ float sum8(float v)
+{
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
+    return v;
+}
+
+__device__ __forceinline__ bool beats(float s1, int i1, float s0, int i0)
+{
+    return (s1 > s0) | ((s1 == s0) & (i1 < i0));
+}
+
+template <int LP, int KM, bool MASK>
+__global__ __launch_bounds__(64 * NW) void k_omp_full(FullArgs a)
+{
+    constexpr int HL = LP / 2;            // coordinates per operand half
+    constexpr int RS = LP + 4;            // LDS row stride
+    constexpr int CP = LP / TPP;          // coordinates per update thread
+    constexpr int NL = KM * (KM + 1) / 2;
+    __shared__ float s_r[P][RS];
+    __shared__ float s_y[P][RS];
+    __shared__ float s_m[MASK ? P : 1][MASK ? RS : 1];
+    __shared__ unsigned s_sel[P][SELW];
+    __shared__ float s_bs[NW][P];
+    __shared__ int s_bi[NW][P];
+    __shared__ int s_k[P];
+    __shared__ float s_l[P][NL];
+    __shared__ float s_z[P][KM];
+    __shared__ float s_al[P][KM];
+    __shared__ int s_sup[P][KM];
+    __shared__ int s_n[P], s_kk[P], s_live[P];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int64_t b0 = (int64_t)blockIdx.x * P;
+    const int ntiles = (a.t + 31) / 32;
+
+    // ---- patch set-up ------------------------------------------------------
+    for (int i = tid; i < P * SELW; i += 64 * NW) s_sel[i / SELW][i % SELW] = 0u;
+    for (int i = tid; i < P * LP; i += 64 * NW) {
+        const int p = i / LP, j = i % LP;
+        const int64_t b = b0 + p;
+        float yv = 0.f, mv = 1.f;
+        if (b < a.b && j < a.l) {
+            yv = a.y[b * (int64_t)a.y_stride + j];
+            if constexpr (MASK) { mv = a.mask[b * (int64_t)a.n + j] ? 1.f : 0.f; yv *= mv; }
+        } else {
+            mv = 0.f;
+        }
+        s_y[p][j] = yv;
+        s_r[p][j] = yv;
+        if constexpr (MASK) s_m[p][j] = mv;
+    }
+    if (tid < P) {
+        const int64_t b = b0 + tid;
+        int k = 0;
+        if (b < a.b) {
+            k = a.kvec ? a.kvec[b] : a.kuni;
+            k = k < a.kcap ? k : a.kcap;
+            k = k < KM ? k : KM;
+            k = k < a.t ? k : a.t;
+            k = k > 0 ? k : 0;
+        }
+        s_kk[tid] = k;
+        s_n[tid] = 0;
+        s_live[tid] = k > 0;
+    }
+    sync();
+    int kmax = 0;
+    for (int p = 0; p < P; ++p) kmax = s_kk[p] > kmax ? s_kk[p] : kmax;
+    int rank = a.rank;
+    (void)rank;
+
+    const int up = tid / TPP;         // patch of this thread in the update phase
+    const int us = tid % TPP;         // its slice of the coordinates
+    float mk[CP];
+#pragma unroll
+    for (int q = 0; q < CP; ++q) mk[q] = MASK ? s_m[up][us * CP + q] : 1.f;
+    int rank_p = MASK ? 0 : a.rank;
+    if constexpr (MASK) {
+        float cnt = 0.f;
+#pragma unroll
+        for (int q = 0; q < CP; ++q) cnt += mk[q];
+        rank_p = (int)sum8(cnt);
+    }
+
+    for (int it = 0; it < kmax; ++it) {
+        // ---- 1. proxy on matrix cores ----------------------------------------
+        const int pp = lane & 31;         // patch column of this lane
+        const int h = lane >> 5;          // operand half
+        float rb[HL];
+        float mb[MASK ? HL : 1];
+#pragma unroll
+        for (int s = 0; s < HL; ++s) {
+            rb[s] = s_r[pp][h * HL + s];
+            if constexpr (MASK) mb[s] = s_m[pp][h * HL + s];
+        }
+        float bs = -1.f;
+        int bi = INT_MAX;
+        const bool plive = s_live[pp] != 0;
+        for (int t = wave; t < ntiles; t += NW) {
+            const int arow = t * 32 + (lane & 31);
+            const float *src = a.v + (int64_t)(arow < a.t ? arow : 0) * a.lp + h * HL;
+            float ab[HL];
+#pragma unroll
+            for (int s = 0; s < HL; s += 4) {
+                const float4 q = *reinterpret_cast<const float4 *>(src + s);
+                ab[s] = q.x; ab[s + 1] = q.y; ab[s + 2] = q.z; ab[s + 3] = q.w;
+            }
+            f32x16 acc = {};
+            f32x16 nac = {};
+#pragma unroll
+            for (int s = 0; s < HL; ++s) {
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ab[s], rb[s], acc, 0, 0, 0);
+                if constexpr (MASK) nac = __builtin_amdgcn_mfma_f32_32x32x2f32(ab[s] * ab[s], mb[s], nac, 0, 0, 0);
+            }
+            const unsigned selw = s_sel[pp][t];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+                const int atom = t * 32 + row;
+                float inv;
+                if constexpr (MASK) inv = nac[r] > 0.f ? 1.f / sqrtf(nac[r]) : -1.f;
+                else inv = atom < a.t ? a.inv_nu[atom] : -1.f;
+                float sc = fabsf(acc[r]) * inv;
+                const bool ok = plive & (atom < a.t) & (inv > 0.f) & (((selw >> row) & 1u) == 0u);
+                sc = ok ? sc : -1.f;
+                if (sc > bs) { bs = sc; bi = atom; }
+            }
+        }
+        // lanes l and l + 32 hold the same patch
+        {
+            auto rs = __builtin_amdgcn_permlane32_swap(__float_as_int(bs), __float_as_int(bs), false, false);
+            auto ri = __builtin_amdgcn_permlane32_swap(bi, bi, false, false);
+            const float s0 = __int_as_float(rs[0]), s1 = __int_as_float(rs[1]);
+            const bool t1 = beats(s1, ri[1], s0, ri[0]);
+            bs = t1 ? s1 : s0;
+            bi = t1 ? ri[1] : ri[0];
+        }
+        if (lane < 32) { s_bs[wave][lane] = bs; s_bi[wave][lane] = bi; }
+        sync();
+        if (tid < P) {
+            float b = s_bs[0][tid];
+            int i = s_bi[0][tid];
+            for (int w = 1; w < NW; ++w)
+                if (beats(s_bs[w][tid], s_bi[w][tid], b, i)) { b = s_bs[w][tid]; i = s_bi[w][tid]; }
+            const bool go = s_live[tid] && b >= 0.f && s_n[tid] < s_kk[tid];
+            s_k[tid] = go ? i : -1;
+        }
+        sync();
+
+        // ---- 2. support merge, projection and residue ------------------------
+        const int k = s_k[up];
+        const int n = s_n[up];
+        if (k >= 0) {
+            float ak[CP];
+            const float *ka = a.v + (int64_t)k * a.lp + us * CP;
+#pragma unroll
+            for (int q = 0; q < CP; ++q) ak[q] = ka[q] * mk[q];
+            float g[KM];
+#pragma unroll
+            for (int m = 0; m < KM; ++m) {
+                float part = 0.f;
+                if (m < n) {
+                    const float *am = a.v + (int64_t)s_sup[up][m] * a.lp + us * CP;
+#pragma unroll
+                    for (int q = 0; q < CP; ++q) part += am[q] * ak[q];
+                }
+                g[m] = part;
+            }
+            float pk = 0.f, ph = 0.f;
+#pragma unroll
+            for (int q = 0; q < CP; ++q) { pk += ak[q] * ak[q]; ph += ak[q] * s_y[up][us * CP + q]; }
+#pragma unroll
+            for (int m = 0; m < KM; ++m) g[m] = sum8(g[m]);
+            const float gkk = sum8(pk);
+            const float hk = sum8(ph);
+            // w = L^{-1} g, pivot = gkk - |w|^2
+            float wv[KM];
+            float ww = 0.f;
+#pragma unroll
+            for (int i = 0; i < KM; ++i) {
+                wv[i] = 0.f;
+                if (i < n) {
+                    float s = g[i];
+#pragma unroll
+                    for (int j = 0; j < i; ++j) s -= s_l[up][i * (i + 1) / 2 + j] * wv[j];
+                    wv[i] = s / s_l[up][i * (i + 1) / 2 + i];
+                    ww += wv[i] * wv[i];
+                }
+            }
+            const float piv = gkk - ww;
+            const bool dep = !(piv > 1e-5f * gkk) || n >= rank_p;
+            if (dep) {
+                if (us == 0) s_live[up] = 0;
+            } else {
+                const float lnn = sqrtf(piv);
+                float zw = 0.f;
+#pragma unroll
+                for (int j = 0; j < KM; ++j) zw += j < n ? wv[j] * s_z[up][j] : 0.f;
+                const float zn = (hk - zw) / lnn;
+                // coefficients: L^T alpha = z with the new row appended
+                float al[KM];
+#pragma unroll
+                for (int i = KM - 1; i >= 0; --i) {
+                    al[i] = 0.f;
+                    if (i <= n) {
+                        float s = i == n ? zn : s_z[up][i];
+#pragma unroll
+                        for (int m = i + 1; m < KM; ++m) {
+                            if (m <= n) {
+                                const float lmi = m == n ? wv[i] : s_l[up][m * (m + 1) / 2 + i];
+                                s -= lmi * al[m];
+                            }
+                        }
+                        al[i] = s / (i == n ? lnn : s_l[up][i * (i + 1) / 2 + i]);
+                    }
+                }
+                // residue on this thread's coordinates
+                float rr[CP];
+#pragma unroll
+                for (int q = 0; q < CP; ++q) rr[q] = s_y[up][us * CP + q];
+#pragma unroll
+                for (int m = 0; m < KM; ++m) {
+                    if (m <= n) {
+                        const int atom = m == n ? k : s_sup[up][m];
+                        const float *am = a.v + (int64_t)atom * a.lp + us * CP;
+#pragma unroll
+                        for (int q = 0; q < CP; ++q) rr[q] -= al[m] * am[q] * mk[q];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < CP; ++q) s_r[up][us * CP + q] = rr[q];
+                if (us == 0) {
+                    for (int j = 0; j < n; ++j) s_l[up][n * (n + 1) / 2 + j] = wv[j];
+                    s_l[up][n * (n + 1) / 2 + n] = lnn;
+                    s_z[up][n] = zn;
+#pragma unroll
+                    for (int m = 0; m < KM; ++m)
+                        if (m <= n) s_al[up][m] = al[m];
+                    s_sup[up][n] = k;
+                    s_sel[up][k >> 5] |= 1u << (k & 31);
+                    s_n[up] = n + 1;
+                }
+            }
+        }
+        sync();
+    }
+
+    // ---- outputs ---------------------------------------------------------------
+    const int64_t b = b0 + up;
+    if (b >= a.b) return;
+    const int nsel = s_n[up];
+    if (us == 0) a.k_used[b] = nsel;
+    for (int i = us; i < a.kcap; i += TPP) {
+        a.support[b * (int64_t)a.kcap + i] = i < nsel ? s_sup[up][i] : -1;
+        a.coef[b * (int64_t)a.kcap + i] = i < nsel ? s_al[up][i] : 0.f;
+    }
+    if (a.xhat) {
+        for (int j = us; j < a.n; j += TPP) {
+            float acc = 0.f;
+            for (int i = 0; i < nsel; ++i) acc += s_al[up][i] * a.d_high[(int64_t)s_sup[up][i] * a.n + j];
+            a.xhat[b * (int64_t)a.n + j] = acc;
+        }
+    }
+}
+
+template <int LP, int KM, bool MASK>
+cspd_status launch(const FullArgs &a, hipStream_t st)
+{
+    const unsigned grid = (unsigned)((a.b + P - 1) / P);
+    char label[96];
+    snprintf(label, sizeof(label), "omp_full_mfma<f32,lp%d,k%d%s>:full", LP, KM, MASK ? ",mask" : "");
+    ProfileToken *tok = profile_begin(label, st);
+    hipLaunchKernelGGL((k_omp_full<LP, KM, MASK>), dim3(grid), dim3(64 * NW), 0, st, a);
+    profile_end(tok, st);
+    CSPD_HIP_CHECK(hipGetLastError());
+    return CSPD_OK;
+}
+
+template <int LP>
+cspd_status by_k(const FullArgs &a, int kmax, bool mask, hipStream_t st)
+{
+    if (kmax <= 8) return mask ? launch<LP, 8, true>(a, st) : launch<LP, 8, false>(a, st);
+    return mask ? launch<LP, 16, true>(a, st) : launch<LP, 16, false>(a, st);
+}
+
+}  // namespace full_impl
+
+bool full_mfma_fits(const cspd_plan_s *p)
+{
+    const ScalePlan &sc = p->sc[p->s - 1];
+    return p->dtype == CSPD_F32 && sc.t <= 32 * full_impl::SELW &&
+           (sc.lp == 16 || sc.lp == 32 || sc.lp == 64 || sc.lp == 128);
+}
 
 cspd_status launch_full_mfma(const cspd_plan_s *p, int64_t b, const void *y, const uint8_t *mask,
                              const int *kvec, int kuni, int *support, void *coef, int *k_used,
                              void *xhat, hipStream_t stream)
 {
-    (void)p; (void)b; (void)y; (void)mask; (void)kvec; (void)kuni; (void)support; (void)coef;
-    (void)k_used; (void)xhat; (void)stream;
-    return set_error(CSPD_E_UNSUPPORTED, "full search over %d atoms is not built yet", p->sc[p->s - 1].t);
+    using namespace full_impl;
+    if (!full_mfma_fits(p))
+        return set_error(CSPD_E_UNSUPPORTED, "full search over %d atoms of length %d is not built for this plan",
+                         p->sc[p->s - 1].t, p->sc[p->s - 1].l);
+    if (b <= 0) return CSPD_OK;
+    const ScalePlan &sc = p->sc[p->s - 1];
+    FullArgs a{};
+    a.b = b;
+    a.y = (const float *)y;
+    a.y_stride = p->m;
+    a.mask = p->phi_kind == CSPD_PHI_MASK ? mask : nullptr;
+    a.n = p->n;
+    a.v = (const float *)sc.v;
+    a.inv_nu = (const float *)sc.inv_nu;
+    a.t = sc.t;
+    a.l = sc.l;
+    a.lp = sc.lp;
+    a.rank = p->phi_kind == CSPD_PHI_DENSE ? p->m : sc.l;
+    a.kvec = kvec;
+    a.kuni = kuni;
+    a.kcap = p->k_max;
+    a.support = support;
+    a.coef = (float *)coef;
+    a.k_used = k_used;
+    a.xhat = (float *)xhat;
+    a.d_high = (const float *)p->d_high;
+    const int kmax = kvec ? p->k_max : kuni;
+    const bool m = a.mask != nullptr;
+    switch (sc.lp) {
+        case 16: return by_k<16>(a, kmax, m, stream);
+        case 32: return by_k<32>(a, kmax, m, stream);
+        case 64: return by_k<64>(a, kmax, m, stream);
+        case 128: return by_k<128>(a, kmax, m, stream);
+        default: return CSPD_E_UNSUPPORTED;
+    }
 }
 
 }  // namespace cspd

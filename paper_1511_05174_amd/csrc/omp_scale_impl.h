@@ -103,12 +103,21 @@ __device__ __forceinline__ void swap_pair(double v, double &a, double &b)
     b = __longlong_as_double(((long long)h1 << 32) | (unsigned)l1);
 }
 
+// (score, index) pairs: larger score wins, equal scores go to the smaller
+// index.  Written with bitwise operators so the compiler emits selects, not
+// branches.
+template <typename T>
+__device__ __forceinline__ bool beats(T s1, int i1, T s0, int i0)
+{
+    return (s1 > s0) | ((s1 == s0) & (i1 < i0));
+}
+
 template <typename T, int CTRL>
 __device__ __forceinline__ void argmax_step(T &s, int &i)
 {
     const T os = dpp<CTRL>(s);
     const int oi = dpp_i<CTRL>(i);
-    const bool take = os > s || (os == s && oi < i);
+    const bool take = beats(os, oi, s, i);
     s = take ? os : s;
     i = take ? oi : i;
 }
@@ -116,7 +125,7 @@ __device__ __forceinline__ void argmax_step(T &s, int &i)
 template <typename T>
 __device__ __forceinline__ void argmax_merge(T s0, int i0, T s1, int i1, T &s, int &i)
 {
-    const bool take1 = s1 > s0 || (s1 == s0 && i1 < i0);
+    const bool take1 = beats(s1, i1, s0, i0);
     s = take1 ? s1 : s0;
     i = take1 ? i1 : i0;
 }
@@ -192,11 +201,14 @@ struct GroupLds {
 // accumulated in FP64 from the stored vectors (all 64 lanes split the dot
 // products), then on lane 0 an FP64 Cholesky in place (pivots kept in
 // piv[0..n)) and, when `solve`, the two triangular solves (solution in h64).
-template <typename T, int LPA, int KM>
-__device__ void gram64_chol(const GroupLds<T, LPA, KM> &w, const ScaleArgs &a, const int *ids, int n,
-                            int lane, double *g64, double *h64, double *piv, double *gdiag, bool solve)
+// Arguments are passed by value: taking the address of the kernel's argument
+// record would move it to scratch memory for the whole kernel.
+template <typename T>
+__device__ __attribute__((noinline)) void gram64_chol(const T *v, int lp, int l, const T *sqw,
+                                                      const T *yhat, const int *ids, int n, int lane,
+                                                      double *g64, double *h64, double *piv,
+                                                      double *gdiag, bool solve)
 {
-    const T *v = (const T *)a.v;
     const int np = n * (n + 1) / 2;
     for (int pidx = lane; pidx < np + n; pidx += 64) {
         double s = 0.0;
@@ -204,18 +216,18 @@ __device__ void gram64_chol(const GroupLds<T, LPA, KM> &w, const ScaleArgs &a, c
             int i = 0, rem = pidx;
             while (rem > i) { rem -= i + 1; ++i; }
             const int j = rem;  // j <= i
-            const T *vi = v + (int64_t)ids[i] * a.lp;
-            const T *vj = v + (int64_t)ids[j] * a.lp;
-            for (int t = 0; t < a.l; ++t) {
-                const double wt = (double)w.sqw[t];
+            const T *vi = v + (int64_t)ids[i] * lp;
+            const T *vj = v + (int64_t)ids[j] * lp;
+            for (int t = 0; t < l; ++t) {
+                const double wt = (double)sqw[t];
                 s += ((double)vi[t] * wt) * ((double)vj[t] * wt);
             }
             g64[i * KX + j] = s;
             g64[j * KX + i] = s;
         } else {
             const int i = pidx - np;
-            const T *vi = v + (int64_t)ids[i] * a.lp;
-            for (int t = 0; t < a.l; ++t) s += (double)vi[t] * (double)w.sqw[t] * (double)w.yhat[t];
+            const T *vi = v + (int64_t)ids[i] * lp;
+            for (int t = 0; t < l; ++t) s += (double)vi[t] * (double)sqw[t] * (double)yhat[t];
             h64[i] = s;
         }
     }
@@ -251,7 +263,8 @@ __device__ void gram64_chol(const GroupLds<T, LPA, KM> &w, const ScaleArgs &a, c
 }
 
 template <typename T, int LP, int NC, int PPW, int KM, bool GRAM>
-__global__ __launch_bounds__(64 * W) void k_omp_scale(ScaleArgs a)
+__global__ __launch_bounds__(64 * W) 
+void k_omp_scale(ScaleArgs a)
 {
     constexpr int G = 64 / PPW;
     constexpr int LPA = GRAM ? LP_GRAM : LP;
@@ -387,7 +400,7 @@ __global__ __launch_bounds__(64 * W) void k_omp_scale(ScaleArgs a)
         c[s] = h;
         e[s] = ee;
         e0[s] = ee;
-        nu[s] = sqrt(ee);
+        nu[s] = T(1) / sqrt(ee);   // inverse norm
         if (!(ee > T(0))) live[s] = false;  // an effective column of zero is never picked
     }
 
@@ -410,7 +423,7 @@ __global__ __launch_bounds__(64 * W) void k_omp_scale(ScaleArgs a)
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             if (live[s]) {
-                const T sc = fabs(c[s]) / nu[s];
+                const T sc = fabs(c[s]) * nu[s];
                 if (sc > best) { best = sc; bidx = atom[s]; }
             }
         }
@@ -462,7 +475,7 @@ __global__ __launch_bounds__(64 * W) void k_omp_scale(ScaleArgs a)
                         double *h64 = g64 + KX * KX;
                         double *pv = h64 + KX;
                         double *gd = pv + KX;
-                        gram64_chol<T, LPA, KM>(wg, a, wg.sup, n + 1, lane, g64, h64, pv, gd, false);
+                        gram64_chol<T>((const T *)a.v, a.lp, a.l, wg.sqw, wg.yhat, wg.sup, n + 1, lane, g64, h64, pv, gd, false);
                         if (gi == g) {
                             const double piv = pv[n], gkk = gd[n];
                             if (!(piv > 1e-10 * gkk)) act = false;  // dependent in FP64 as well
@@ -473,40 +486,43 @@ __global__ __launch_bounds__(64 * W) void k_omp_scale(ScaleArgs a)
                 }
             }
         }
-        if (!act) active = false;
-        if (act) {
-            const T inv = T(1) / lnn;
-            const T zn = ck * inv;
+        active = active & act;
+        // updates run unconditionally; a group that stopped uses inv = 0,
+        // which leaves its state unchanged
+        const T inv = act ? T(1) / lnn : T(0);
+        const T zn = ck * inv;
+        const int kb = act ? bidx : INT_MAX;
 #pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                T g = 0;
-                if constexpr (!GRAM) {
+        for (int s = 0; s < NC; ++s) {
+            T g = 0;
+            if constexpr (!GRAM) {
 #pragma unroll
-                    for (int j = 0; j < LP; ++j) g += v[s][j] * w.vk[j];
-                } else {
-                    if (atom[s] != INT_MAX) g = ((const T *)a.gram)[(int64_t)bidx * a.t + atom[s]];
-                }
-                T dot = 0;
-#pragma unroll
-                for (int m = 0; m < n; ++m) dot += w.uk[m] * u[s][m];
-                const T un = (g - dot) * inv;
-                u[s][n] = un;
-                c[s] -= un * zn;
-                e[s] -= un * un;
-                if (atom[s] == bidx) live[s] = false;
+                for (int j = 0; j < LP; ++j) g += v[s][j] * w.vk[j];
+            } else {
+                if (act & (atom[s] != INT_MAX)) g = ((const T *)a.gram)[(int64_t)bidx * a.t + atom[s]];
             }
-            // column gl of L^{-1}: new entry of the appended row
-            T xd = gl == n ? T(1) : T(0);
+            T dot = 0;
 #pragma unroll
-            for (int m = 0; m < n; ++m) xd -= w.uk[m] * x[m];
-            x[n] = xd * inv;
-            z[n] = zn;
-            if (gl == 0) w.sup[n] = bidx;
-            trg += e0k;
-            lmax = n == 0 ? lnn : (lnn > lmax ? lnn : lmax);
-            lmin = n == 0 ? lnn : (lnn < lmin ? lnn : lmin);
-            nsel = n + 1;
+            for (int m = 0; m < n; ++m) dot += w.uk[m] * u[s][m];
+            const T un = (g - dot) * inv;
+            u[s][n] = un;
+            c[s] -= un * zn;
+            e[s] -= un * un;
+            live[s] = live[s] & (atom[s] != kb);
         }
+        // column gl of L^{-1}: new entry of the appended row
+        T xd = gl == n ? T(1) : T(0);
+#pragma unroll
+        for (int m = 0; m < n; ++m) xd -= w.uk[m] * x[m];
+        x[n] = xd * inv;
+        z[n] = zn;
+        if (act & (gl == 0)) w.sup[n] = bidx;
+        trg += act ? e0k : T(0);
+        const T lv = act ? lnn : (n == 0 ? T(1) : lmax);
+        lmax = n == 0 ? lv : (lv > lmax ? lv : lmax);
+        const T lw = act ? lnn : (n == 0 ? T(1) : lmin);
+        lmin = n == 0 ? lw : (lw < lmin ? lw : lmin);
+        nsel = act ? n + 1 : nsel;
     }
     wave_sync();
 
@@ -544,7 +560,7 @@ __global__ __launch_bounds__(64 * W) void k_omp_scale(ScaleArgs a)
                     double *h64 = g64 + KX * KX;
                     double *pv = h64 + KX;
                     double *gd = pv + KX;
-                    gram64_chol<T, LPA, KM>(wg, a, wg.sup, ng, lane, g64, h64, pv, gd, true);
+                    gram64_chol<T>((const T *)a.v, a.lp, a.l, wg.sqw, wg.yhat, wg.sup, ng, lane, g64, h64, pv, gd, true);
                     if (lane == g * G)
                         for (int i = 0; i < ng; ++i) wg.alpha[i] = (T)h64[i];
                     wave_sync();

@@ -83,6 +83,16 @@ __global__ void k_norms(const double *__restrict__ w64, int t_atoms, int l, T *_
     nu2[t] = (T)s;
 }
 
+__global__ void k_inv_norms(const double *__restrict__ w64, int t_atoms, int l, float *__restrict__ inv)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= t_atoms) return;
+    const double *a = w64 + (int64_t)t * l;
+    double s = 0.0;
+    for (int i = 0; i < l; ++i) s = fma(a[i], a[i], s);
+    inv[t] = s > 0.0 ? (float)(1.0 / sqrt(s)) : -1.0f;   // negative: never selectable
+}
+
 template <typename T>
 __global__ void k_gram(const double *__restrict__ w64, int t_atoms, int l, T *__restrict__ g)
 {
@@ -121,6 +131,10 @@ cspd_status finish_scale(ScalePlan &sc, const double *a64, const double *w64, bo
         CSPD_HIP_CHECK(hipMalloc(&sc.nu2, sizeof(T) * (size_t)sc.t));
         bytes += sizeof(T) * (size_t)sc.t;
         k_norms<T><<<blocks_for(sc.t, bs), bs, 0, st>>>(w64, sc.t, sc.l, (T *)sc.nu2);
+        CSPD_HIP_CHECK(hipGetLastError());
+        CSPD_HIP_CHECK(hipMalloc(&sc.inv_nu, sizeof(float) * (size_t)sc.t));
+        bytes += sizeof(float) * (size_t)sc.t;
+        k_inv_norms<<<blocks_for(sc.t, bs), bs, 0, st>>>(w64, sc.t, sc.l, (float *)sc.inv_nu);
         CSPD_HIP_CHECK(hipGetLastError());
     }
     if (want_gram) {

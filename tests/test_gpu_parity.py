@@ -199,3 +199,21 @@ def test_c2_full_size_sampled():
     rep = parity.compare(ws, sup, out["coef"][idx], out["k_used"][idx], out["xhat"][idx], tie_tol=1e-6)
     _say(f"[cross c2 full-size sampled] {rep.summary()}")
     assert not rep.mismatched and rep.coef_rel_max <= 1e-5 and rep.xhat_rel_max <= 1e-5
+
+
+# ------------------------------------------- full OMP on matrix cores (large T)
+def test_c2_full_mfma_masked():
+    check_full(synth.make("c2", batch=2053))
+
+
+def test_c3_full_mfma_dense():
+    check_full(synth.make("c3", batch=1024))
+
+
+def test_c4_full_mfma_uneven_k():
+    out, _ = check_full(synth.make("c4", batch=1029))
+    assert out["k_used"].min() >= 4
+
+
+def test_c5c_full_mfma_lightfield():
+    check_full(synth.make("c5c", batch=515))
