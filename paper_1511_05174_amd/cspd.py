@@ -310,3 +310,83 @@ def cspd_profile_read():
         lib.cspd_profile_read(i, buf, 128, C.byref(cnt), C.byref(ms))
         out[buf.value.decode()] = (int(cnt.value), float(ms.value))
     return out
+
+
+class Server:
+    """Owns a cspd_server_t and the host buffers of its pending jobs."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        self.pending = {}
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.cspd_serve_destroy(h)
+
+
+def cspd_serve_create(device: int = 0, hbm_budget_bytes: int = 16 << 30, max_slots: int = 4) -> Server:
+    h = C.c_void_p()
+    _check(load().cspd_serve_create(int(device), int(hbm_budget_bytes), int(max_slots), C.byref(h)))
+    return Server(h.value)
+
+
+def cspd_serve_submit(server: Server, plan: Plan, y: np.ndarray, mask: Optional[np.ndarray] = None,
+                      k_fine: Optional[np.ndarray] = None, k_fine_uniform: int = 0,
+                      k_scale: Sequence[int] = (), full: bool = False, want_coef: bool = True,
+                      want_xhat: bool = True) -> int:
+    """Queue a job on host arrays; returns its id.  Outputs are collected by
+    cspd_serve_poll."""
+    ndt = np.float64 if plan.dtype == "f64" else np.float32
+    y = np.ascontiguousarray(y, dtype=ndt)
+    B = y.shape[0]
+    if y.shape != (B, plan.m):
+        raise ValueError(f"y must be (B, {plan.m})")
+    bufs = {"y": y}
+    if mask is not None:
+        bufs["mask"] = np.ascontiguousarray(mask, dtype=np.uint8)
+    if k_fine is not None:
+        bufs["k_fine"] = np.ascontiguousarray(k_fine, dtype=np.int32)
+    bufs["support"] = np.empty((B, plan.k_max), dtype=np.int32)
+    bufs["k_used"] = np.empty((B,), dtype=np.int32)
+    if want_coef:
+        bufs["coef"] = np.empty((B, plan.k_max), dtype=ndt)
+    if want_xhat:
+        bufs["xhat"] = np.empty((B, plan.n), dtype=ndt)
+    j = Job()
+    j.plan = plan.handle
+    j.B = B
+    for name in ("y", "mask", "k_fine", "support", "coef", "k_used", "xhat"):
+        if name in bufs:
+            setattr(j, name, bufs[name].ctypes.data)
+    j.k_fine_uniform = int(k_fine_uniform)
+    for i, v in enumerate(k_scale):
+        j.k_scale[i] = int(v)
+    j.full = 1 if full else 0
+    jid = C.c_uint64()
+    _check(load().cspd_serve_submit(server.handle, C.byref(j), C.byref(jid)))
+    server.pending[jid.value] = (bufs, plan)
+    return jid.value
+
+
+def cspd_serve_poll(server: Server, job_id: int, timeout_us: int = -1):
+    """Returns (outputs dict, stats dict) once the job has finished, or None
+    while it is pending (E_BUSY).  Raises on failure or an unknown id."""
+    st = JobStats()
+    rc = load().cspd_serve_poll(server.handle, C.c_uint64(job_id), int(timeout_us), C.byref(st))
+    if rc == E_BUSY:
+        return None
+    if rc != OK:
+        server.pending.pop(job_id, None)
+        _check(rc)
+    bufs, _plan = server.pending.pop(job_id)
+    stats = {f: getattr(st, f) for f, _ in JobStats._fields_}
+    out = {k: v for k, v in bufs.items() if k in ("support", "coef", "k_used", "xhat")}
+    return out, stats
+
+
+def cspd_serve_destroy(server: Server):
+    h, server.handle = server.handle, None
+    if h:
+        load().cspd_serve_destroy(h)
+    server.pending.clear()

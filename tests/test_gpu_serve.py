@@ -1,0 +1,96 @@
+"""Serving loop on the GPU: continuous batching gives every job the same
+result it gets alone; admission respects the HBM budget."""
+import numpy as np
+import pytest
+
+import gpu_util as G
+import synth
+from paper_1511_05174_amd import cspd
+
+pytestmark = pytest.mark.gpu
+
+
+def _alone(plan, w, ks, full):
+    if full:
+        return G.run_full(plan, w)
+    return G.run_cross(plan, w, k_scales=ks)
+
+
+def _submit(srv, plan, w, ks, full):
+    return cspd.cspd_serve_submit(srv, plan, w.y, w.mask, w.k_fine, ks[-1], ks[:-1], full=full)
+
+
+def test_mix_equals_alone():
+    G.torch_mod()
+    wl = {"c2": synth.make("c2", batch=20000), "c5a": synth.make("c5a", batch=9000),
+          "c5b": synth.make("c5b", batch=6000)}
+    plans = {k: cspd.plan_from_workload(w) for k, w in wl.items()}
+    rng = np.random.default_rng(7)
+    srv = cspd.cspd_serve_create(0, 2 << 30, 3)
+    jobs = []
+    for i in range(40):
+        name = ["c2", "c5a", "c5b"][i % 3]
+        w = wl[name]
+        lo = int(rng.integers(0, w.batch - 1))
+        size = int(np.exp(rng.uniform(np.log(8), np.log(3000))))
+        idx = np.arange(lo, min(w.batch, lo + size))
+        sub = synth.subset(w, idx)
+        ks = list(w.k_scales)
+        full = (i % 7 == 3) and name == "c2"
+        jid = _submit(srv, plans[name], sub, ks, full)
+        jobs.append((jid, name, sub, ks, full))
+    batched = 0
+    for jid, name, sub, ks, full in jobs:
+        res = cspd.cspd_serve_poll(srv, jid, -1)
+        assert res is not None
+        out, st = res
+        assert st["status"] == 0 and st["patches"] == sub.batch
+        assert st["submit_ns"] <= st["admit_ns"] <= st["start_ns"] <= st["finish_ns"]
+        batched += st["batched_with"] > 0
+        ref = _alone(plans[name], sub, ks, full)
+        for k in ("support", "k_used"):
+            assert np.array_equal(out[k], ref[k]), (name, k)
+        assert np.array_equal(out["coef"].astype(np.float64), ref["coef"])
+        assert np.array_equal(out["xhat"].astype(np.float64), ref["xhat"])
+    cspd.cspd_serve_destroy(srv)
+    print(f"jobs batched with others: {batched} of {len(jobs)}", flush=True)
+
+
+def test_budget_admission_and_errors():
+    G.torch_mod()
+    w = synth.make("c2", batch=8192)
+    plan = cspd.plan_from_workload(w)
+    one = 4096 * (4 * 64 + 64 + 4 + 16 * 8 + 4 + 4 * 64 + 16 * 4) + 4096
+    srv = cspd.cspd_serve_create(0, int(one * 1.5), 2)   # one 4096-patch job at a time
+    ids = []
+    for s in range(0, 8192, 4096):
+        sub = synth.subset(w, np.arange(s, s + 4096))
+        ids.append((_submit(srv, plan, sub, w.k_scales, False), sub))
+    big = synth.subset(w, np.arange(0, 8192))
+    with pytest.raises(cspd.CspdError) as ei:
+        _submit(srv, plan, big, w.k_scales, False)
+    assert ei.value.code == cspd.E_CAPACITY
+    spans = []
+    for jid, sub in ids:
+        out, st = cspd.cspd_serve_poll(srv, jid, -1)
+        spans.append((st["admit_ns"], st["finish_ns"]))
+        ref = G.run_cross(plan, sub)
+        assert np.array_equal(out["support"], ref["support"])
+    spans.sort()
+    assert spans[1][0] >= spans[0][1] - 1_000_000   # second admitted after the first freed memory
+    with pytest.raises(cspd.CspdError) as ei:
+        cspd.cspd_serve_poll(srv, 10 ** 9, 0)
+    assert ei.value.code == cspd.E_NOTFOUND
+    cspd.cspd_serve_destroy(srv)
+
+
+def test_many_small_jobs_are_batched():
+    G.torch_mod()
+    w = synth.make("c2", batch=4096)
+    plan = cspd.plan_from_workload(w)
+    srv = cspd.cspd_serve_create(0, 1 << 30, 1)
+    ids = [_submit(srv, plan, synth.subset(w, np.arange(i * 64, i * 64 + 64)), w.k_scales, False)
+           for i in range(64)]
+    stats = [cspd.cspd_serve_poll(srv, j, -1)[1] for j in ids]
+    assert max(s["batched_with"] for s in stats) > 0
+    cspd.cspd_serve_destroy(srv)
