@@ -46,6 +46,14 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Square root and reciprocal of a pivot.  FP32 uses the hardware
+// instructions (about 1 ulp; the coefficients' error is dominated by the
+// conditioning of the support), FP64 the correctly rounded forms.
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+
 template <typename T> __device__ __forceinline__ T dep_tol();
 template <> __device__ __forceinline__ double dep_tol<double>() { return 1e-10; }
 template <> __device__ __forceinline__ float dep_tol<float>() { return 1e-5f; }
@@ -131,7 +139,43 @@ __device__ __forceinline__ void argmax_merge(T s0, int i0, T s1, int i1, T &s, i
 }
 
 // Group-wide argmax with ties to the lowest index; every lane of the group
-// ends with the result.
+// ends with the result.  FP32 scores are non-negative (or -1 for "none"), so
+// (score bits, ~index) packed into 64 bits orders exactly like (score, -index)
+// and each step is one 64-bit compare.
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v)
+{
+    const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)v);
+    const unsigned hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+template <int WIDTH>
+__device__ __forceinline__ unsigned long long swap_max_u64(unsigned long long v)
+{
+    int l0, l1, h0, h1;
+    swap_pair_i<WIDTH>((int)(unsigned)v, l0, l1);
+    swap_pair_i<WIDTH>((int)(unsigned)(v >> 32), h0, h1);
+    const unsigned long long a = ((unsigned long long)(unsigned)h0 << 32) | (unsigned)l0;
+    const unsigned long long b = ((unsigned long long)(unsigned)h1 << 32) | (unsigned)l1;
+    return a > b ? a : b;
+}
+
+template <int G>
+__device__ __forceinline__ void group_argmax(float &s, int &i)
+{
+    unsigned long long k = s >= 0.f ? (((unsigned long long)__float_as_uint(s) << 32) | (unsigned)(~i)) : 0ull;
+    unsigned long long o;
+    o = dpp_u64<DPP_QUAD_XOR1>(k); k = o > k ? o : k;
+    o = dpp_u64<DPP_QUAD_XOR2>(k); k = o > k ? o : k;
+    o = dpp_u64<DPP_ROW_HALF_MIRROR>(k); k = o > k ? o : k;
+    o = dpp_u64<DPP_ROW_MIRROR>(k); k = o > k ? o : k;
+    if constexpr (G >= 32) k = swap_max_u64<16>(k);
+    if constexpr (G >= 64) k = swap_max_u64<32>(k);
+    s = k ? __uint_as_float((unsigned)(k >> 32)) : -1.f;
+    i = k ? (int)~(unsigned)k : INT_MAX;
+}
+
 template <int G, typename T>
 __device__ __forceinline__ void group_argmax(T &s, int &i)
 {
@@ -422,12 +466,13 @@ void k_omp_scale(ScaleArgs a)
         int bidx = INT_MAX;
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
-            if (live[s]) {
-                const T sc = fabs(c[s]) * nu[s];
-                if (sc > best) { best = sc; bidx = atom[s]; }
-            }
+            const T sc = live[s] ? fabs(c[s]) * nu[s] : T(-1);
+            const bool up = sc > best;
+            best = up ? sc : best;
+            bidx = up ? atom[s] : bidx;
         }
-        if (!act) { best = T(-1); bidx = INT_MAX; }
+        best = act ? best : T(-1);
+        bidx = act ? bidx : INT_MAX;
         group_argmax<G>(best, bidx);
         act = act && best >= T(0);          // candidates exhausted otherwise
         // the owning lane publishes its vector, its u row and its scalars
@@ -459,7 +504,7 @@ void k_omp_scale(ScaleArgs a)
         }
         if (act && !need64) {
             if (!(ek > dep_tol<T>() * e0k)) act = false;  // picked atom is dependent
-            else lnn = sqrt(ek);
+            else lnn = fast_sqrt(ek);
         }
         if constexpr (sizeof(T) == 4) {
             // FP64 pivot: Cholesky of the FP64 Gram of Omega + {k}, one group at a time
@@ -489,7 +534,7 @@ void k_omp_scale(ScaleArgs a)
         active = active & act;
         // updates run unconditionally; a group that stopped uses inv = 0,
         // which leaves its state unchanged
-        const T inv = act ? T(1) / lnn : T(0);
+        const T inv = act ? fast_rcp(lnn) : T(0);
         const T zn = ck * inv;
         const int kb = act ? bidx : INT_MAX;
 #pragma unroll
