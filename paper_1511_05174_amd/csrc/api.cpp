@@ -134,6 +134,7 @@ ScaleArgs base_args(const cspd_plan_s *p, int s, int64_t B, const void *y, const
     a.m_dense = p->m;
     a.blk_off = sc.blk_off;
     a.blk_idx = sc.blk_idx;
+    a.blk_ident = sc.blk_ident;
     a.q = sc.q;
     a.d_high = p->d_high;
     return a;
@@ -303,6 +304,7 @@ cspd_status cspd_omp_cross_scale(cspd_plan_t p, int64_t B, const void *y, const 
         if (s > 0) {
             a.prev_sup = coarse + (off - k_scale[s - 1]);
             a.prev_stride = ksum;
+            a.prev_count = k_scale[s - 1];
             a.prev_kused = kused_c + (int64_t)B * (s - 1);
         }
         if (s + 1 < p->s) {

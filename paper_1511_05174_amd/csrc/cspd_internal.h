@@ -53,6 +53,7 @@ struct ScalePlan {
     void *gram = nullptr;     // t x t effective Gram (null unless precomputed)
     int *blk_off = nullptr;   // l + 1 (fold only): fine samples of each coarse sample
     int *blk_idx = nullptr;   // N (fold only)
+    int blk_ident = 0;        // fold whose blocks are single samples in signal order
 };
 
 }  // namespace cspd
@@ -91,9 +92,11 @@ struct ScaleArgs {
     int m_dense;                // measurement dim when dense (rank bound)
     const int *blk_off;
     const int *blk_idx;
+    int blk_ident;              // 1: coordinate t of the scale is fine sample t
     int first;                  // 1: every atom is a candidate
     const int *prev_sup;        // b x prev_stride (first == 0)
     int prev_stride;
+    int prev_count;             // entries of the previous scale in each prev_sup row
     const int *prev_kused;      // b
     int q;                      // children per parent
     const int *kvec;            // b or null

@@ -5,7 +5,7 @@
 // candidate s*G + l.  At scale 0 every atom of D_0 is a candidate (problem
 // (P_low) of Section III-C); at finer scales the candidates are the child
 // blocks f(Omega) of the previous scale's support (Section III-B, problem
-// (P_high), Algorithm 2), in ascending atom order.
+// (P_high), Algorithm 2).
 //
 // Each OMP iteration (Algorithm 1: proxy, support merge, projection, residue)
 // is carried in candidate coordinates with an incremental Cholesky factor L of
@@ -315,6 +315,7 @@ void k_omp_scale(ScaleArgs a)
     constexpr int VL = GRAM ? 1 : LP;       // per-slot vector registers
     __shared__ GroupLds<T, LPA, KM> lds[W * PPW];
     __shared__ double lds64[W][KX * KX + 4 * KX];
+    extern __shared__ double dyn_lds[];     // block-fold staging (fold_lds_bytes)
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int gi = lane / G;
@@ -323,62 +324,140 @@ void k_omp_scale(ScaleArgs a)
     if (wave_first >= a.b) return;          // the whole wavefront leaves together
     const int64_t b = wave_first + gi;
     const bool valid = b < a.b;
+    const int64_t bb = valid ? b : wave_first;   // a row that exists, for loads
     GroupLds<T, LPA, KM> &w = lds[wv * PPW + gi];
-    const T *y = (const T *)a.y + (valid ? b : 0) * (int64_t)a.y_stride;
+    const T *y = (const T *)a.y + bb * (int64_t)a.y_stride;
     const int lp = GRAM ? a.lp : LP;
+
+    // Every load of the prologue is issued into registers before any result
+    // is used (one round trip to memory); the candidate vectors follow once
+    // the candidate set is known.
+    // ---- previous support and sparsity -----------------------------------
+    int kp = 0, pv = -1;
+    if (!a.first) {
+        kp = a.prev_kused[bb];
+        if (a.prev_count > 0) {   // entries at or past prev_count are masked where used
+            const int gc = gl < a.prev_count ? gl : 0;
+            pv = a.prev_sup[bb * (int64_t)a.prev_stride + gc];
+        }
+    }
+    const int kreq = a.kvec ? a.kvec[bb] : a.kuni;
+
+    // ---- measurement samples (and the fold's block table) ----------------
+    constexpr int NJ = 256 / G;            // fold plans have n <= 256, dense m <= 256
+    const bool fold = a.fold == kFold;
+    const bool blocks = fold && !a.blk_ident;
+    const int ny = fold ? a.n : a.l;       // samples of y read at this scale
+    const uint8_t *mrow = (fold && a.mask) ? a.mask + bb * (int64_t)a.n : nullptr;
+    T yr[NJ];
+    int mr[NJ];
+#pragma unroll
+    for (int r = 0; r < NJ; ++r) {
+        yr[r] = T(0);
+        mr[r] = 0;
+        if (r * G < ny) {
+            const int j = r * G + gl;
+            const int jc = j < ny ? j : 0;
+            yr[r] = y[jc];
+            mr[r] = mrow ? (int)mrow[jc] : 1;
+        }
+    }
+    constexpr int NT = 256 / 64 + 1;       // block table entries per lane (n + l + 1 <= 513)
+    int tb[2 * NT];
+    const int ntab = blocks ? a.l + 1 + a.n : 0;
+#pragma unroll
+    for (int r = 0; r < 2 * NT; ++r) {
+        tb[r] = 0;
+        if (r * 64 < ntab) {
+            const int i = r * 64 + lane;
+            const int ic = i < ntab ? i : 0;
+            tb[r] = ic <= a.l ? a.blk_off[ic] : a.blk_idx[ic - a.l - 1];
+        }
+    }
 
     // ---- measurement in the scale's coordinates -------------------------
     int rank_bound = 0;
-    for (int t0 = 0; t0 < lp; t0 += G) {
-        const int t = t0 + gl;
-        bool nz = false;
-        if (t < lp) {
-            T yh = 0, sq = 0;
-            if (valid && t < a.l) {
-                if (a.fold == kFold) {
+    if (!fold) {
+#pragma unroll
+        for (int r = 0; r < NJ; ++r) {
+            const int t = r * G + gl;
+            if (r * G < lp && t < lp) {
+                w.yhat[t] = (valid && t < a.l) ? yr[r] : T(0);
+                w.sqw[t] = T(1);
+            }
+        }
+        rank_bound = a.m_dense;
+    } else if (!blocks) {
+        // coordinate t is fine sample t: weight 1 if observed, else 0
+#pragma unroll
+        for (int r = 0; r < NJ; ++r) {
+            if (r * G < lp) {
+                const int t = r * G + gl;
+                const bool obs = valid && t < a.l && mr[r] != 0;
+                if (t < lp) {
+                    w.yhat[t] = obs ? yr[r] : T(0);
+                    w.sqw[t] = obs ? T(1) : T(0);
+                }
+                rank_bound += group_count<G>(obs, lane);
+            }
+        }
+    } else {
+        // blocks of several fine samples: stage the patch's observed samples
+        // and the block table in LDS, then each lane folds its coordinates
+        T *ys = (T *)dyn_lds + (wv * PPW + gi) * 2 * a.n;
+        T *ms = ys + a.n;
+        int *bo = (int *)((T *)dyn_lds + W * PPW * 2 * a.n) + wv * (a.l + 1 + a.n);
+        int *bi = bo + a.l + 1;
+#pragma unroll
+        for (int r = 0; r < 2 * NT; ++r)
+            if (r * 64 + lane < ntab) bo[r * 64 + lane] = tb[r];
+#pragma unroll
+        for (int r = 0; r < NJ; ++r) {
+            const int j = r * G + gl;
+            if (r * G < a.n && j < a.n) {
+                const bool obs = valid && mr[r] != 0;
+                ys[j] = obs ? yr[r] : T(0);
+                ms[j] = obs ? T(1) : T(0);
+            }
+        }
+        wave_sync();
+        for (int t0 = 0; t0 < lp; t0 += G) {
+            const int t = t0 + gl;
+            bool nz = false;
+            if (t < lp) {
+                T yh = 0, sq = 0;
+                if (t < a.l) {
                     T cnt = 0, acc = 0;
-                    const int j0 = a.blk_off[t], j1 = a.blk_off[t + 1];
+                    const int j0 = bo[t], j1 = bo[t + 1];
                     for (int jj = j0; jj < j1; ++jj) {
-                        const int j = a.blk_idx[jj];
-                        const bool obs = a.mask ? a.mask[b * (int64_t)a.n + j] != 0 : true;
-                        if (obs) { cnt += T(1); acc += y[j]; }
+                        const int j = bi[jj];
+                        cnt += ms[j];
+                        acc += ys[j];
                     }
                     sq = sqrt(cnt);
                     yh = cnt > T(0) ? acc / sq : T(0);
                     nz = cnt > T(0);
-                } else {
-                    yh = y[t];
-                    sq = T(1);
-                    nz = true;
                 }
+                w.yhat[t] = yh;
+                w.sqw[t] = sq;
             }
-            w.yhat[t] = yh;
-            w.sqw[t] = sq;
+            rank_bound += group_count<G>(nz, lane);
         }
-        rank_bound += group_count<G>(nz, lane);
     }
-    if (a.fold != kFold) rank_bound = a.m_dense;
 
     // ---- candidate set ---------------------------------------------------
+    // Candidates of a finer scale are the child blocks of the previous
+    // support, in the order of that support; the order only places
+    // candidates on lanes (ties in the proxy go to the lowest atom index).
     int nc = 0;
-    if (valid) {
-        if (a.first) {
-            nc = a.t;
-        } else {
-            const int kp = a.prev_kused[b];
-            const int *ps = a.prev_sup + b * (int64_t)a.prev_stride;
-            if (gl < kp) {
-                const int pi = ps[gl];
-                int rank = 0;
-                for (int j = 0; j < kp; ++j) rank += ps[j] < pi;
-                w.par[rank] = pi;
-            }
-            nc = kp * a.q;
-        }
+    if (a.first) {
+        nc = valid ? a.t : 0;
+    } else {
+        if (gl < KX) w.par[gl] = gl < a.prev_count ? pv : -1;
+        nc = valid ? kp * a.q : 0;
     }
     int K = 0;
     if (valid) {
-        const int kreq = a.kvec ? a.kvec[b] : a.kuni;
         K = kreq < nc ? kreq : nc;
         K = K < KM ? K : KM;
         K = K < a.sup_count ? K : a.sup_count;
@@ -400,52 +479,73 @@ void k_omp_scale(ScaleArgs a)
     T u[NC][KM];
     int atom[NC];
     bool live[NC];
+    const T *src[NC];
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
         const int ci = s * G + gl;
         live[s] = ci < nc;
-        atom[s] = INT_MAX;
-        if (live[s]) atom[s] = a.first ? ci : w.par[ci / a.q] * a.q + ci % a.q;
+        int at = ci;
+        if (!a.first) {
+            const int pi = w.par[min(ci / a.q, KX - 1)];
+            at = pi * a.q + ci % a.q;
+        }
+        atom[s] = live[s] ? at : INT_MAX;
+        src[s] = (const T *)a.v + (int64_t)(live[s] ? at : 0) * (GRAM ? lp : LP);
 #pragma unroll
         for (int m = 0; m < KM; ++m) u[s][m] = T(0);
-        T h = 0, ee = 0;
-        if constexpr (!GRAM) {
-            const T *src = (const T *)a.v + (int64_t)(live[s] ? atom[s] : 0) * LP;
+    }
+    T h[NC], ee[NC];
+#pragma unroll
+    for (int s = 0; s < NC; ++s) { h[s] = T(0); ee[s] = T(0); }
+    if constexpr (!GRAM) {
+        // every slot's vector is requested before any is used
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
             if constexpr (sizeof(T) == 4) {
 #pragma unroll
                 for (int j = 0; j < LP; j += 4) {
-                    const float4 q = *reinterpret_cast<const float4 *>(src + j);
+                    const float4 q = *reinterpret_cast<const float4 *>(src[s] + j);
                     v[s][j] = q.x; v[s][j + 1] = q.y; v[s][j + 2] = q.z; v[s][j + 3] = q.w;
                 }
             } else {
 #pragma unroll
                 for (int j = 0; j < LP; j += 2) {
-                    const double2 q = *reinterpret_cast<const double2 *>(src + j);
+                    const double2 q = *reinterpret_cast<const double2 *>(src[s] + j);
                     v[s][j] = q.x; v[s][j + 1] = q.y;
                 }
             }
+        }
 #pragma unroll
-            for (int j = 0; j < LP; ++j) {
-                const T x = live[s] ? v[s][j] * w.sqw[j] : T(0);
+        for (int j = 0; j < LP; ++j) {
+            const T sw = w.sqw[j], yh = w.yhat[j];
+#pragma unroll
+            for (int s = 0; s < NC; ++s) {
+                const T xv = v[s][j] * sw;
+                const T x = live[s] ? xv : T(0);
                 v[s][j] = x;
-                h += x * w.yhat[j];
-                ee += x * x;
-            }
-        } else {
-            if (live[s]) {
-                const T *src = (const T *)a.v + (int64_t)atom[s] * lp;
-                for (int j = 0; j < lp; ++j) {
-                    const T x = src[j] * w.sqw[j];
-                    h += x * w.yhat[j];
-                    ee += x * x;
-                }
+                h[s] += x * yh;
+                ee[s] += x * x;
             }
         }
-        c[s] = h;
-        e[s] = ee;
-        e0[s] = ee;
-        nu[s] = T(1) / sqrt(ee);   // inverse norm
-        if (!(ee > T(0))) live[s] = false;  // an effective column of zero is never picked
+    } else {
+        for (int j = 0; j < lp; ++j) {
+            const T sw = w.sqw[j], yh = w.yhat[j];
+#pragma unroll
+            for (int s = 0; s < NC; ++s) {
+                const T xv = src[s][j] * sw;
+                const T x = live[s] ? xv : T(0);
+                h[s] += x * yh;
+                ee[s] += x * x;
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        c[s] = h[s];
+        e[s] = ee[s];
+        e0[s] = ee[s];
+        nu[s] = T(1) / sqrt(ee[s]);   // inverse norm
+        if (!(ee[s] > T(0))) live[s] = false;  // an effective column of zero is never picked
     }
 
     // ---- OMP iterations (Algorithm 1), unrolled so u / x / z stay in VGPRs
@@ -624,11 +724,26 @@ void k_omp_scale(ScaleArgs a)
         const T *dh = (const T *)a.d_high;
         T *xh = (T *)a.xhat + b * (int64_t)a.n;
         for (int j = gl; j < a.n; j += G) {
+            // every atom's sample is requested at once; unused terms add zero
             T acc = 0;
-            for (int i = 0; i < nsel; ++i) acc += w.alpha[i] * dh[(int64_t)w.sup[i] * a.n + j];
+#pragma unroll
+            for (int i = 0; i < KM; ++i) {
+                const bool in = i < nsel;
+                const int si = in ? w.sup[i] : 0;
+                const T al = in ? w.alpha[i] : T(0);
+                acc += al * dh[(int64_t)si * a.n + j];
+            }
             xh[j] = acc;
         }
     }
+}
+
+// Dynamic LDS of one workgroup: per group the patch's observed samples and
+// their indicators (2 n values), per wavefront the block table (l + 1 + n).
+inline size_t fold_lds_bytes(const ScaleArgs &a, size_t elem, int ppw)
+{
+    if (a.fold != kFold || a.blk_ident) return 0;
+    return elem * (size_t)(W * ppw * 2 * a.n) + sizeof(int) * (size_t)(W * (a.l + 1 + a.n));
 }
 
 template <typename T, int LP, int NC, int PPW, int KM, bool GRAM>
@@ -644,7 +759,8 @@ cspd_status launch_one(const ScaleArgs &a, hipStream_t st)
         snprintf(label, sizeof(label), "omp_scale<%s,%s,lp%d,nc%d,ppw%d,k%d>:s%d", sizeof(T) == 8 ? "f64" : "f32",
                  GRAM ? "gram" : "vec", GRAM ? a.lp : LP, NC, PPW, KM, a.scale);
     ProfileToken *tok = profile_begin(label, st);
-    hipLaunchKernelGGL((k_omp_scale<T, LP, NC, PPW, KM, GRAM>), dim3(grid), dim3(64 * W), 0, st, a);
+    hipLaunchKernelGGL((k_omp_scale<T, LP, NC, PPW, KM, GRAM>), dim3(grid), dim3(64 * W),
+                       fold_lds_bytes(a, sizeof(T), PPW), st, a);
     profile_end(tok, st);
     CSPD_HIP_CHECK(hipGetLastError());
     return CSPD_OK;

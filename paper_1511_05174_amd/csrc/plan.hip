@@ -212,6 +212,9 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
             CSPD_HIP_CHECK(hipMemcpyAsync(sc.blk_idx, idx.data(), sizeof(int) * (size_t)N,
                                           hipMemcpyHostToDevice, st));
             p->bytes += sizeof(int) * (size_t)(ns + 1 + N);
+            bool ident = ns == N;
+            for (int j = 0; ident && j < N; ++j) ident = idx[j] == j;
+            sc.blk_ident = ident ? 1 : 0;
         }
         sc.n_s = ns;
         sc.t = T;
