@@ -28,7 +28,7 @@ cspd_status set_error(cspd_status code, const char *fmt, ...)
 
 void clear_error() { g_err.clear(); }
 
-bool scale_vec_fits(int lp, int max_cand);
+bool scale_vec_fits(int lp, int max_cand, bool f64);
 
 namespace {
 
@@ -241,7 +241,8 @@ cspd_status cspd_omp_full(cspd_plan_t p, int64_t B, const void *y, const uint8_t
     a.xhat = xhat;
     const int cand = sc.t;
     cspd_status rc;
-    if (scale_vec_fits(sc.lp, cand) || sc.gram) rc = launch_scale(p->dtype, a, cand, !scale_vec_fits(sc.lp, cand), st);
+    const bool fits = scale_vec_fits(sc.lp, cand, p->dtype == CSPD_F64);
+    if (fits || sc.gram) rc = launch_scale(p->dtype, a, cand, !fits, st);
     else rc = launch_full_mfma(p, B, y, mask, k, k_uniform, support, coef, k_used, xhat, st);
     if (rc == CSPD_E_UNSUPPORTED && cspd::g_err.empty())
         return set_error(rc, "no full-search kernel for T = %d, length %d", sc.t, sc.l);
@@ -277,7 +278,7 @@ cspd_status cspd_omp_cross_scale(cspd_plan_t p, int64_t B, const void *y, const 
     for (int s = 0; s < p->s; ++s) {
         const int kprev = s == 0 ? 0 : k_scale[s - 1];
         cand[s] = max_candidates(p, s, s == 0, kprev);
-        if (!scale_vec_fits(p->sc[s].lp, cand[s])) {
+        if (!scale_vec_fits(p->sc[s].lp, cand[s], p->dtype == CSPD_F64)) {
             if (s == 0 && p->sc[s].gram) gram[s] = 1;
             else return set_error(CSPD_E_UNSUPPORTED, "scale %d: no kernel for %d candidates of length %d",
                                   s, cand[s], p->sc[s].l);

@@ -35,8 +35,9 @@ bool have_vec(int lp, int nc, int ppw)
 // Register-resident shape for `max_cand` candidates of length `lp`:
 // two patches per wavefront when their vectors fit in 64 VGPRs, else one
 // patch per wavefront within 128 VGPRs.  Returns false when neither fits.
-bool scale_vec_shape(int lp, int max_cand, int *nc, int *ppw)
+bool scale_vec_shape(int lp, int max_cand, bool f64, int *nc, int *ppw)
 {
+    (void)f64;
     const int n2 = pow2_at_least((max_cand + 31) / 32);
     if (n2 * lp <= 64 && have_vec(lp, n2, 2)) { *nc = n2; *ppw = 2; return true; }
     const int n1 = pow2_at_least((max_cand + 63) / 64);
@@ -44,10 +45,10 @@ bool scale_vec_shape(int lp, int max_cand, int *nc, int *ppw)
     return false;
 }
 
-bool scale_vec_fits(int lp, int max_cand)
+bool scale_vec_fits(int lp, int max_cand, bool f64)
 {
     int nc, ppw;
-    return scale_vec_shape(lp, max_cand, &nc, &ppw);
+    return scale_vec_shape(lp, max_cand, f64, &nc, &ppw);
 }
 
 cspd_status launch_scale(int dtype, const ScaleArgs &a, int max_cand, bool gram, hipStream_t st)
@@ -57,7 +58,7 @@ cspd_status launch_scale(int dtype, const ScaleArgs &a, int max_cand, bool gram,
     if (gram) {
         nc = pow2_at_least((max_cand + 63) / 64);
         if (nc > 16 || a.lp > 256) return CSPD_E_UNSUPPORTED;
-    } else if (!scale_vec_shape(a.lp, max_cand, &nc, &ppw)) {
+    } else if (!scale_vec_shape(a.lp, max_cand, dtype == CSPD_F64, &nc, &ppw)) {
         return CSPD_E_UNSUPPORTED;
     }
     const int k = a.sup_count < kMaxK ? a.sup_count : kMaxK;

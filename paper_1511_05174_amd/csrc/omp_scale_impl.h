@@ -39,11 +39,15 @@ constexpr int W = kWavesPerBlock;
 constexpr int KX = kMaxK;        // FP64 rare-path table size
 constexpr int LP_GRAM = 256;     // LDS row length for gram-mode kernels
 
+// LDS exchange between lanes of one wavefront.  Every LDS record of these
+// kernels is private to one wavefront, and a wavefront's LDS operations are
+// performed in issue order, so wavefront-scope fences only have to keep the
+// compiler from reordering; no wait for the writes is needed.
 __device__ __forceinline__ void wave_sync()
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Square root and reciprocal of a pivot.  FP32 uses the hardware
@@ -61,10 +65,13 @@ template <> __device__ __forceinline__ float dep_tol<float>() { return 1e-5f; }
 // ---- cross-lane primitives (groups of 16, 32 or 64 lanes) -----------------
 enum { DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_ROW_HALF_MIRROR = 0x141, DPP_ROW_MIRROR = 0x140 };
 
+// Row-local lane permutation.  Every lane of the wavefront is active where
+// these are used, so no lane reads a disabled one; written as an update with
+// a zero `old` so that the compiler folds it into the consuming instruction.
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v)
 {
-    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
 
 template <int CTRL>
@@ -139,41 +146,58 @@ __device__ __forceinline__ void argmax_merge(T s0, int i0, T s1, int i1, T &s, i
 }
 
 // Group-wide argmax with ties to the lowest index; every lane of the group
-// ends with the result.  FP32 scores are non-negative (or -1 for "none"), so
-// (score bits, ~index) packed into 64 bits orders exactly like (score, -index)
-// and each step is one 64-bit compare.
-template <int CTRL>
-__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v)
+// ends with the result.  FP32 scores are non-negative (or -1 for "none"):
+// one integer reduction over their bit patterns finds the largest score, a
+// second one the lowest index among the lanes that hold it.
+template <int G>
+__device__ __forceinline__ int group_max(int k)
 {
-    const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)v);
-    const unsigned hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(v >> 32));
-    return ((unsigned long long)hi << 32) | lo;
+    k = max(k, dpp_i<DPP_QUAD_XOR1>(k));
+    k = max(k, dpp_i<DPP_QUAD_XOR2>(k));
+    k = max(k, dpp_i<DPP_ROW_HALF_MIRROR>(k));
+    k = max(k, dpp_i<DPP_ROW_MIRROR>(k));
+    if constexpr (G >= 32) {
+        int x, y;
+        swap_pair_i<16>(k, x, y);
+        k = max(x, y);
+    }
+    if constexpr (G >= 64) {
+        int x, y;
+        swap_pair_i<32>(k, x, y);
+        k = max(x, y);
+    }
+    return k;
 }
 
-template <int WIDTH>
-__device__ __forceinline__ unsigned long long swap_max_u64(unsigned long long v)
+template <int G>
+__device__ __forceinline__ int group_min(int k)
 {
-    int l0, l1, h0, h1;
-    swap_pair_i<WIDTH>((int)(unsigned)v, l0, l1);
-    swap_pair_i<WIDTH>((int)(unsigned)(v >> 32), h0, h1);
-    const unsigned long long a = ((unsigned long long)(unsigned)h0 << 32) | (unsigned)l0;
-    const unsigned long long b = ((unsigned long long)(unsigned)h1 << 32) | (unsigned)l1;
-    return a > b ? a : b;
+    k = min(k, dpp_i<DPP_QUAD_XOR1>(k));
+    k = min(k, dpp_i<DPP_QUAD_XOR2>(k));
+    k = min(k, dpp_i<DPP_ROW_HALF_MIRROR>(k));
+    k = min(k, dpp_i<DPP_ROW_MIRROR>(k));
+    if constexpr (G >= 32) {
+        int x, y;
+        swap_pair_i<16>(k, x, y);
+        k = min(x, y);
+    }
+    if constexpr (G >= 64) {
+        int x, y;
+        swap_pair_i<32>(k, x, y);
+        k = min(x, y);
+    }
+    return k;
 }
 
 template <int G>
 __device__ __forceinline__ void group_argmax(float &s, int &i)
 {
-    unsigned long long k = s >= 0.f ? (((unsigned long long)__float_as_uint(s) << 32) | (unsigned)(~i)) : 0ull;
-    unsigned long long o;
-    o = dpp_u64<DPP_QUAD_XOR1>(k); k = o > k ? o : k;
-    o = dpp_u64<DPP_QUAD_XOR2>(k); k = o > k ? o : k;
-    o = dpp_u64<DPP_ROW_HALF_MIRROR>(k); k = o > k ? o : k;
-    o = dpp_u64<DPP_ROW_MIRROR>(k); k = o > k ? o : k;
-    if constexpr (G >= 32) k = swap_max_u64<16>(k);
-    if constexpr (G >= 64) k = swap_max_u64<32>(k);
-    s = k ? __uint_as_float((unsigned)(k >> 32)) : -1.f;
-    i = k ? (int)~(unsigned)k : INT_MAX;
+    // bit patterns of non-negative floats order like the floats; -1 is
+    // negative as an integer
+    const int sb = __float_as_int(s);
+    const int mb = group_max<G>(sb);
+    i = group_min<G>((sb == mb && mb >= 0) ? i : INT_MAX);
+    s = __int_as_float(mb);
 }
 
 template <int G, typename T>
@@ -238,7 +262,6 @@ struct GroupLds {
     T alpha[KX];
     T sc[4];
     int sup[KX];
-    int par[KX];
 };
 
 // FP64 Gram matrix and right-hand side of atoms ids[0..n-1] of one group,
@@ -332,6 +355,56 @@ void k_omp_scale(ScaleArgs a)
     // Every load of the prologue is issued into registers before any result
     // is used (one round trip to memory); the candidate vectors follow once
     // the candidate set is known.
+    // ---- candidate set ---------------------------------------------------
+    // At the first scale every atom is a candidate; at a finer scale the
+    // candidates are the child blocks of the previous support, in the order
+    // of that support (the order only places candidates on lanes: ties in
+    // the proxy go to the lowest atom index).  Each lane then requests its
+    // candidate vectors at once.
+    T v[NC][VL];
+    T c[NC], e[NC], e0[NC], nu[NC];
+    T u[NC][KM];
+    int atom[NC];
+    bool live[NC];
+    const T *src[NC];
+    int nc = 0;
+    auto candidates = [&](int ncand, int pvv) {
+        nc = ncand;
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const int ci = s * G + gl;
+            live[s] = ci < nc;
+            int at = ci;
+            if (!a.first) {
+                // parent ci / q of the previous support, from the lane that loaded it
+                const int pj = live[s] ? ci / a.q : 0;
+                const int pi = __shfl(pvv, pj, G);
+                at = pi * a.q + ci % a.q;
+            }
+            atom[s] = live[s] ? at : INT_MAX;
+            src[s] = (const T *)a.v + (int64_t)(live[s] ? at : 0) * (GRAM ? lp : LP);
+        }
+        if constexpr (!GRAM) {
+#pragma unroll
+            for (int s = 0; s < NC; ++s) {
+                if constexpr (sizeof(T) == 4) {
+#pragma unroll
+                    for (int j = 0; j < LP; j += 4) {
+                        const float4 q = *reinterpret_cast<const float4 *>(src[s] + j);
+                        v[s][j] = q.x; v[s][j + 1] = q.y; v[s][j + 2] = q.z; v[s][j + 3] = q.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < LP; j += 2) {
+                        const double2 q = *reinterpret_cast<const double2 *>(src[s] + j);
+                        v[s][j] = q.x; v[s][j + 1] = q.y;
+                    }
+                }
+            }
+        }
+    };
+    if (a.first) candidates(valid ? a.t : 0, -1);   // needs no load
+
     // ---- previous support and sparsity -----------------------------------
     int kp = 0, pv = -1;
     if (!a.first) {
@@ -344,10 +417,12 @@ void k_omp_scale(ScaleArgs a)
     const int kreq = a.kvec ? a.kvec[bb] : a.kuni;
 
     // ---- measurement samples (and the fold's block table) ----------------
-    constexpr int NJ = 256 / G;            // fold plans have n <= 256, dense m <= 256
+    // Without blocks a lane reads the samples of its own coordinates (at most
+    // lp of them); blocks stage all n samples through LDS further down.
+    constexpr int NJ = GRAM ? 256 / G : (LP + G - 1) / G;
     const bool fold = a.fold == kFold;
     const bool blocks = fold && !a.blk_ident;
-    const int ny = fold ? a.n : a.l;       // samples of y read at this scale
+    const int ny = blocks ? 0 : a.l;       // samples of y read here
     const uint8_t *mrow = (fold && a.mask) ? a.mask + bb * (int64_t)a.n : nullptr;
     T yr[NJ];
     int mr[NJ];
@@ -362,18 +437,8 @@ void k_omp_scale(ScaleArgs a)
             mr[r] = mrow ? (int)mrow[jc] : 1;
         }
     }
-    constexpr int NT = 256 / 64 + 1;       // block table entries per lane (n + l + 1 <= 513)
-    int tb[2 * NT];
-    const int ntab = blocks ? a.l + 1 + a.n : 0;
-#pragma unroll
-    for (int r = 0; r < 2 * NT; ++r) {
-        tb[r] = 0;
-        if (r * 64 < ntab) {
-            const int i = r * 64 + lane;
-            const int ic = i < ntab ? i : 0;
-            tb[r] = ic <= a.l ? a.blk_off[ic] : a.blk_idx[ic - a.l - 1];
-        }
-    }
+
+    if (!a.first) candidates(valid ? kp * a.q : 0, pv);
 
     // ---- measurement in the scale's coordinates -------------------------
     int rank_bound = 0;
@@ -408,17 +473,16 @@ void k_omp_scale(ScaleArgs a)
         T *ms = ys + a.n;
         int *bo = (int *)((T *)dyn_lds + W * PPW * 2 * a.n) + wv * (a.l + 1 + a.n);
         int *bi = bo + a.l + 1;
-#pragma unroll
-        for (int r = 0; r < 2 * NT; ++r)
-            if (r * 64 + lane < ntab) bo[r * 64 + lane] = tb[r];
-#pragma unroll
-        for (int r = 0; r < NJ; ++r) {
-            const int j = r * G + gl;
-            if (r * G < a.n && j < a.n) {
-                const bool obs = valid && mr[r] != 0;
-                ys[j] = obs ? yr[r] : T(0);
-                ms[j] = obs ? T(1) : T(0);
-            }
+        const int ntab = a.l + 1 + a.n;
+#pragma unroll 4
+        for (int i = lane; i < ntab; i += 64) bo[i] = i <= a.l ? a.blk_off[i] : a.blk_idx[i - a.l - 1];
+#pragma unroll 4
+        for (int j = gl; j < a.n; j += G) {
+            const T yv = y[j];
+            const int mk = mrow ? (int)mrow[j] : 1;
+            const bool obs = valid && mk != 0;
+            ys[j] = obs ? yv : T(0);
+            ms[j] = obs ? T(1) : T(0);
         }
         wave_sync();
         for (int t0 = 0; t0 < lp; t0 += G) {
@@ -445,17 +509,6 @@ void k_omp_scale(ScaleArgs a)
         }
     }
 
-    // ---- candidate set ---------------------------------------------------
-    // Candidates of a finer scale are the child blocks of the previous
-    // support, in the order of that support; the order only places
-    // candidates on lanes (ties in the proxy go to the lowest atom index).
-    int nc = 0;
-    if (a.first) {
-        nc = valid ? a.t : 0;
-    } else {
-        if (gl < KX) w.par[gl] = gl < a.prev_count ? pv : -1;
-        nc = valid ? kp * a.q : 0;
-    }
     int K = 0;
     if (valid) {
         K = kreq < nc ? kreq : nc;
@@ -464,57 +517,23 @@ void k_omp_scale(ScaleArgs a)
         K = K > 0 ? K : 0;
     }
     // iterations the wavefront runs: the largest K of its groups
-    int kwave = K;
-    if constexpr (PPW == 2) {
-        int o0, o1;
-        swap_pair_i<32>(K, o0, o1);
-        kwave = o0 > o1 ? o0 : o1;
+    int kwave = 0;
+#pragma unroll
+    for (int g = 0; g < PPW; ++g) {
+        const int kg = __builtin_amdgcn_readlane(K, g * G);
+        kwave = kg > kwave ? kg : kwave;
     }
-    kwave = __builtin_amdgcn_readfirstlane(kwave);
-    wave_sync();
 
     // ---- per-candidate state --------------------------------------------
-    T v[NC][VL];
-    T c[NC], e[NC], e0[NC], nu[NC];
-    T u[NC][KM];
-    int atom[NC];
-    bool live[NC];
-    const T *src[NC];
+    wave_sync();
 #pragma unroll
-    for (int s = 0; s < NC; ++s) {
-        const int ci = s * G + gl;
-        live[s] = ci < nc;
-        int at = ci;
-        if (!a.first) {
-            const int pi = w.par[min(ci / a.q, KX - 1)];
-            at = pi * a.q + ci % a.q;
-        }
-        atom[s] = live[s] ? at : INT_MAX;
-        src[s] = (const T *)a.v + (int64_t)(live[s] ? at : 0) * (GRAM ? lp : LP);
+    for (int s = 0; s < NC; ++s)
 #pragma unroll
         for (int m = 0; m < KM; ++m) u[s][m] = T(0);
-    }
     T h[NC], ee[NC];
 #pragma unroll
     for (int s = 0; s < NC; ++s) { h[s] = T(0); ee[s] = T(0); }
     if constexpr (!GRAM) {
-        // every slot's vector is requested before any is used
-#pragma unroll
-        for (int s = 0; s < NC; ++s) {
-            if constexpr (sizeof(T) == 4) {
-#pragma unroll
-                for (int j = 0; j < LP; j += 4) {
-                    const float4 q = *reinterpret_cast<const float4 *>(src[s] + j);
-                    v[s][j] = q.x; v[s][j + 1] = q.y; v[s][j + 2] = q.z; v[s][j + 3] = q.w;
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < LP; j += 2) {
-                    const double2 q = *reinterpret_cast<const double2 *>(src[s] + j);
-                    v[s][j] = q.x; v[s][j + 1] = q.y;
-                }
-            }
-        }
 #pragma unroll
         for (int j = 0; j < LP; ++j) {
             const T sw = w.sqw[j], yh = w.yhat[j];
@@ -548,11 +567,13 @@ void k_omp_scale(ScaleArgs a)
         if (!(ee[s] > T(0))) live[s] = false;  // an effective column of zero is never picked
     }
 
-    // ---- OMP iterations (Algorithm 1), unrolled so u / x / z stay in VGPRs
+    // ---- OMP iterations (Algorithm 1), unrolled so u and x stay in VGPRs
     T x[KM];          // column gl of L^{-1}
-    T z[KM];          // L^{-1} A_Omega^T y (group-uniform)
 #pragma unroll
-    for (int m = 0; m < KM; ++m) { x[m] = T(0); z[m] = T(0); }
+    for (int m = 0; m < KM; ++m) x[m] = T(0);
+    // alpha_gl = sum_i (L^{-1})_{i,gl} z_i with z = L^{-1} A_Omega^T y, and the
+    // squared norm of column gl of L^{-1}, accumulated as the rows appear
+    T al = 0, col2 = 0;
     bool active = K > 0;
     int nsel = 0;
     T trg = 0;        // trace of the support's Gram matrix
@@ -567,7 +588,7 @@ void k_omp_scale(ScaleArgs a)
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             const T sc = live[s] ? fabs(c[s]) * nu[s] : T(-1);
-            const bool up = sc > best;
+            const bool up = (sc > best) | ((sc == best) & (atom[s] < bidx));
             best = up ? sc : best;
             bidx = up ? atom[s] : bidx;
         }
@@ -637,15 +658,42 @@ void k_omp_scale(ScaleArgs a)
         const T inv = act ? fast_rcp(lnn) : T(0);
         const T zn = ck * inv;
         const int kb = act ? bidx : INT_MAX;
+        // Gram column <a_i, a_k> of every candidate; the selected vector is
+        // read in chunks, the next chunk requested before the current one is
+        // used, so that few registers hold it at a time
+        T gcol[NC];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) gcol[s] = T(0);
+        if constexpr (!GRAM) {
+            constexpr int CH = LP <= 16 ? LP : 8;
+            T cur[CH], nxt[CH];
+            const T *vkp = w.vk;
+#pragma unroll
+            for (int j = 0; j < CH; ++j) cur[j] = vkp[j];
+#pragma unroll
+            for (int j0 = 0; j0 < LP; j0 += CH) {
+                if (j0 + CH < LP) {
+                    // the address of the next chunk is made to depend on the
+                    // sums so far, so the compiler cannot request it earlier
+                    asm volatile("" : "+v"(vkp) : "v"(gcol[0]));
+#pragma unroll
+                    for (int j = 0; j < CH; ++j) nxt[j] = vkp[j0 + CH + j];
+                }
+#pragma unroll
+                for (int s = 0; s < NC; ++s)
+#pragma unroll
+                    for (int j = 0; j < CH; ++j) gcol[s] += v[s][j0 + j] * cur[j];
+#pragma unroll
+                for (int j = 0; j < CH; ++j) cur[j] = nxt[j];
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < NC; ++s)
+                if (act & (atom[s] != INT_MAX)) gcol[s] = ((const T *)a.gram)[(int64_t)bidx * a.t + atom[s]];
+        }
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
-            T g = 0;
-            if constexpr (!GRAM) {
-#pragma unroll
-                for (int j = 0; j < LP; ++j) g += v[s][j] * w.vk[j];
-            } else {
-                if (act & (atom[s] != INT_MAX)) g = ((const T *)a.gram)[(int64_t)bidx * a.t + atom[s]];
-            }
+            const T g = gcol[s];
             T dot = 0;
 #pragma unroll
             for (int m = 0; m < n; ++m) dot += w.uk[m] * u[s][m];
@@ -660,7 +708,8 @@ void k_omp_scale(ScaleArgs a)
 #pragma unroll
         for (int m = 0; m < n; ++m) xd -= w.uk[m] * x[m];
         x[n] = xd * inv;
-        z[n] = zn;
+        al += x[n] * zn;
+        col2 += x[n] * x[n];
         if (act & (gl == 0)) w.sup[n] = bidx;
         trg += act ? e0k : T(0);
         const T lv = act ? lnn : (n == 0 ? T(1) : lmax);
@@ -679,13 +728,7 @@ void k_omp_scale(ScaleArgs a)
             for (int i = gl; i < a.sup_count; i += G) sup_out[i] = i < nsel ? w.sup[i] : -1;
         return;
     }
-    // coefficients: alpha_j = sum_i (L^{-1})_{ij} z_i, lane j of the group
-    T al = 0, col2 = 0;
-#pragma unroll
-    for (int i = 0; i < KM; ++i) {
-        al += x[i] * z[i];
-        col2 += x[i] * x[i];
-    }
+    // coefficients: lane j of the group holds alpha_j
     if (gl < nsel) w.alpha[gl] = al;
     if constexpr (sizeof(T) == 4) {
         // FP64 back-substitution when the FP32 normal equations would miss the
