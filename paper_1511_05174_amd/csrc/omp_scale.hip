@@ -5,9 +5,9 @@
 
 namespace cspd {
 
-cspd_status dispatch_scale_f32_k4(const ScaleArgs &, int, int, int, bool, hipStream_t);
-cspd_status dispatch_scale_f32_k8(const ScaleArgs &, int, int, int, bool, hipStream_t);
-cspd_status dispatch_scale_f32_k16(const ScaleArgs &, int, int, int, bool, hipStream_t);
+cspd_status dispatch_scale_f32_k4(const ScaleArgs &, int, int, int, bool, bool, hipStream_t);
+cspd_status dispatch_scale_f32_k8(const ScaleArgs &, int, int, int, bool, bool, hipStream_t);
+cspd_status dispatch_scale_f32_k16(const ScaleArgs &, int, int, int, bool, bool, hipStream_t);
 cspd_status dispatch_scale_f64_k16(const ScaleArgs &, int, int, int, bool, hipStream_t);
 
 namespace {
@@ -64,9 +64,13 @@ cspd_status launch_scale(int dtype, const ScaleArgs &a, int max_cand, bool gram,
     const int k = a.sup_count < kMaxK ? a.sup_count : kMaxK;
     const int kreq = a.kvec ? k : (a.kuni < k ? a.kuni : k);
     if (dtype == CSPD_F64) return dispatch_scale_f64_k16(a, a.lp, nc, ppw, gram, st);
-    if (kreq <= 4) return dispatch_scale_f32_k4(a, a.lp, nc, ppw, gram, st);
-    if (kreq <= 8) return dispatch_scale_f32_k8(a, a.lp, nc, ppw, gram, st);
-    return dispatch_scale_f32_k16(a, a.lp, nc, ppw, gram, st);
+    // up to 32 candidates of length <= 64: each patch's candidate Gram matrix
+    // on the matrix cores, two patches per wavefront
+    const bool mg = !gram && max_cand <= 32 && a.lp <= 64;
+    if (mg) { nc = 1; ppw = 2; }
+    if (kreq <= 4) return dispatch_scale_f32_k4(a, a.lp, nc, ppw, gram, mg, st);
+    if (kreq <= 8) return dispatch_scale_f32_k8(a, a.lp, nc, ppw, gram, mg, st);
+    return dispatch_scale_f32_k16(a, a.lp, nc, ppw, gram, mg, st);
 }
 
 }  // namespace cspd

@@ -3,10 +3,16 @@
 
 namespace cspd {
 
-cspd_status dispatch_scale_f32_k4(const ScaleArgs &a, int lp, int nc, int ppw, bool gram,
+cspd_status dispatch_scale_f32_k4(const ScaleArgs &a, int lp, int nc, int ppw, bool gram, bool mg,
                                      hipStream_t st)
 {
     using namespace scale_impl;
+    if (mg) {
+        if (lp == 16) return launch_one<float, 16, 1, 2, 4, false, true>(a, st);
+        if (lp == 32) return launch_one<float, 32, 1, 2, 4, false, true>(a, st);
+        if (lp == 64) return launch_one<float, 64, 1, 2, 4, false, true>(a, st);
+        return CSPD_E_UNSUPPORTED;
+    }
     if (gram) {
         switch (nc) {
             case 1: return launch_one<float, 0, 1, 1, 4, true>(a, st);

@@ -329,13 +329,16 @@ __device__ __attribute__((noinline)) void gram64_chol(const T *v, int lp, int l,
     wave_sync();
 }
 
-template <typename T, int LP, int NC, int PPW, int KM, bool GRAM>
-__global__ __launch_bounds__(64 * W) 
+template <typename T, int LP, int NC, int PPW, int KM, bool GRAM, bool MG>
+__global__ __launch_bounds__(64 * W)
 void k_omp_scale(ScaleArgs a)
 {
+    static_assert(!MG || (sizeof(T) == 4 && NC == 1 && PPW == 2 && !GRAM && LP <= 64),
+                  "matrix-core Gram: FP32, one slot, two patches per wavefront");
     constexpr int G = 64 / PPW;
     constexpr int LPA = GRAM ? LP_GRAM : LP;
-    constexpr int VL = GRAM ? 1 : LP;       // per-slot vector registers
+    constexpr int VL = (GRAM || MG) ? 1 : LP;   // per-slot vector registers
+    constexpr int LH = MG ? LP / 2 : 1;         // coordinates per lane and patch (matrix-core Gram)
     __shared__ GroupLds<T, LPA, KM> lds[W * PPW];
     __shared__ double lds64[W][KX * KX + 4 * KX];
     extern __shared__ double dyn_lds[];     // block-fold staging (fold_lds_bytes)
@@ -367,9 +370,34 @@ void k_omp_scale(ScaleArgs a)
     int atom[NC];
     bool live[NC];
     const T *src[NC];
+    // Matrix-core Gram: lane l holds candidate l % 32 of both patches of the
+    // wavefront, coordinates [(l / 32) LH, (l / 32 + 1) LH) of each (the
+    // MFMA's two k rows split the coordinates in halves).
+    T vm[MG ? 2 : 1][LH];
+    bool livep[2] = {false, false};
     int nc = 0;
     auto candidates = [&](int ncand, int pvv) {
         nc = ncand;
+        if constexpr (MG) {
+            const int hh = lane >> 5;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int ncp = __builtin_amdgcn_readlane(ncand, p * 32);
+                livep[p] = gl < ncp;
+                int at = gl;
+                if (!a.first) {
+                    const int pj = livep[p] ? gl / a.q : 0;
+                    const int pi = __shfl(pvv, p * 32 + pj, 64);
+                    at = pi * a.q + gl % a.q;
+                }
+                const T *sp = (const T *)a.v + (int64_t)(livep[p] ? at : 0) * LP + hh * LH;
+#pragma unroll
+                for (int j = 0; j < LH; j += 4) {
+                    const float4 q = *reinterpret_cast<const float4 *>(sp + j);
+                    vm[p][j] = q.x; vm[p][j + 1] = q.y; vm[p][j + 2] = q.z; vm[p][j + 3] = q.w;
+                }
+            }
+        }
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             const int ci = s * G + gl;
@@ -384,7 +412,7 @@ void k_omp_scale(ScaleArgs a)
             atom[s] = live[s] ? at : INT_MAX;
             src[s] = (const T *)a.v + (int64_t)(live[s] ? at : 0) * (GRAM ? lp : LP);
         }
-        if constexpr (!GRAM) {
+        if constexpr (!GRAM && !MG) {
 #pragma unroll
             for (int s = 0; s < NC; ++s) {
                 if constexpr (sizeof(T) == 4) {
@@ -533,7 +561,56 @@ void k_omp_scale(ScaleArgs a)
     T h[NC], ee[NC];
 #pragma unroll
     for (int s = 0; s < NC; ++s) { h[s] = T(0); ee[s] = T(0); }
-    if constexpr (!GRAM) {
+    typedef float gram_t __attribute__((ext_vector_type(16)));
+    gram_t gm[2];
+    if constexpr (MG) {
+        // weighted candidates, their correlations with y-hat and squared norms
+        // (each lane sums its half of the coordinates, the halves are added)
+        const int hh = lane >> 5;
+        T hf[2], ef[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const GroupLds<T, LPA, KM> &wp = lds[wv * PPW + p];
+            T hs = 0, es = 0;
+#pragma unroll
+            for (int j = 0; j < LH; ++j) {
+                const T sw = wp.sqw[hh * LH + j], yh = wp.yhat[hh * LH + j];
+                const T xv = vm[p][j] * sw;
+                const T x = livep[p] ? xv : T(0);
+                vm[p][j] = x;
+                hs += x * yh;
+                es += x * x;
+            }
+            T lo, hi;
+            swap_pair<32>(hs, lo, hi);
+            hf[p] = lo + hi;
+            swap_pair<32>(es, lo, hi);
+            ef[p] = lo + hi;
+        }
+        h[0] = gi ? hf[1] : hf[0];
+        ee[0] = gi ? ef[1] : ef[0];
+        // Gram matrices of both patches' candidates on the matrix cores:
+        // lane l ends with column l % 32, rows 8 (r / 4) + 4 (l / 32) + r % 4
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) gm[p][r] = 0.f;
+#pragma unroll
+        for (int j = 0; j < LH; ++j) {
+            gm[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[0][j], vm[0][j], gm[0], 0, 0, 0);
+            gm[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[1][j], vm[1][j], gm[1], 0, 0, 0);
+        }
+        // keep the Gram entries in ordinary VGPRs, where a row can be picked
+        // by a wavefront-uniform register index
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                float t = gm[p][r];
+                asm volatile("" : "+v"(t));
+                gm[p][r] = t;
+            }
+    } else if constexpr (!GRAM) {
 #pragma unroll
         for (int j = 0; j < LP; ++j) {
             const T sw = w.sqw[j], yh = w.yhat[j];
@@ -597,10 +674,13 @@ void k_omp_scale(ScaleArgs a)
         group_argmax<G>(best, bidx);
         act = act && best >= T(0);          // candidates exhausted otherwise
         // the owning lane publishes its vector, its u row and its scalars
+        bool selected = false;
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
-            if (act && live[s] && atom[s] == bidx) {
-                if constexpr (!GRAM) {
+            const bool sel = act && live[s] && atom[s] == bidx;
+            selected = selected || sel;
+            if (sel) {
+                if constexpr (!GRAM && !MG) {
 #pragma unroll
                     for (int j = 0; j < LP; ++j) w.vk[j] = v[s][j];
                 }
@@ -664,7 +744,23 @@ void k_omp_scale(ScaleArgs a)
         T gcol[NC];
 #pragma unroll
         for (int s = 0; s < NC; ++s) gcol[s] = T(0);
-        if constexpr (!GRAM) {
+        if constexpr (MG) {
+            // the selected candidate's slot in each patch, then its row of the
+            // Gram matrix (symmetric): row k, column gl lives in lane
+            // gl + 32 ((k / 4) % 2), register 4 (k / 8) + k % 4
+            const unsigned long long own = __ballot(selected);
+            const unsigned o0 = (unsigned)own, o1 = (unsigned)(own >> 32);
+            const int k0 = o0 ? __builtin_ctz(o0) : 0;
+            const int k1 = o1 ? __builtin_ctz(o1) : 0;
+            const float x0 = gm[0][4 * (k0 >> 3) + (k0 & 3)];
+            const float x1 = gm[1][4 * (k1 >> 3) + (k1 & 3)];
+            float lo0, hi0, lo1, hi1;
+            swap_pair<32>(x0, lo0, hi0);
+            swap_pair<32>(x1, lo1, hi1);
+            const float g0 = ((k0 >> 2) & 1) ? hi0 : lo0;
+            const float g1 = ((k1 >> 2) & 1) ? hi1 : lo1;
+            gcol[0] = gi ? g1 : g0;
+        } else if constexpr (!GRAM) {
             constexpr int CH = LP <= 16 ? LP : 8;
             T cur[CH], nxt[CH];
             const T *vkp = w.vk;
@@ -789,20 +885,21 @@ inline size_t fold_lds_bytes(const ScaleArgs &a, size_t elem, int ppw)
     return elem * (size_t)(W * ppw * 2 * a.n) + sizeof(int) * (size_t)(W * (a.l + 1 + a.n));
 }
 
-template <typename T, int LP, int NC, int PPW, int KM, bool GRAM>
+template <typename T, int LP, int NC, int PPW, int KM, bool GRAM, bool MG = false>
 cspd_status launch_one(const ScaleArgs &a, hipStream_t st)
 {
     const int64_t waves = (a.b + PPW - 1) / PPW;
     const unsigned grid = (unsigned)((waves + W - 1) / W);
     char label[112];
+    const char *mode = GRAM ? "gram" : (MG ? "mfma" : "vec");
     if (a.first && a.last)
         snprintf(label, sizeof(label), "omp_scale<%s,%s,lp%d,nc%d,ppw%d,k%d>:full", sizeof(T) == 8 ? "f64" : "f32",
-                 GRAM ? "gram" : "vec", GRAM ? a.lp : LP, NC, PPW, KM);
+                 mode, GRAM ? a.lp : LP, NC, PPW, KM);
     else
         snprintf(label, sizeof(label), "omp_scale<%s,%s,lp%d,nc%d,ppw%d,k%d>:s%d", sizeof(T) == 8 ? "f64" : "f32",
-                 GRAM ? "gram" : "vec", GRAM ? a.lp : LP, NC, PPW, KM, a.scale);
+                 mode, GRAM ? a.lp : LP, NC, PPW, KM, a.scale);
     ProfileToken *tok = profile_begin(label, st);
-    hipLaunchKernelGGL((k_omp_scale<T, LP, NC, PPW, KM, GRAM>), dim3(grid), dim3(64 * W),
+    hipLaunchKernelGGL((k_omp_scale<T, LP, NC, PPW, KM, GRAM, MG>), dim3(grid), dim3(64 * W),
                        fold_lds_bytes(a, sizeof(T), PPW), st, a);
     profile_end(tok, st);
     CSPD_HIP_CHECK(hipGetLastError());
