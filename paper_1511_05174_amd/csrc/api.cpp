@@ -328,7 +328,8 @@ cspd_status cspd_omp_cross_scale(cspd_plan_t p, int64_t B, const void *y, const 
             a.coef_out = coef;
             a.xhat = xhat;
         }
-        rc = launch_scale(p->dtype, a, cand[s], gram[s], st);
+        rc = s == 0 ? launch_first_mfma(p->dtype, a, st) : CSPD_E_UNSUPPORTED;
+        if (rc == CSPD_E_UNSUPPORTED) rc = launch_scale(p->dtype, a, cand[s], gram[s], st);
     }
     (void)hipFreeAsync(work, st);
     return rc;

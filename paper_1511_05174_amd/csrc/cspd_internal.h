@@ -117,6 +117,10 @@ struct ScaleArgs {
 cspd_status launch_scale(int dtype, const ScaleArgs &a, int max_candidates, bool gram_mode,
                          hipStream_t stream);
 
+// First scale of a cross-scale call on the matrix cores (shared dictionary,
+// 16 patches per wavefront); CSPD_E_UNSUPPORTED when the shape does not fit.
+cspd_status launch_first_mfma(int dtype, const ScaleArgs &a, hipStream_t stream);
+
 // Full-dictionary proxy on matrix cores (large T).
 cspd_status launch_full_mfma(const cspd_plan_s *p, int64_t b, const void *y, const uint8_t *mask,
                              const int *kvec, int kuni, int *support, void *coef, int *k_used,

@@ -827,11 +827,57 @@ void k_omp_scale(ScaleArgs a)
     // coefficients: lane j of the group holds alpha_j
     if (gl < nsel) w.alpha[gl] = al;
     if constexpr (sizeof(T) == 4) {
-        // FP64 back-substitution when the FP32 normal equations would miss the
-        // coefficient tolerance: their error grows like kappa(G) * 2^-24, and
-        // tr(G) tr(G^{-1}) / n estimates kappa(G) within a factor n.
+        // One step of mixed-precision refinement.  The FP32 normal equations
+        // leave an error of about kappa(G) 2^-24; the residual of the normal
+        // equations, r = A_Omega^T (y-hat - A_Omega alpha), is formed in FP64
+        // from the stored vectors, and the correction G^{-1} r = L^{-T} L^{-1} r
+        // goes through the FP32 factor (lane j holds column j of L^{-1}),
+        // which leaves an error of about (kappa(G) 2^-24)^2.
+        wave_sync();
+        {
+            double part[KM];
+            T alv[KM];
+            int sid[KM];
+#pragma unroll
+            for (int i = 0; i < KM; ++i) {
+                const bool in = i < nsel;
+                part[i] = 0.0;
+                sid[i] = in ? w.sup[i] : 0;
+                alv[i] = in ? w.alpha[i] : T(0);
+            }
+            const T *vv = (const T *)a.v;
+            for (int t = gl; t < a.l; t += G) {
+                const double sq = (double)w.sqw[t];
+                double res = (double)w.yhat[t];
+                double av[KM];
+#pragma unroll
+                for (int i = 0; i < KM; ++i) {
+                    av[i] = (double)vv[(int64_t)sid[i] * a.lp + t] * sq;
+                    res -= (double)alv[i] * av[i];
+                }
+#pragma unroll
+                for (int i = 0; i < KM; ++i) part[i] += av[i] * res;
+            }
+            T rme = 0;
+#pragma unroll
+            for (int i = 0; i < KM; ++i) {
+                const double ri = group_sum<G>(part[i]);
+                rme = gl == i ? (T)ri : rme;
+            }
+            T dl = 0;
+#pragma unroll
+            for (int m = 0; m < KM; ++m) {
+                const T wm = group_sum<G>(x[m] * rme);
+                dl += x[m] * wm;
+            }
+            al += dl;
+        }
+        if (gl < nsel) w.alpha[gl] = al;
+        // FP64 back-substitution when even the refined FP32 solution would miss
+        // the coefficient tolerance (1e-5 relative): tr(G) tr(G^{-1}) / n
+        // estimates kappa(G) within a factor n.
         const T trinv = group_sum<G>(col2);
-        const bool ill = nsel > 1 && (double)trg * (double)trinv / nsel > 1e2;
+        const bool ill = nsel > 1 && (double)trg * (double)trinv / nsel > 1e4;
         const unsigned long long mi = __ballot(ill);
         wave_sync();
         if (mi) {

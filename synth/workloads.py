@@ -107,7 +107,17 @@ def gaussian_dict(rng, t: int, n: int) -> np.ndarray:
     return unit_columns(rng.standard_normal((t, n)))
 
 
-def child_dict(rng, parent: np.ndarray, up_map: np.ndarray, q: int) -> np.ndarray:
+# Scale of the fine detail that children add to their upsampled parent.  At
+# 0.5 the detail carries about a sixth of a child's energy (cosine between a
+# child and its upsampled parent about 0.92): children resemble their parents,
+# as the learned fine atoms of Section III do.  (At 1.0 the detail is as
+# strong as the parent part and the coarse search under a pixel mask loses
+# its parents much more often.)
+CHILD_DETAIL = 0.5
+
+
+def child_dict(rng, parent: np.ndarray, up_map: np.ndarray, q: int,
+               detail: float = CHILD_DETAIL) -> np.ndarray:
     """Children that look like their upsampled parent plus detail that the box
     down-sampler removes, so W d_child is exactly proportional to d_parent.
 
@@ -122,7 +132,7 @@ def child_dict(rng, parent: np.ndarray, up_map: np.ndarray, q: int) -> np.ndarra
     block_sum = np.zeros((t_c * q, n_c))
     np.add.at(block_sum.T, up_map, g.T)
     g -= (block_sum / counts)[:, up_map]
-    d = np.repeat(up, q, axis=0) + g / np.sqrt(n_f)
+    d = np.repeat(up, q, axis=0) + detail * g / np.sqrt(n_f)
     return unit_columns(d)
 
 
