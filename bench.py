@@ -61,11 +61,17 @@ def kernel_flops(w, k_scales):
     return out
 
 
+COPY_PROBE_FLOATS = 64 << 20   # 256 MiB read and written by the calibration pass
+
+
 def kernel_source_hash():
+    """Hash of the sources of the cross-scale kernels (the first-scale and
+    per-scale kernels and what they include); a traffic summary taken on other
+    sources is not used."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1511_05174_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
+        if name.startswith(("omp_scale", "omp_first", "cspd_internal")) and name.endswith((".hip", ".h")):
             h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 
@@ -143,6 +149,78 @@ def serve_phase(cspd, plan, w, ks, gpu_rate, jobs=300, seed=11):
             "slots": 4, "hbm_budget_bytes": 8 << 30, "note": "host buffers in pageable memory; latency includes PCIe copies"}
 
 
+def traffic_probe(workload: str, steps: int = 3):
+    """A plain elementwise pass over a buffer of known size, then a few
+    cross-scale steps: run under rocprofv3 --pmc FETCH_SIZE, and again under
+    WRITE_SIZE, then summarize both with --traffic-summarize."""
+    import torch
+
+    import synth
+    from paper_1511_05174_amd import cspd
+
+    dev = torch.device("cuda", 0)
+    n = COPY_PROBE_FLOATS
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)      # reads 4 n bytes, writes 4 n bytes
+    torch.cuda.synchronize()
+    w = synth.make(workload)
+    ks = list(w.k_scales)
+    plan = cspd.plan_from_workload(w)
+    ndt = np.float64 if w.dtype == "f64" else np.float32
+    y = torch.from_numpy(np.ascontiguousarray(w.y.astype(ndt))).to(dev)
+    mask = None if w.mask is None else torch.from_numpy(w.mask).to(dev)
+    kf = None if w.k_fine is None else torch.from_numpy(w.k_fine.astype(np.int32)).to(dev)
+    for _ in range(steps):
+        cspd.cspd_omp_cross_scale(plan, y, mask, ks[:-1], kf, ks[-1])
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": workload, "copy_floats": n, "steps": steps, "scales": w.n_scales}))
+
+
+def traffic_summarize(fetch_db: str, write_db: str, workload: str, command: str):
+    """HBM bytes per launch of each scale's kernel from the two counter runs
+    of --traffic-probe, each counter scaled by what it reads for the plain
+    elementwise pass (4 n bytes fetched and 4 n written)."""
+    import sqlite3
+
+    import synth
+
+    def dispatches(db, counter):
+        c = sqlite3.connect(db)
+        rows = c.execute("select dispatch_id, kernel_name, sum(value) from counters_collection "
+                         "where counter_name = ? group by dispatch_id order by dispatch_id",
+                         (counter,)).fetchall()
+        return [(k, float(v)) for _, k, v in rows]
+
+    s_count = synth.make(workload, batch=1).n_scales
+    out = {"workload": workload, "source_hash": kernel_source_hash(), "command": command,
+           "copy_bytes_each_way": 4 * COPY_PROBE_FLOATS, "kernels": {}}
+    for counter, key in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        rows = dispatches(fetch_db if key == "fetch" else write_db, counter)
+        copies = [v for k, v in rows if "elementwise" in k]
+        omp = [(k, v) for k, v in rows if "k_omp_" in k]
+        copy_kib = float(np.median(copies))
+        factor = 4 * COPY_PROBE_FLOATS / (copy_kib * 1024.0)
+        out[f"{key}_factor"] = factor
+        out[f"copy_{key}_kib"] = copy_kib
+        for i, (k, v) in enumerate(omp):
+            role = f"s{i % s_count}" if s_count > 1 else "full"
+            ent = out["kernels"].setdefault(role, {"name": k.split("(")[0], f"{key}_kib": []})
+            ent.setdefault(f"{key}_kib", []).append(v)
+            out[f"{key}_factor"] = factor
+    for role, ent in out["kernels"].items():
+        fk = float(np.median(ent["fetch_kib"]))
+        wk = float(np.median(ent["write_kib"]))
+        ent["fetch_kib"] = fk
+        ent["write_kib"] = wk
+        ent["hbm_bytes_per_launch"] = fk * 1024.0 * out["fetch_factor"] + wk * 1024.0 * out["write_factor"]
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,7 +233,20 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=65536,
                     help="patches of the workload the oracle is timed on")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="known-size elementwise pass plus cross-scale steps, for rocprofv3 --pmc")
+    ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write profiles/traffic_<workload>.json from the two counter runs")
+    ap.add_argument("--traffic-command", default="",
+                    help="the commands that produced the counter runs (recorded in the summary)")
     args = ap.parse_args()
+    if args.traffic_probe:
+        traffic_probe(args.workload)
+        return
+    if args.traffic_summarize:
+        traffic_summarize(args.traffic_summarize[0], args.traffic_summarize[1], args.workload,
+                          args.traffic_command)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(every patch is independent: the batch would be split across GPUs, see DESIGN.md)",
@@ -223,7 +314,7 @@ def main():
     traffic = load_traffic(args.workload, role, 1)
     peak = PEAK_FP32_VECTOR_TFLOPS if w.dtype == "f32" else PEAK_FP64_VECTOR_TFLOPS
     roofline = {
-        "bound": "alu",
+        "bound": "mfma" if "mfma" in label else "alu",
         "achieved": achieved,
         "peak": peak,
         "unit": "TFLOP/s",

@@ -217,3 +217,34 @@ def test_c4_full_mfma_uneven_k():
 
 def test_c5c_full_mfma_lightfield():
     check_full(synth.make("c5c", batch=515))
+
+
+# ------------------------------------ first scale on the matrix cores (GEMM)
+@pytest.mark.parametrize("t0,k_low", [(32, 3), (64, 8), (128, 5)])
+def test_first_scale_mask_shapes(t0, k_low):
+    """Coarse dictionaries of one, two and four 32-atom tiles, sparsity up to 8."""
+    w = synth.custom([16, 64], [t0, t0 * 4], batch=1029, seed=11 + t0, phi_kind="mask",
+                     k_scales=[k_low, 6], sigma=0.005, dict_kind="model", dtype="f32")
+    check_cross(w)
+
+
+def test_first_scale_dense_operator():
+    """Shared Gaussian operator of 24 rows: the coarse candidates are the
+    columns of Phi U D_0 (length 24), on the matrix-core first scale."""
+    w = synth.custom([16, 64], [64, 256], batch=777, seed=21, phi_kind="dense", m=24,
+                     k_scales=[4, 6], sigma=0.005, dict_kind="model", dtype="f32")
+    check_cross(w)
+
+
+def test_first_scale_duplicate_atoms():
+    """Duplicated and negated coarse atoms: exact ties go to the lower index
+    and the copy never joins the support (it is dependent)."""
+    w = synth.custom([16, 64], [32, 128], batch=515, seed=23, phi_kind="mask",
+                     k_scales=[6, 6], sigma=0.005, dict_kind="model", dtype="f32")
+    d0 = w.dicts[0]
+    d0[1] = d0[0]
+    d0[5] = -d0[4]
+    out, _ = check_cross(w)
+    for b in range(w.batch):
+        s = set(out["support_coarse"][b, :6].tolist())
+        assert not ({0, 1} <= s) and not ({4, 5} <= s)
