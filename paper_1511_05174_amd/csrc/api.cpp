@@ -181,7 +181,7 @@ cspd_status cspd_plan(const cspd_plan_desc *d, cspd_plan_t *out)
     p->phi_kind = d->phi_kind;
     p->dtype = d->dtype;
     p->corr_mode = d->corr_mode;
-    p->rescore_m = d->rescore_m ? d->rescore_m : 8;
+    p->rescore_m = d->rescore_m ? d->rescore_m : 16;
     p->k_max = d->k_max;
     p->device = d->device;
     hipStream_t st;
@@ -242,7 +242,9 @@ cspd_status cspd_omp_full(cspd_plan_t p, int64_t B, const void *y, const uint8_t
     const int cand = sc.t;
     cspd_status rc;
     const bool fits = scale_vec_fits(sc.lp, cand, p->dtype == CSPD_F64);
-    if (fits || sc.gram) rc = launch_scale(p->dtype, a, cand, !fits, st);
+    // a reduced-precision proxy runs on the full-search kernel
+    const bool lowp = p->corr_mode != CSPD_CORR_NATIVE && sc.v_lo != nullptr;
+    if ((fits || sc.gram) && !lowp) rc = launch_scale(p->dtype, a, cand, !fits, st);
     else rc = launch_full_mfma(p, B, y, mask, k, k_uniform, support, coef, k_used, xhat, st);
     if (rc == CSPD_E_UNSUPPORTED && cspd::g_err.empty())
         return set_error(rc, "no full-search kernel for T = %d, length %d", sc.t, sc.l);

@@ -16,6 +16,15 @@
 // The MFMA operands use a coordinate permutation shared by both sides: lane
 // half h of an operand supplies coordinate h*LP/2 + s at step s, so every lane
 // reads a contiguous half row of A and of the residual.
+//
+// Reduced-precision proxy (a precision option, not in the paper): the proxy
+// tiles run on bf16 or fp16 matrix cores (v_mfma_f32_32x32x16_*, FP32
+// accumulation) from the plan's 16-bit copy of A and a 16-bit copy of the
+// residual (scaled per patch to a maximum of 1, which leaves the argmax
+// unchanged and keeps fp16 clear of underflow).  Each of the eight lanes that
+// serve a patch keeps its RR best scores; those 8 RR candidates are re-scored
+// with exact FP32 correlations and norms, and the argmax is taken over the
+// re-scored values.  Everything after the pick stays FP32.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -27,6 +36,10 @@ namespace cspd {
 namespace full_impl {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+enum { CM_NATIVE = 0, CM_BF16 = 1, CM_F16 = 2 };
 
 constexpr int P = 32;          // patches per workgroup
 constexpr int NW = 4;          // wavefronts per workgroup
@@ -54,6 +67,7 @@ struct FullArgs {
     int *k_used;
     float *xhat;
     const float *d_high;       // T x n
+    const uint16_t *v_lo;      // t x lp, bf16 or fp16 copy of v (reduced-precision proxy)
 };
 
 __device__ __forceinline__ void sync() { __syncthreads(); }
@@ -72,7 +86,63 @@ __device__ __forceinline__ bool beats(float s1, int i1, float s0, int i0)
     return (s1 > s0) | ((s1 == s0) & (i1 < i0));
 }
 
-template <int LP, int KM, bool MASK>
+// Eight 16-bit values from eight floats (round to nearest even).
+template <int CM>
+__device__ __forceinline__ void pack8(const float *f, unsigned (&w)[4])
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        unsigned lo, hi;
+        if constexpr (CM == CM_BF16) {
+            unsigned u0 = __float_as_uint(f[2 * i]), u1 = __float_as_uint(f[2 * i + 1]);
+            u0 += 0x7fffu + ((u0 >> 16) & 1u);
+            u1 += 0x7fffu + ((u1 >> 16) & 1u);
+            lo = u0 >> 16;
+            hi = u1 >> 16;
+        } else {
+            const _Float16 h0 = (_Float16)f[2 * i], h1 = (_Float16)f[2 * i + 1];
+            lo = *reinterpret_cast<const unsigned short *>(&h0);
+            hi = *reinterpret_cast<const unsigned short *>(&h1);
+        }
+        w[i] = lo | (hi << 16);
+    }
+}
+
+template <int CM>
+__device__ __forceinline__ f32x16 mfma16(const unsigned (&x)[4], const unsigned (&y)[4], f32x16 acc)
+{
+    if constexpr (CM == CM_BF16) {
+        bf16x8 xa, ya;
+        __builtin_memcpy(&xa, x, 16);
+        __builtin_memcpy(&ya, y, 16);
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, ya, acc, 0, 0, 0);
+    } else {
+        f16x8 xa, ya;
+        __builtin_memcpy(&xa, x, 16);
+        __builtin_memcpy(&ya, y, 16);
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(xa, ya, acc, 0, 0, 0);
+    }
+}
+
+// Best (score, atom) over the eight consecutive lanes of a patch.
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(float &s, int &i)
+{
+    const float os = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), CTRL, 0xF, 0xF, false));
+    const int oi = __builtin_amdgcn_mov_dpp(i, CTRL, 0xF, 0xF, false);
+    const bool take = beats(os, oi, s, i);
+    s = take ? os : s;
+    i = take ? oi : i;
+}
+
+__device__ __forceinline__ void argmax8(float &s, int &i)
+{
+    argmax_dpp<0xB1>(s, i);
+    argmax_dpp<0x4E>(s, i);
+    argmax_dpp<0x141>(s, i);
+}
+
+template <int LP, int KM, bool MASK, int CM, int RR>
 __global__ __launch_bounds__(64 * NW) void k_omp_full(FullArgs a)
 {
     constexpr int HL = LP / 2;            // coordinates per operand half
@@ -91,6 +161,7 @@ __global__ __launch_bounds__(64 * NW) void k_omp_full(FullArgs a)
     __shared__ float s_al[P][KM];
     __shared__ int s_sup[P][KM];
     __shared__ int s_n[P], s_kk[P], s_live[P];
+    __shared__ int s_cand[CM != CM_NATIVE ? P : 1][CM != CM_NATIVE ? NW * 2 * RR : 1];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -160,22 +231,54 @@ __global__ __launch_bounds__(64 * NW) void k_omp_full(FullArgs a)
         }
         float bs = -1.f;
         int bi = INT_MAX;
+        float bs2 = -1.f;          // second best of this lane (RR == 2)
+        int bi2 = INT_MAX;
         const bool plive = s_live[pp] != 0;
+        unsigned rlo[CM != CM_NATIVE ? HL / 8 : 1][4];
+        if constexpr (CM != CM_NATIVE) {
+            // 16-bit residual half of the lane's patch, scaled to max |r| = 1
+            float mx = 0.f;
+#pragma unroll
+            for (int s = 0; s < HL; ++s) mx = fmaxf(mx, fabsf(rb[s]));
+            {
+                auto rs = __builtin_amdgcn_permlane32_swap(__float_as_int(mx), __float_as_int(mx), false, false);
+                mx = fmaxf(__int_as_float(rs[0]), __int_as_float(rs[1]));
+            }
+            const float sc = mx > 0.f ? 1.f / mx : 0.f;
+#pragma unroll
+            for (int g = 0; g < HL / 8; ++g) {
+                float f[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) f[j] = rb[8 * g + j] * sc;
+                pack8<CM>(f, rlo[g]);
+            }
+        }
         for (int t = wave; t < ntiles; t += NW) {
             const int arow = t * 32 + (lane & 31);
-            const float *src = a.v + (int64_t)(arow < a.t ? arow : 0) * a.lp + h * HL;
-            float ab[HL];
-#pragma unroll
-            for (int s = 0; s < HL; s += 4) {
-                const float4 q = *reinterpret_cast<const float4 *>(src + s);
-                ab[s] = q.x; ab[s + 1] = q.y; ab[s + 2] = q.z; ab[s + 3] = q.w;
-            }
             f32x16 acc = {};
             f32x16 nac = {};
+            if constexpr (CM == CM_NATIVE || MASK) {
+                const float *src = a.v + (int64_t)(arow < a.t ? arow : 0) * a.lp + h * HL;
+                float ab[HL];
 #pragma unroll
-            for (int s = 0; s < HL; ++s) {
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ab[s], rb[s], acc, 0, 0, 0);
-                if constexpr (MASK) nac = __builtin_amdgcn_mfma_f32_32x32x2f32(ab[s] * ab[s], mb[s], nac, 0, 0, 0);
+                for (int s = 0; s < HL; s += 4) {
+                    const float4 q = *reinterpret_cast<const float4 *>(src + s);
+                    ab[s] = q.x; ab[s + 1] = q.y; ab[s + 2] = q.z; ab[s + 3] = q.w;
+                }
+#pragma unroll
+                for (int s = 0; s < HL; ++s) {
+                    if constexpr (CM == CM_NATIVE) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ab[s], rb[s], acc, 0, 0, 0);
+                    if constexpr (MASK) nac = __builtin_amdgcn_mfma_f32_32x32x2f32(ab[s] * ab[s], mb[s], nac, 0, 0, 0);
+                }
+            }
+            if constexpr (CM != CM_NATIVE) {
+                const uint16_t *srl = a.v_lo + (int64_t)(arow < a.t ? arow : 0) * a.lp + h * HL;
+#pragma unroll
+                for (int g = 0; g < HL / 8; ++g) {
+                    const uint4 q = *reinterpret_cast<const uint4 *>(srl + 8 * g);
+                    const unsigned x[4] = {q.x, q.y, q.z, q.w};
+                    acc = mfma16<CM>(x, rlo[g], acc);
+                }
             }
             const unsigned selw = s_sel[pp][t];
 #pragma unroll
@@ -188,9 +291,54 @@ __global__ __launch_bounds__(64 * NW) void k_omp_full(FullArgs a)
                 float sc = fabsf(acc[r]) * inv;
                 const bool ok = plive & (atom < a.t) & (inv > 0.f) & (((selw >> row) & 1u) == 0u);
                 sc = ok ? sc : -1.f;
+                if constexpr (RR == 2) {
+                    const bool up1 = sc > bs, up2 = sc > bs2;
+                    bs2 = up1 ? bs : (up2 ? sc : bs2);
+                    bi2 = up1 ? bi : (up2 ? atom : bi2);
+                }
                 if (sc > bs) { bs = sc; bi = atom; }
             }
         }
+        if constexpr (CM != CM_NATIVE) {
+            // every lane's pool to LDS, then FP32 re-scoring by the update threads
+            int *cd = s_cand[pp] + (wave * 2 + h) * RR;
+            cd[0] = bs >= 0.f ? bi : -1;
+            if constexpr (RR == 2) cd[1] = bs2 >= 0.f ? bi2 : -1;
+            sync();
+            {
+                const int upp = tid / TPP, uss = tid % TPP;
+                float best = -1.f;
+                int bidx = INT_MAX;
+#pragma unroll
+                for (int j = 0; j < RR; ++j) {
+                    const int atom = s_cand[upp][uss * RR + j];
+                    if (atom >= 0) {
+                        const float *ar = a.v + (int64_t)atom * a.lp;
+                        float c = 0.f, nn = 0.f;
+                        for (int q = 0; q < LP; q += 4) {
+                            const float4 v4 = *reinterpret_cast<const float4 *>(ar + q);
+                            const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                c += vv[e] * s_r[upp][q + e];
+                                if constexpr (MASK) nn += vv[e] * vv[e] * s_m[upp][q + e];
+                            }
+                        }
+                        float inv;
+                        if constexpr (MASK) inv = nn > 0.f ? 1.f / sqrtf(nn) : -1.f;
+                        else inv = a.inv_nu[atom];
+                        const float sc = inv > 0.f ? fabsf(c) * inv : -1.f;
+                        if (beats(sc, atom, best, bidx)) { best = sc; bidx = atom; }
+                    }
+                }
+                argmax8(best, bidx);
+                if (uss == 0) {
+                    const bool go = s_live[upp] && best >= 0.f && s_n[upp] < s_kk[upp];
+                    s_k[upp] = go ? bidx : -1;
+                }
+            }
+            sync();
+        } else {
         // lanes l and l + 32 hold the same patch
         {
             auto rs = __builtin_amdgcn_permlane32_swap(__float_as_int(bs), __float_as_int(bs), false, false);
@@ -211,6 +359,7 @@ __global__ __launch_bounds__(64 * NW) void k_omp_full(FullArgs a)
             s_k[tid] = go ? i : -1;
         }
         sync();
+        }
 
         // ---- 2. support merge, projection and residue ------------------------
         const int k = s_k[up];
@@ -328,24 +477,44 @@ __global__ __launch_bounds__(64 * NW) void k_omp_full(FullArgs a)
     }
 }
 
-template <int LP, int KM, bool MASK>
+template <int LP, int KM, bool MASK, int CM, int RR>
 cspd_status launch(const FullArgs &a, hipStream_t st)
 {
     const unsigned grid = (unsigned)((a.b + P - 1) / P);
     char label[96];
-    snprintf(label, sizeof(label), "omp_full_mfma<f32,lp%d,k%d%s>:full", LP, KM, MASK ? ",mask" : "");
+    const char *ty = CM == CM_BF16 ? "bf16" : (CM == CM_F16 ? "f16" : "f32");
+    snprintf(label, sizeof(label), "omp_full_mfma<%s,lp%d,k%d%s,m%d>:full", ty, LP, KM, MASK ? ",mask" : "",
+             CM == CM_NATIVE ? 0 : 8 * RR);
     ProfileToken *tok = profile_begin(label, st);
-    hipLaunchKernelGGL((k_omp_full<LP, KM, MASK>), dim3(grid), dim3(64 * NW), 0, st, a);
+    hipLaunchKernelGGL((k_omp_full<LP, KM, MASK, CM, RR>), dim3(grid), dim3(64 * NW), 0, st, a);
     profile_end(tok, st);
     CSPD_HIP_CHECK(hipGetLastError());
     return CSPD_OK;
 }
 
-template <int LP>
-cspd_status by_k(const FullArgs &a, int kmax, bool mask, hipStream_t st)
+template <int LP, int KM, int CM, int RR>
+cspd_status by_mask(const FullArgs &a, bool mask, hipStream_t st)
 {
-    if (kmax <= 8) return mask ? launch<LP, 8, true>(a, st) : launch<LP, 8, false>(a, st);
-    return mask ? launch<LP, 16, true>(a, st) : launch<LP, 16, false>(a, st);
+    return mask ? launch<LP, KM, true, CM, RR>(a, st) : launch<LP, KM, false, CM, RR>(a, st);
+}
+
+template <int LP, int KM>
+cspd_status by_mode(const FullArgs &a, bool mask, int corr, int rr, hipStream_t st)
+{
+    if constexpr (LP >= 16) {
+        if (corr == CSPD_CORR_BF16_RESCORE)
+            return rr == 1 ? by_mask<LP, KM, CM_BF16, 1>(a, mask, st) : by_mask<LP, KM, CM_BF16, 2>(a, mask, st);
+        if (corr == CSPD_CORR_F16_RESCORE)
+            return rr == 1 ? by_mask<LP, KM, CM_F16, 1>(a, mask, st) : by_mask<LP, KM, CM_F16, 2>(a, mask, st);
+    }
+    return by_mask<LP, KM, CM_NATIVE, 1>(a, mask, st);
+}
+
+template <int LP>
+cspd_status by_k(const FullArgs &a, int kmax, bool mask, int corr, int rr, hipStream_t st)
+{
+    if (kmax <= 8) return by_mode<LP, 8>(a, mask, corr, rr, st);
+    return by_mode<LP, 16>(a, mask, corr, rr, st);
 }
 
 }  // namespace full_impl
@@ -387,13 +556,16 @@ cspd_status launch_full_mfma(const cspd_plan_s *p, int64_t b, const void *y, con
     a.k_used = k_used;
     a.xhat = (float *)xhat;
     a.d_high = (const float *)p->d_high;
+    a.v_lo = (const uint16_t *)sc.v_lo;
     const int kmax = kvec ? p->k_max : kuni;
     const bool m = a.mask != nullptr;
+    const int corr = sc.v_lo ? p->corr_mode : CSPD_CORR_NATIVE;
+    const int rr = p->rescore_m <= 8 ? 1 : 2;   // candidates kept per lane (8 lanes per patch)
     switch (sc.lp) {
-        case 16: return by_k<16>(a, kmax, m, stream);
-        case 32: return by_k<32>(a, kmax, m, stream);
-        case 64: return by_k<64>(a, kmax, m, stream);
-        case 128: return by_k<128>(a, kmax, m, stream);
+        case 16: return by_k<16>(a, kmax, m, corr, rr, stream);
+        case 32: return by_k<32>(a, kmax, m, corr, rr, stream);
+        case 64: return by_k<64>(a, kmax, m, corr, rr, stream);
+        case 128: return by_k<128>(a, kmax, m, corr, rr, stream);
         default: return CSPD_E_UNSUPPORTED;
     }
 }
