@@ -149,6 +149,95 @@ def serve_phase(cspd, plan, w, ks, gpu_rate, jobs=300, seed=11):
             "slots": 4, "hbm_budget_bytes": 8 << 30, "note": "host buffers in pageable memory; latency includes PCIe copies"}
 
 
+def precision_phase(cspd, steps: int = 3):
+    """Reduced-precision proxy study on the three-scale workload's finest
+    scale (full OMP, 4096 atoms of length 128, K = 12, 262,144 patches): time
+    per call of the FP32 proxy and of the bf16 / fp16 proxies with FP32
+    re-scoring, and how far each result is from the FP32 path's."""
+    import torch
+
+    import synth
+
+    w = synth.make("c3")
+    B = w.batch
+    K = w.k_scales[-1]
+    dev = torch.device("cuda", 0)
+    y = torch.from_numpy(np.ascontiguousarray(w.y.astype(np.float32))).to(dev)
+    out = {"workload": f"c3 finest scale: {B} patches, {w.atoms[-1]} atoms of length {w.m}, K {K}",
+           "modes": {}}
+    ref = None
+    for mode in ("native", "bf16", "f16"):
+        plan = cspd.plan_from_workload(w, corr_mode=mode)
+        sup, coef, ku, xh = cspd.cspd_omp_full(plan, y, None, None, K)
+        torch.cuda.synchronize()
+        cspd.cspd_profile_reset()
+        cspd.cspd_profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            cspd.cspd_omp_full(plan, y, None, None, K, support=sup, coef=coef, k_used=ku, xhat=xh)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cspd.cspd_profile_enable(False)
+        prof = cspd.cspd_profile_read()
+        s_np = sup.cpu().numpy()
+        x_np = xh.double().cpu().numpy()
+        ent = {"ms_per_call": (t1 - t0) / steps * 1e3, "patches_per_s": B * steps / (t1 - t0),
+               "kernels": {k: v[1] / max(v[0], 1) for k, v in prof.items()}}
+        if ref is None:
+            ref = (s_np, x_np)
+        else:
+            d = np.linalg.norm(x_np - ref[1], axis=1) / np.maximum(np.linalg.norm(ref[1], axis=1), 1e-30)
+            ent["same_support_as_fp32"] = float(np.mean(np.all(s_np == ref[0], axis=1)))
+            ent["xhat_rel_diff_vs_fp32_q99"] = float(np.quantile(d, 0.99))
+            ent["xhat_rel_diff_vs_fp32_max"] = float(d.max())
+            ent["speedup_vs_fp32"] = out["modes"]["native"]["ms_per_call"] / ent["ms_per_call"]
+        out["modes"][mode] = ent
+        cspd.cspd_plan_destroy(plan)
+    return out
+
+
+def graph_phase(cspd, w, ks, sizes=(1024, 8192, 65536), reps=50):
+    """Wall time per call of a cross-scale call issued eagerly (library call
+    per batch: workspace, one launch per scale) and replayed from a captured
+    HIP graph, at several batch sizes (slices of the workload)."""
+    import torch
+
+    import synth
+
+    plan = cspd.plan_from_workload(w)
+    out = {}
+    for n in sizes:
+        n = min(n, w.batch)
+        sub = synth.subset(w, np.arange(n))
+        ndt = np.float64 if w.dtype == "f64" else np.float32
+        y = torch.from_numpy(np.ascontiguousarray(sub.y.astype(ndt))).cuda()
+        mask = None if sub.mask is None else torch.from_numpy(np.ascontiguousarray(sub.mask)).cuda()
+        res = cspd.cspd_omp_cross_scale(plan, y, mask, ks[:-1], None, ks[-1])
+        g, *_ = cspd.cspd_graph_cross_scale(plan, y, mask, ks[:-1], None, ks[-1])
+
+        def eager():
+            cspd.cspd_omp_cross_scale(plan, y, mask, ks[:-1], None, ks[-1], support=res[0], coef=res[1],
+                                      k_used=res[2], xhat=res[3])
+
+        def replay():
+            cspd.cspd_graph_launch(g)
+
+        ent = {}
+        for name, fn in (("eager", eager), ("graph", replay)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            ent[f"{name}_us"] = (time.perf_counter() - t0) / reps * 1e6
+        ent["graph_speedup"] = ent["eager_us"] / ent["graph_us"]
+        out[str(n)] = ent
+        del g
+    return out
+
+
 def traffic_probe(workload: str, steps: int = 3):
     """A plain elementwise pass over a buffer of known size, then a few
     cross-scale steps: run under rocprofv3 --pmc FETCH_SIZE, and again under
@@ -231,6 +320,8 @@ def main():
     ap.add_argument("--no-full", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=65536,
                     help="patches of the workload the oracle is timed on")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -400,6 +491,18 @@ def main():
         serving = serve_phase(cspd, plan, w, ks, B / t_cross)
         print(f"[bench] serving: {serving}", file=sys.stderr, flush=True)
 
+    # ---- batching: captured HIP graphs against eager calls
+    graphs = None
+    if not args.no_graph:
+        graphs = graph_phase(cspd, w, ks)
+        print(f"[bench] graphs: {json.dumps(graphs)}", file=sys.stderr, flush=True)
+
+    # ---- precision: bf16 / fp16 proxies with FP32 re-scoring (full OMP, 3-scale workload)
+    precision = None
+    if not args.no_precision:
+        precision = precision_phase(cspd)
+        print(f"[bench] precision: {json.dumps(precision)}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         import synth as _s
@@ -438,6 +541,8 @@ def main():
         "quality": quality,
         "equal_psnr": equal,
         "serving": serving,
+        "precision": precision,
+        "graphs": graphs,
     }
     print(json.dumps(line))
 

@@ -115,6 +115,7 @@ typedef struct cspd_plan_desc {
 } cspd_plan_desc;
 
 typedef struct cspd_plan_s *cspd_plan_t;
+typedef struct cspd_graph_s *cspd_graph_t;
 
 /*
  * Build a plan: validate the description, upload the dictionaries and Phi,
@@ -169,6 +170,27 @@ cspd_status cspd_omp_cross_scale(cspd_plan_t plan, int64_t B, const void *y, con
                                  int32_t k_fine_uniform, int32_t *support, void *coef,
                                  int32_t *k_used, void *xhat, int32_t *support_coarse,
                                  void *hip_stream);
+
+/*
+ * A cross-scale call (or, for S = 1, a full-dictionary call) captured once
+ * into a HIP graph for a fixed batch and fixed buffers: every scale's kernel
+ * is one node, and a replay launches them all with one graph launch, without
+ * host work or allocation per call.  The graph owns its workspace (allocated
+ * here).  Arguments as for cspd_omp_cross_scale, without a stream; the
+ * buffers must outlive the graph, and their contents may change between
+ * replays (the graph reads them when it runs).  Replays on one graph must not
+ * overlap (they share the workspace).  Errors as for the call, E_INVALID for
+ * B = 0, E_DEVICE when capture or instantiation fails.
+ */
+cspd_status cspd_graph_cross_scale(cspd_plan_t plan, int64_t B, const void *y, const uint8_t *mask,
+                                   const int32_t *k_scale, const int32_t *k_fine,
+                                   int32_t k_fine_uniform, int32_t *support, void *coef,
+                                   int32_t *k_used, void *xhat, int32_t *support_coarse,
+                                   cspd_graph_t *out);
+/* Replay a captured call on a HIP stream (stream-ordered). */
+cspd_status cspd_graph_launch(cspd_graph_t graph, void *hip_stream);
+/* Free the graph (waits until the device is idle) and its workspace. */
+void cspd_graph_destroy(cspd_graph_t graph);
 
 /* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of reconstruction jobs on one device.      */

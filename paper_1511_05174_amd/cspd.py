@@ -7,6 +7,7 @@ library is missing, importing the functions raises -- there is no fallback.
 Names follow the C entry points:
   cspd_plan, cspd_plan_destroy, cspd_plan_device_bytes,
   cspd_omp_full, cspd_omp_cross_scale,
+  cspd_graph_cross_scale, cspd_graph_launch, cspd_graph_destroy,
   cspd_serve_create, cspd_serve_submit, cspd_serve_poll, cspd_serve_destroy,
   cspd_last_error, cspd_version.
 """
@@ -92,6 +93,11 @@ SIGNATURES = {
     "cspd_omp_cross_scale": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cspd_graph_cross_scale": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "cspd_graph_launch": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "cspd_graph_destroy": (None, [C.c_void_p]),
     "cspd_serve_create": (C.c_int32, [C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_void_p)]),
     "cspd_serve_submit": (C.c_int32, [C.c_void_p, C.POINTER(Job), C.POINTER(C.c_uint64)]),
     "cspd_serve_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64, C.POINTER(JobStats)]),
@@ -288,6 +294,47 @@ def cspd_omp_cross_scale(plan: Plan, y, mask=None, k_scale: Sequence[int] = (), 
                                        int(k_fine_uniform), _ptr(support), _ptr(coef), _ptr(k_used),
                                        _ptr(xhat), _ptr(support_coarse), _stream(stream)))
     return support, coef, k_used, xhat
+
+
+class Graph:
+    """A captured call (cspd_graph_t) and the tensors it reads and writes."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self.keep = keep            # buffers the graph refers to stay alive with it
+
+    def __del__(self):
+        try:
+            cspd_graph_destroy(self)
+        except Exception:
+            pass
+
+
+def cspd_graph_cross_scale(plan: Plan, y, mask=None, k_scale: Sequence[int] = (), k_fine=None,
+                           k_fine_uniform: int = 0, support=None, coef=None, k_used=None, xhat=None,
+                           support_coarse=None, want_xhat: bool = True):
+    """Capture a cross-scale call into a HIP graph; returns (graph, support,
+    coef, k_used, xhat).  Replays read y / mask / k_fine as they are then."""
+    _check_inputs(plan, y, mask, k_fine)
+    B = y.shape[0]
+    support, coef, k_used, xhat = _outputs(plan, B, support, coef, k_used, xhat, want_xhat)
+    ks = (C.c_int32 * MAX_SCALES)(*([int(v) for v in k_scale] + [0] * (MAX_SCALES - len(k_scale))))
+    h = C.c_void_p()
+    _check(load().cspd_graph_cross_scale(plan.handle, B, _ptr(y), _ptr(mask), ks, _ptr(k_fine),
+                                         int(k_fine_uniform), _ptr(support), _ptr(coef), _ptr(k_used),
+                                         _ptr(xhat), _ptr(support_coarse), C.byref(h)))
+    g = Graph(h.value, (plan, y, mask, k_fine, support, coef, k_used, xhat, support_coarse))
+    return g, support, coef, k_used, xhat
+
+
+def cspd_graph_launch(graph: Graph, stream=None):
+    _check(load().cspd_graph_launch(graph.handle, _stream(stream)))
+
+
+def cspd_graph_destroy(graph: Graph):
+    h, graph.handle = graph.handle, None
+    if h:
+        load().cspd_graph_destroy(h)
 
 
 def cspd_profile_enable(on: bool = True):

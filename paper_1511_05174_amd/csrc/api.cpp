@@ -149,8 +149,111 @@ int max_candidates(const cspd_plan_s *p, int s, bool first, int k_prev)
     return (int)(v < p->sc[s].t ? v : p->sc[s].t);
 }
 
+
+// Validated scalars of one cross-scale call.
+struct CrossCall {
+    int ksum = 0;
+    std::vector<int> cand;
+    std::vector<char> gram;
+};
+
+cspd_status prepare_cross(const cspd_plan_s *p, int64_t B, const void *y, const uint8_t *mask,
+                          const int32_t *k_scale, const int32_t *k_fine, int32_t k_fine_uniform,
+                          const int32_t *support, const void *coef, const int32_t *k_used, CrossCall &c)
+{
+    if (B < 0) return set_error(CSPD_E_INVALID, "B = %lld", (long long)B);
+    if (!k_scale) return set_error(CSPD_E_INVALID, "k_scale is NULL");
+    c.ksum = 0;
+    for (int s = 0; s + 1 < p->s; ++s) {
+        if (k_scale[s] < 0 || k_scale[s] > p->k_max)
+            return set_error(CSPD_E_SHAPE, "k_scale[%d] = %d outside [0, k_max = %d]", s, k_scale[s], p->k_max);
+        c.ksum += k_scale[s];
+    }
+    if (!k_fine && (k_fine_uniform < 0 || k_fine_uniform > p->k_max))
+        return set_error(CSPD_E_SHAPE, "k_fine_uniform %d outside [0, k_max = %d]", k_fine_uniform, p->k_max);
+    if (B == 0) return CSPD_OK;
+    if (!y || !support || !coef || !k_used) return set_error(CSPD_E_INVALID, "y / support / coef / k_used is NULL");
+    if (p->phi_kind == CSPD_PHI_MASK && !mask) return set_error(CSPD_E_INVALID, "mask plan needs a mask");
+    // candidate counts per scale must have kernels before anything is launched
+    c.cand.assign(p->s, 0);
+    c.gram.assign(p->s, 0);
+    for (int s = 0; s < p->s; ++s) {
+        const int kprev = s == 0 ? 0 : k_scale[s - 1];
+        c.cand[s] = max_candidates(p, s, s == 0, kprev);
+        if (!scale_vec_fits(p->sc[s].lp, c.cand[s], p->dtype == CSPD_F64)) {
+            if (s == 0 && p->sc[s].gram) c.gram[s] = 1;
+            else return set_error(CSPD_E_UNSUPPORTED, "scale %d: no kernel for %d candidates of length %d",
+                                  s, c.cand[s], p->sc[s].l);
+        }
+    }
+    return CSPD_OK;
+}
+
+// Workspace of a cross-scale call: the coarse scales' k_used, and their
+// supports unless the caller keeps them.
+size_t cross_workspace_bytes(const cspd_plan_s *p, int64_t B, int ksum, bool caller_keeps_supports)
+{
+    const int64_t nk = B * (p->s - 1);
+    return sizeof(int32_t) * (size_t)(nk + (caller_keeps_supports ? 0 : B * (int64_t)ksum));
+}
+
+// One kernel per scale on `st`; `work` holds cross_workspace_bytes.
+cspd_status run_cross(const cspd_plan_s *p, int64_t B, const void *y, const uint8_t *mask,
+                      const int32_t *k_scale, const int32_t *k_fine, int32_t k_fine_uniform,
+                      int32_t *support, void *coef, int32_t *k_used, void *xhat, int32_t *support_coarse,
+                      int32_t *work, const CrossCall &c, hipStream_t st)
+{
+    const int64_t nk = B * (p->s - 1);
+    int32_t *kused_c = work;
+    int32_t *coarse = support_coarse ? support_coarse : work + nk;
+    cspd_status rc = CSPD_OK;
+    int off = 0;
+    for (int s = 0; s < p->s && rc == CSPD_OK; ++s) {
+        ScaleArgs a = base_args(p, s, B, y, mask);
+        a.first = s == 0;
+        a.scale = s;
+        if (s > 0) {
+            a.prev_sup = coarse + (off - k_scale[s - 1]);
+            a.prev_stride = c.ksum;
+            a.prev_count = k_scale[s - 1];
+            a.prev_kused = kused_c + B * (s - 1);
+        }
+        if (s + 1 < p->s) {
+            a.kvec = nullptr;
+            a.kuni = k_scale[s];
+            a.last = 0;
+            a.sup_out = coarse + off;
+            a.sup_stride = c.ksum;
+            a.sup_count = k_scale[s];
+            a.kused_out = kused_c + B * s;
+            off += k_scale[s];
+        } else {
+            a.kvec = k_fine;
+            a.kuni = k_fine_uniform;
+            a.last = 1;
+            a.sup_out = support;
+            a.sup_stride = p->k_max;
+            a.sup_count = p->k_max;
+            a.kused_out = k_used;
+            a.coef_out = coef;
+            a.xhat = xhat;
+        }
+        rc = s == 0 ? launch_first_mfma(p->dtype, a, st) : CSPD_E_UNSUPPORTED;
+        if (rc == CSPD_E_UNSUPPORTED) rc = launch_scale(p->dtype, a, c.cand[s], c.gram[s], st);
+    }
+    return rc;
+}
+
 }  // namespace
 }  // namespace cspd
+
+struct cspd_graph_s {
+    int device = 0;
+    void *work = nullptr;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 using namespace cspd;
 
@@ -261,80 +364,103 @@ cspd_status cspd_omp_cross_scale(cspd_plan_t p, int64_t B, const void *y, const 
     if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
     if (p->s == 1)
         return cspd_omp_full(p, B, y, mask, k_fine, k_fine_uniform, support, coef, k_used, xhat, hip_stream);
-    if (B < 0) return set_error(CSPD_E_INVALID, "B = %lld", (long long)B);
-    if (!k_scale) return set_error(CSPD_E_INVALID, "k_scale is NULL");
-    int ksum = 0;
-    for (int s = 0; s + 1 < p->s; ++s) {
-        if (k_scale[s] < 0 || k_scale[s] > p->k_max)
-            return set_error(CSPD_E_SHAPE, "k_scale[%d] = %d outside [0, k_max = %d]", s, k_scale[s], p->k_max);
-        ksum += k_scale[s];
-    }
-    if (!k_fine && (k_fine_uniform < 0 || k_fine_uniform > p->k_max))
-        return set_error(CSPD_E_SHAPE, "k_fine_uniform %d outside [0, k_max = %d]", k_fine_uniform, p->k_max);
-    if (B == 0) return CSPD_OK;
-    if (!y || !support || !coef || !k_used) return set_error(CSPD_E_INVALID, "y / support / coef / k_used is NULL");
-    if (p->phi_kind == CSPD_PHI_MASK && !mask) return set_error(CSPD_E_INVALID, "mask plan needs a mask");
-    // candidate counts per scale must have kernels before anything is launched
-    std::vector<int> cand(p->s);
-    std::vector<char> gram(p->s, 0);
-    for (int s = 0; s < p->s; ++s) {
-        const int kprev = s == 0 ? 0 : k_scale[s - 1];
-        cand[s] = max_candidates(p, s, s == 0, kprev);
-        if (!scale_vec_fits(p->sc[s].lp, cand[s], p->dtype == CSPD_F64)) {
-            if (s == 0 && p->sc[s].gram) gram[s] = 1;
-            else return set_error(CSPD_E_UNSUPPORTED, "scale %d: no kernel for %d candidates of length %d",
-                                  s, cand[s], p->sc[s].l);
-        }
-    }
+    CrossCall c;
+    cspd_status rc = prepare_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, c);
+    if (rc != CSPD_OK || B == 0) return rc;
     DeviceGuard g(p->device);
     if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
     hipStream_t st = (hipStream_t)hip_stream;
     // coarse supports: the caller's buffer, or a stream-ordered temporary
     int32_t *work = nullptr;
-    int32_t *coarse = support_coarse;
-    const int64_t nk = (int64_t)B * (p->s - 1);
-    size_t wbytes = sizeof(int32_t) * (size_t)(nk + (support_coarse ? 0 : (int64_t)B * ksum));
+    const size_t wbytes = cross_workspace_bytes(p, B, c.ksum, support_coarse != nullptr);
     if (hipMallocAsync((void **)&work, wbytes, st) != hipSuccess)
         return set_error(CSPD_E_NOMEM, "workspace of %zu bytes", wbytes);
-    int32_t *kused_c = work;
-    if (!coarse) coarse = work + nk;
-    cspd_status rc = CSPD_OK;
-    int off = 0;
-    for (int s = 0; s < p->s && rc == CSPD_OK; ++s) {
-        ScaleArgs a = base_args(p, s, B, y, mask);
-        a.first = s == 0;
-        a.scale = s;
-        if (s > 0) {
-            a.prev_sup = coarse + (off - k_scale[s - 1]);
-            a.prev_stride = ksum;
-            a.prev_count = k_scale[s - 1];
-            a.prev_kused = kused_c + (int64_t)B * (s - 1);
-        }
-        if (s + 1 < p->s) {
-            a.kvec = nullptr;
-            a.kuni = k_scale[s];
-            a.last = 0;
-            a.sup_out = coarse + off;
-            a.sup_stride = ksum;
-            a.sup_count = k_scale[s];
-            a.kused_out = kused_c + (int64_t)B * s;
-            off += k_scale[s];
-        } else {
-            a.kvec = k_fine;
-            a.kuni = k_fine_uniform;
-            a.last = 1;
-            a.sup_out = support;
-            a.sup_stride = p->k_max;
-            a.sup_count = p->k_max;
-            a.kused_out = k_used;
-            a.coef_out = coef;
-            a.xhat = xhat;
-        }
-        rc = s == 0 ? launch_first_mfma(p->dtype, a, st) : CSPD_E_UNSUPPORTED;
-        if (rc == CSPD_E_UNSUPPORTED) rc = launch_scale(p->dtype, a, cand[s], gram[s], st);
-    }
+    rc = run_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat,
+                   support_coarse, work, c, st);
     (void)hipFreeAsync(work, st);
     return rc;
+}
+
+cspd_status cspd_graph_cross_scale(cspd_plan_t p, int64_t B, const void *y, const uint8_t *mask,
+                                   const int32_t *k_scale, const int32_t *k_fine,
+                                   int32_t k_fine_uniform, int32_t *support, void *coef,
+                                   int32_t *k_used, void *xhat, int32_t *support_coarse,
+                                   cspd_graph_t *out)
+{
+    clear_error();
+    if (!out) return set_error(CSPD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+    if (B <= 0) return set_error(CSPD_E_INVALID, "B = %lld (a graph needs patches)", (long long)B);
+    CrossCall c;
+    if (p->s > 1) {
+        const cspd_status rc = prepare_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef,
+                                             k_used, c);
+        if (rc != CSPD_OK) return rc;
+    }
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
+    cspd_graph_s *gr = new cspd_graph_s();
+    gr->device = p->device;
+    auto fail = [&](cspd_status code, const char *what) {
+        cspd_graph_destroy(gr);
+        return set_error(code, "%s", what);
+    };
+    const size_t wbytes = p->s > 1 ? cross_workspace_bytes(p, B, c.ksum, support_coarse != nullptr) : 0;
+    if (wbytes && hipMalloc(&gr->work, wbytes) != hipSuccess) return fail(CSPD_E_NOMEM, "graph workspace");
+    if (hipStreamCreateWithFlags(&gr->capture, hipStreamNonBlocking) != hipSuccess)
+        return fail(CSPD_E_DEVICE, "capture stream");
+    if (hipStreamBeginCapture(gr->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(CSPD_E_DEVICE, "hipStreamBeginCapture failed");
+    cspd_status rc;
+    {
+        ProfileSuspend quiet;
+        if (p->s == 1)
+            rc = cspd_omp_full(p, B, y, mask, k_fine, k_fine_uniform, support, coef, k_used, xhat, gr->capture);
+        else
+            rc = run_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat,
+                           support_coarse, (int32_t *)gr->work, c, gr->capture);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(gr->capture, &graph);
+    gr->graph = graph;
+    if (rc != CSPD_OK) {
+        const std::string msg = cspd::g_err;
+        cspd_graph_destroy(gr);
+        return set_error(rc, "%s", msg.c_str());
+    }
+    if (ce != hipSuccess || !graph) return fail(CSPD_E_DEVICE, "hipStreamEndCapture failed");
+    if (hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        return fail(CSPD_E_DEVICE, "hipGraphInstantiate failed");
+    *out = gr;
+    return CSPD_OK;
+}
+
+cspd_status cspd_graph_launch(cspd_graph_t gr, void *hip_stream)
+{
+    clear_error();
+    if (!gr || !gr->exec) return set_error(CSPD_E_INVALID, "graph is NULL");
+    DeviceGuard g(gr->device);
+    if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", gr->device);
+    CSPD_HIP_CHECK(hipGraphLaunch(gr->exec, (hipStream_t)hip_stream));
+    return CSPD_OK;
+}
+
+void cspd_graph_destroy(cspd_graph_t gr)
+{
+    if (!gr) return;
+    DeviceGuard g(gr->device);
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    if (gr->capture) {
+        (void)hipStreamSynchronize(gr->capture);
+        (void)hipStreamDestroy(gr->capture);
+    }
+    if (gr->work) {
+        (void)hipDeviceSynchronize();   // no replay may still read the workspace
+        (void)hipFree(gr->work);
+    }
+    delete gr;
 }
 
 }  // extern "C"

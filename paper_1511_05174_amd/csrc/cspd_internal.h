@@ -131,6 +131,11 @@ cspd_status launch_full_mfma(const cspd_plan_s *p, int64_t b, const void *y, con
 struct ProfileToken;
 ProfileToken *profile_begin(const char *label, hipStream_t stream);
 void profile_end(ProfileToken *tok, hipStream_t stream);
+// While alive, this thread's launches record no profiling events (graph capture).
+struct ProfileSuspend {
+    ProfileSuspend();
+    ~ProfileSuspend();
+};
 
 // Plan-time kernels.
 cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t stream);

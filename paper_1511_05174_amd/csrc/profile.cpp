@@ -58,9 +58,16 @@ void settle_locked()
 
 }  // namespace
 
+namespace {
+thread_local int t_suspended = 0;   // launches being captured into a graph record no events
+}
+
+ProfileSuspend::ProfileSuspend() { ++t_suspended; }
+ProfileSuspend::~ProfileSuspend() { --t_suspended; }
+
 ProfileToken *profile_begin(const char *label, hipStream_t stream)
 {
-    if (!g_on.load(std::memory_order_relaxed)) return nullptr;
+    if (!g_on.load(std::memory_order_relaxed) || t_suspended) return nullptr;
     ProfileToken *t = new ProfileToken();
     if (hipEventCreate(&t->start) != hipSuccess) { delete t; return nullptr; }
     if (hipEventCreate(&t->stop) != hipSuccess) { (void)hipEventDestroy(t->start); delete t; return nullptr; }
