@@ -238,6 +238,39 @@ def graph_phase(cspd, w, ks, sizes=(1024, 8192, 65536), reps=50):
     return out
 
 
+def autotune_phase(cspd, w, ks, y, mask, kf, steps: int = 10):
+    """Autotuner on the benchmark batch: the kernel it keeps per scale, and the
+    time per cross-scale step with the tuned plan against the shape rules
+    (two plans of the same workload, timed alternately)."""
+    import torch
+
+    rules = cspd.plan_from_workload(w)
+    tuned = cspd.plan_from_workload(w)
+    t0 = time.perf_counter()
+    cspd.cspd_autotune(tuned, y, mask, ks[:-1], kf, ks[-1], reps=3)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    chosen = {}
+    for s in range(w.n_scales):
+        kb = 0 if ks[s] <= 4 else (1 if ks[s] <= 8 else 2)
+        kind, nc, ppw, cand = cspd.cspd_tuned_kernel(tuned, s, kb)
+        chosen[f"s{s}"] = {"kind": kind, "nc": nc, "ppw": ppw, "cand": cand}
+    res = {}
+    for name, plan in (("rules", rules), ("tuned", tuned)):
+        out = cspd.cspd_omp_cross_scale(plan, y, mask, ks[:-1], kf, ks[-1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            cspd.cspd_omp_cross_scale(plan, y, mask, ks[:-1], kf, ks[-1], support=out[0], coef=out[1],
+                                      k_used=out[2], xhat=out[3])
+        torch.cuda.synchronize()
+        res[f"{name}_ms"] = (time.perf_counter() - t0) / steps * 1e3
+    res["speedup"] = res["rules_ms"] / res["tuned_ms"]
+    res["tune_s"] = tune_s
+    res["chosen"] = chosen
+    return res
+
+
 def traffic_probe(workload: str, steps: int = 3):
     """A plain elementwise pass over a buffer of known size, then a few
     cross-scale steps: run under rocprofv3 --pmc FETCH_SIZE, and again under
@@ -322,6 +355,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=65536,
                     help="patches of the workload the oracle is timed on")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -497,6 +531,12 @@ def main():
         graphs = graph_phase(cspd, w, ks)
         print(f"[bench] graphs: {json.dumps(graphs)}", file=sys.stderr, flush=True)
 
+    # ---- batching: autotuned kernel per scale against the shape rules
+    autotune = None
+    if not args.no_autotune:
+        autotune = autotune_phase(cspd, w, ks, y, mask, kf)
+        print(f"[bench] autotune: {json.dumps(autotune)}", file=sys.stderr, flush=True)
+
     # ---- precision: bf16 / fp16 proxies with FP32 re-scoring (full OMP, 3-scale workload)
     precision = None
     if not args.no_precision:
@@ -543,6 +583,7 @@ def main():
         "serving": serving,
         "precision": precision,
         "graphs": graphs,
+        "autotune": autotune,
     }
     print(json.dumps(line))
 

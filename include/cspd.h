@@ -192,6 +192,43 @@ cspd_status cspd_graph_launch(cspd_graph_t graph, void *hip_stream);
 /* Free the graph (waits until the device is idle) and its workspace. */
 void cspd_graph_destroy(cspd_graph_t graph);
 
+/*
+ * Autotuner (not in the paper: kernel selection for Algorithm 2's scales).
+ * Runs the cross-scale call once on the caller's batch, then, scale by
+ * scale, times every kernel variant that can run that scale (the
+ * first-scale matrix-core kernel, the per-patch Gram on the matrix cores,
+ * each vector layout, the precomputed-Gram kernel), `reps` launches each,
+ * and keeps the fastest in the plan, keyed by scale, by the scale's
+ * sparsity bucket (K <= 4, <= 8, <= 16) and by its candidate count.  Later
+ * cross-scale calls (and graphs captured after) with the same key use it;
+ * other keys keep the shape rules.  Every variant computes the same result
+ * up to FP32 rounding order.  Arguments as for cspd_omp_cross_scale (inputs
+ * only: outputs go to scratch allocated and freed here); blocks until done.
+ * FP32 plans with S >= 2 only (others: no-op).  Errors: as for the call,
+ * E_INVALID for reps outside 1..1000, E_NOMEM for the scratch.
+ */
+cspd_status cspd_autotune(cspd_plan_t plan, int64_t B, const void *y, const uint8_t *mask,
+                          const int32_t *k_scale, const int32_t *k_fine, int32_t k_fine_uniform,
+                          int32_t reps, void *hip_stream);
+/*
+ * The plan's tuned kernel for (scale, bucket 0..2): kind 0 = none (shape
+ * rules), 1 = first-scale matrix-core, 2 = vector layout (nc column chunks,
+ * ppw patches per wavefront), 3 = precomputed Gram, 4 = per-patch Gram on
+ * the matrix cores; cand = candidate count it was timed on.
+ * Errors: E_INVALID for a NULL argument or an index out of range.
+ */
+cspd_status cspd_tuned_kernel(cspd_plan_t plan, int32_t scale, int32_t bucket, int32_t *kind, int32_t *nc,
+                              int32_t *ppw, int32_t *cand);
+/*
+ * Pin a kernel for (scale, bucket, cand), e.g. one read back from
+ * cspd_tuned_kernel in an earlier process, without timing; kind 0 clears
+ * the entry (shape rules again).  Errors: E_INVALID for an index out of
+ * range or cand outside 1..T of the scale, E_UNSUPPORTED when the variant
+ * cannot run that scale at that candidate count.
+ */
+cspd_status cspd_set_tuned_kernel(cspd_plan_t plan, int32_t scale, int32_t bucket, int32_t kind, int32_t nc,
+                                  int32_t ppw, int32_t cand);
+
 /* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of reconstruction jobs on one device.      */
 /* (Not in the paper: a request loop around the calls above.)             */

@@ -8,6 +8,7 @@ Names follow the C entry points:
   cspd_plan, cspd_plan_destroy, cspd_plan_device_bytes,
   cspd_omp_full, cspd_omp_cross_scale,
   cspd_graph_cross_scale, cspd_graph_launch, cspd_graph_destroy,
+  cspd_autotune, cspd_tuned_kernel, cspd_set_tuned_kernel,
   cspd_serve_create, cspd_serve_submit, cspd_serve_poll, cspd_serve_destroy,
   cspd_last_error, cspd_version.
 """
@@ -98,6 +99,12 @@ SIGNATURES = {
                                            C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "cspd_graph_launch": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "cspd_graph_destroy": (None, [C.c_void_p]),
+    "cspd_autotune": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_int32, C.c_int32, C.c_void_p]),
+    "cspd_tuned_kernel": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "cspd_set_tuned_kernel": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                          C.c_int32]),
     "cspd_serve_create": (C.c_int32, [C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_void_p)]),
     "cspd_serve_submit": (C.c_int32, [C.c_void_p, C.POINTER(Job), C.POINTER(C.c_uint64)]),
     "cspd_serve_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64, C.POINTER(JobStats)]),
@@ -335,6 +342,36 @@ def cspd_graph_destroy(graph: Graph):
     h, graph.handle = graph.handle, None
     if h:
         load().cspd_graph_destroy(h)
+
+
+TUNED_KINDS = {0: "rules", 1: "first_mfma", 2: "vec", 3: "gram", 4: "mfma_gram"}
+
+
+def cspd_autotune(plan: Plan, y, mask=None, k_scale: Sequence[int] = (), k_fine=None,
+                  k_fine_uniform: int = 0, reps: int = 3, stream=None):
+    """Time every kernel variant of each scale on this batch and keep the
+    fastest in the plan (blocks until done)."""
+    _check_inputs(plan, y, mask, k_fine)
+    ks = (C.c_int32 * MAX_SCALES)(*([int(v) for v in k_scale] + [0] * (MAX_SCALES - len(k_scale))))
+    _check(load().cspd_autotune(plan.handle, y.shape[0], _ptr(y), _ptr(mask), ks, _ptr(k_fine),
+                                int(k_fine_uniform), int(reps), _stream(stream)))
+
+
+def cspd_tuned_kernel(plan: Plan, scale: int, bucket: int):
+    """(kind name, nc, ppw, cand) of the plan's tuned kernel for a scale and
+    sparsity bucket (0: K <= 4, 1: K <= 8, 2: K <= 16)."""
+    kind, nc, ppw, cand = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().cspd_tuned_kernel(plan.handle, int(scale), int(bucket), C.byref(kind), C.byref(nc),
+                                    C.byref(ppw), C.byref(cand)))
+    return TUNED_KINDS.get(kind.value, str(kind.value)), nc.value, ppw.value, cand.value
+
+
+def cspd_set_tuned_kernel(plan: Plan, scale: int, bucket: int, kind, nc: int = 1, ppw: int = 1, cand: int = 0):
+    """Pin a kernel variant (kind name or number; \"rules\" clears)."""
+    if isinstance(kind, str):
+        kind = {v: k for k, v in TUNED_KINDS.items()}[kind]
+    _check(load().cspd_set_tuned_kernel(plan.handle, int(scale), int(bucket), int(kind), int(nc), int(ppw),
+                                        int(cand)))
 
 
 def cspd_profile_enable(on: bool = True):

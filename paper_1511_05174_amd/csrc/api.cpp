@@ -197,6 +197,66 @@ size_t cross_workspace_bytes(const cspd_plan_s *p, int64_t B, int ksum, bool cal
     return sizeof(int32_t) * (size_t)(nk + (caller_keeps_supports ? 0 : B * (int64_t)ksum));
 }
 
+// Arguments of scale s of a cross-scale call.
+ScaleArgs cross_scale_args(const cspd_plan_s *p, int s, int64_t B, const void *y, const uint8_t *mask,
+                           const int32_t *k_scale, const int32_t *k_fine, int32_t k_fine_uniform,
+                           int32_t *support, void *coef, int32_t *k_used, void *xhat, int32_t *coarse,
+                           int32_t *kused_c, int ksum)
+{
+    int off = 0;
+    for (int i = 0; i < s; ++i) off += k_scale[i];
+    ScaleArgs a = base_args(p, s, B, y, mask);
+    a.first = s == 0;
+    a.scale = s;
+    if (s > 0) {
+        a.prev_sup = coarse + (off - k_scale[s - 1]);
+        a.prev_stride = ksum;
+        a.prev_count = k_scale[s - 1];
+        a.prev_kused = kused_c + B * (s - 1);
+    }
+    if (s + 1 < p->s) {
+        a.kvec = nullptr;
+        a.kuni = k_scale[s];
+        a.last = 0;
+        a.sup_out = coarse + off;
+        a.sup_stride = ksum;
+        a.sup_count = k_scale[s];
+        a.kused_out = kused_c + B * s;
+    } else {
+        a.kvec = k_fine;
+        a.kuni = k_fine_uniform;
+        a.last = 1;
+        a.sup_out = support;
+        a.sup_stride = p->k_max;
+        a.sup_count = p->k_max;
+        a.kused_out = k_used;
+        a.coef_out = coef;
+        a.xhat = xhat;
+    }
+    return a;
+}
+
+// One scale with the plan's autotuned kernel if there is one, else by the
+// shape rules.
+cspd_status launch_cross_scale(const cspd_plan_s *p, int s, const ScaleArgs &a, const CrossCall &c, hipStream_t st)
+{
+    KernelChoice tc;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        tc = p->tuned[s][k_bucket(a)];
+    }
+    if (tc.kind != kChoiceAuto && tc.cand == c.cand[s]) {
+        const cspd_status rc = launch_choice(p->dtype, a, tc, st);
+        if (rc == CSPD_E_UNSUPPORTED && cspd::g_err.empty())
+            return set_error(rc, "scale %d: tuned kernel kind %d (nc %d, ppw %d) cannot run this call", s, tc.kind,
+                             tc.nc, tc.ppw);
+        return rc;
+    }
+    cspd_status rc = s == 0 ? launch_first_mfma(p->dtype, a, st) : CSPD_E_UNSUPPORTED;
+    if (rc == CSPD_E_UNSUPPORTED) rc = launch_scale(p->dtype, a, c.cand[s], c.gram[s], st);
+    return rc;
+}
+
 // One kernel per scale on `st`; `work` holds cross_workspace_bytes.
 cspd_status run_cross(const cspd_plan_s *p, int64_t B, const void *y, const uint8_t *mask,
                       const int32_t *k_scale, const int32_t *k_fine, int32_t k_fine_uniform,
@@ -207,39 +267,10 @@ cspd_status run_cross(const cspd_plan_s *p, int64_t B, const void *y, const uint
     int32_t *kused_c = work;
     int32_t *coarse = support_coarse ? support_coarse : work + nk;
     cspd_status rc = CSPD_OK;
-    int off = 0;
     for (int s = 0; s < p->s && rc == CSPD_OK; ++s) {
-        ScaleArgs a = base_args(p, s, B, y, mask);
-        a.first = s == 0;
-        a.scale = s;
-        if (s > 0) {
-            a.prev_sup = coarse + (off - k_scale[s - 1]);
-            a.prev_stride = c.ksum;
-            a.prev_count = k_scale[s - 1];
-            a.prev_kused = kused_c + B * (s - 1);
-        }
-        if (s + 1 < p->s) {
-            a.kvec = nullptr;
-            a.kuni = k_scale[s];
-            a.last = 0;
-            a.sup_out = coarse + off;
-            a.sup_stride = c.ksum;
-            a.sup_count = k_scale[s];
-            a.kused_out = kused_c + B * s;
-            off += k_scale[s];
-        } else {
-            a.kvec = k_fine;
-            a.kuni = k_fine_uniform;
-            a.last = 1;
-            a.sup_out = support;
-            a.sup_stride = p->k_max;
-            a.sup_count = p->k_max;
-            a.kused_out = k_used;
-            a.coef_out = coef;
-            a.xhat = xhat;
-        }
-        rc = s == 0 ? launch_first_mfma(p->dtype, a, st) : CSPD_E_UNSUPPORTED;
-        if (rc == CSPD_E_UNSUPPORTED) rc = launch_scale(p->dtype, a, c.cand[s], c.gram[s], st);
+        const ScaleArgs a = cross_scale_args(p, s, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef,
+                                             k_used, xhat, coarse, kused_c, c.ksum);
+        rc = launch_cross_scale(p, s, a, c, st);
     }
     return rc;
 }
@@ -461,6 +492,129 @@ void cspd_graph_destroy(cspd_graph_t gr)
         (void)hipFree(gr->work);
     }
     delete gr;
+}
+
+cspd_status cspd_autotune(cspd_plan_t p, int64_t B, const void *y, const uint8_t *mask,
+                          const int32_t *k_scale, const int32_t *k_fine, int32_t k_fine_uniform,
+                          int32_t reps, void *hip_stream)
+{
+    clear_error();
+    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+    if (reps < 1 || reps > 1000) return set_error(CSPD_E_INVALID, "reps %d outside 1..1000", reps);
+    if (p->s < 2 || p->dtype != CSPD_F32 || B == 0) return CSPD_OK;   // nothing to choose
+    CrossCall c;
+    int32_t dummy = 0;
+    cspd_status rc = prepare_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, &dummy, &dummy, &dummy, c);
+    if (rc != CSPD_OK) return rc;
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    ProfileSuspend quiet;
+    // scratch outputs and workspace for the timing runs
+    int32_t *work = nullptr, *sup = nullptr, *ku = nullptr;
+    void *coef = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        if (work) (void)hipFree(work);
+        if (sup) (void)hipFree(sup);
+        if (ku) (void)hipFree(ku);
+        if (coef) (void)hipFree(coef);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    const size_t wbytes = cross_workspace_bytes(p, B, c.ksum, false);
+    if (hipMalloc((void **)&work, wbytes) != hipSuccess || hipMalloc((void **)&sup, sizeof(int32_t) * B * p->k_max) != hipSuccess ||
+        hipMalloc((void **)&ku, sizeof(int32_t) * B) != hipSuccess ||
+        hipMalloc(&coef, sizeof(float) * B * p->k_max) != hipSuccess) {
+        cleanup();
+        return set_error(CSPD_E_NOMEM, "autotune scratch for %lld patches", (long long)B);
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return set_error(CSPD_E_DEVICE, "hipEventCreate failed");
+    }
+    // one call with the current choices leaves every coarse support in place
+    rc = run_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, sup, coef, ku, nullptr, nullptr, work, c, st);
+    if (rc != CSPD_OK) { cleanup(); return rc; }
+    const int64_t nk = B * (p->s - 1);
+    for (int s = 0; s < p->s; ++s) {
+        const ScaleArgs a = cross_scale_args(p, s, B, y, mask, k_scale, k_fine, k_fine_uniform, sup, coef, ku,
+                                             nullptr, work + nk, work, c.ksum);
+        KernelChoice ch[24];
+        const int nch = scale_choices(p->dtype, a, c.cand[s], p->sc[s].gram != nullptr, ch, 24);
+        float best_ms = 0.f;
+        int best = -1;
+        for (int i = 0; i < nch; ++i) {
+            if (launch_choice(p->dtype, a, ch[i], st) != CSPD_OK) { clear_error(); continue; }
+            (void)hipEventRecord(e0, st);
+            bool ok = true;
+            for (int r = 0; r < reps && ok; ++r) ok = launch_choice(p->dtype, a, ch[i], st) == CSPD_OK;
+            (void)hipEventRecord(e1, st);
+            float ms = 0.f;
+            if (!ok || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                clear_error();
+                continue;
+            }
+            if (best < 0 || ms < best_ms) { best_ms = ms; best = i; }
+        }
+        if (best >= 0) {
+            ch[best].cand = c.cand[s];
+            std::lock_guard<std::mutex> lk(p->mu);
+            p->tuned[s][k_bucket(a)] = ch[best];
+        }
+    }
+    cleanup();
+    return CSPD_OK;
+}
+
+cspd_status cspd_tuned_kernel(cspd_plan_t p, int32_t scale, int32_t k_bucket_, int32_t *kind, int32_t *nc,
+                              int32_t *ppw, int32_t *cand)
+{
+    clear_error();
+    if (!p || !kind || !nc || !ppw || !cand) return set_error(CSPD_E_INVALID, "NULL argument");
+    if (scale < 0 || scale >= p->s || k_bucket_ < 0 || k_bucket_ > 2)
+        return set_error(CSPD_E_INVALID, "scale %d / bucket %d out of range", scale, k_bucket_);
+    std::lock_guard<std::mutex> lk(p->mu);
+    const KernelChoice &c = p->tuned[scale][k_bucket_];
+    *kind = c.kind;
+    *nc = c.nc;
+    *ppw = c.ppw;
+    *cand = c.cand;
+    return CSPD_OK;
+}
+
+cspd_status cspd_set_tuned_kernel(cspd_plan_t p, int32_t scale, int32_t k_bucket_, int32_t kind, int32_t nc,
+                                  int32_t ppw, int32_t cand)
+{
+    clear_error();
+    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+    if (scale < 0 || scale >= p->s || k_bucket_ < 0 || k_bucket_ > 2)
+        return set_error(CSPD_E_INVALID, "scale %d / bucket %d out of range", scale, k_bucket_);
+    KernelChoice c;
+    if (kind != kChoiceAuto) {
+        if (cand < 1 || cand > p->sc[scale].t)
+            return set_error(CSPD_E_INVALID, "cand %d outside [1, T = %d]", cand, p->sc[scale].t);
+        // the variants that can run this scale at this candidate count
+        ScaleArgs a = base_args(p, scale, 1, nullptr, nullptr);
+        a.first = scale == 0;
+        a.last = scale + 1 == p->s;
+        a.kvec = nullptr;
+        a.kuni = a.sup_count = 4 << k_bucket_;   // largest K of the bucket
+        KernelChoice ch[24];
+        const int nch = scale_choices(p->dtype, a, cand, p->sc[scale].gram != nullptr, ch, 24);
+        int hit = -1;
+        for (int i = 0; i < nch && hit < 0; ++i)
+            if (ch[i].kind == kind && (kind == kChoiceFirstMfma || (ch[i].nc == nc && ch[i].ppw == ppw))) hit = i;
+        if (hit < 0)
+            return set_error(CSPD_E_UNSUPPORTED, "scale %d: no kernel kind %d (nc %d, ppw %d) for %d candidates",
+                             scale, kind, nc, ppw, cand);
+        c = ch[hit];
+        c.cand = cand;
+    }
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->tuned[scale][k_bucket_] = c;
+    return CSPD_OK;
 }
 
 }  // extern "C"

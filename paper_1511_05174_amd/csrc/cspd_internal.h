@@ -58,6 +58,17 @@ struct ScalePlan {
 
 }  // namespace cspd
 
+namespace cspd {
+// A kernel variant for one scale (autotuned or chosen by shape rules).
+enum ChoiceKind { kChoiceAuto = 0, kChoiceFirstMfma = 1, kChoiceVec = 2, kChoiceGram = 3, kChoiceMfmaGram = 4 };
+struct KernelChoice {
+    int kind = kChoiceAuto;
+    int nc = 1;
+    int ppw = 1;
+    int cand = 0;   // candidate count it was timed on; used only for that count
+};
+}  // namespace cspd
+
 struct cspd_plan_s {
     int s = 0;           // scales
     int n = 0;           // finest dimension
@@ -71,7 +82,9 @@ struct cspd_plan_s {
     int64_t bytes = 0;
     cspd::ScalePlan sc[CSPD_MAX_SCALES];
     void *d_high = nullptr;   // T_high x N atom-contiguous (plan dtype), for x-hat
-    std::mutex mu;
+    // autotuned kernel per scale and sparsity bucket (K <= 4, <= 8, <= 16)
+    cspd::KernelChoice tuned[CSPD_MAX_SCALES][3];
+    mutable std::mutex mu;   // guards tuned
 };
 
 namespace cspd {
@@ -112,6 +125,15 @@ struct ScaleArgs {
     const void *d_high;         // T_high x n (last)
 };
 
+// Kernel variants that can run one scale (FP32): the first-scale MFMA kernel,
+// the MFMA-Gram kernel, the register shapes and the Gram-table kernel that
+// hold `max_cand` candidates.  Returns how many were written (at most cap).
+int scale_choices(int dtype, const ScaleArgs &a, int max_cand, bool has_gram, KernelChoice *out, int cap);
+// Launches one scale with an explicit variant.
+cspd_status launch_choice(int dtype, const ScaleArgs &a, const KernelChoice &c, hipStream_t stream);
+// Sparsity bucket of a scale's launch (0: K <= 4, 1: <= 8, 2: <= 16).
+int k_bucket(const ScaleArgs &a);
+
 // Selects and launches the per-scale kernel; returns CSPD_E_UNSUPPORTED when
 // no instantiation fits.
 cspd_status launch_scale(int dtype, const ScaleArgs &a, int max_candidates, bool gram_mode,
@@ -119,6 +141,8 @@ cspd_status launch_scale(int dtype, const ScaleArgs &a, int max_candidates, bool
 
 // First scale of a cross-scale call on the matrix cores (shared dictionary,
 // 16 patches per wavefront); CSPD_E_UNSUPPORTED when the shape does not fit.
+// Whether the first-scale matrix-core kernel has an instance for this scale.
+bool first_mfma_fits(int dtype, const ScaleArgs &a);
 cspd_status launch_first_mfma(int dtype, const ScaleArgs &a, hipStream_t stream);
 
 // Full-dictionary proxy on matrix cores (large T).

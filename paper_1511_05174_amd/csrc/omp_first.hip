@@ -340,13 +340,21 @@ cspd_status launch(const ScaleArgs &a, hipStream_t st)
 // FP32, a uniform sparsity of at most 8, a vector length of at most 16 with
 // up to 128 atoms (or 32 with up to 64), and fold plans with at most 64 fine
 // samples.  Returns CSPD_E_UNSUPPORTED otherwise (nothing is launched).
+bool first_mfma_fits(int dtype, const ScaleArgs &a)
+{
+    using namespace first_impl;
+    if (dtype != CSPD_F32 || !a.first || a.last || a.kvec) return false;
+    if (a.fold == kFold && a.n > NMAX) return false;
+    const int k = a.kuni < a.sup_count ? a.kuni : a.sup_count;
+    if (k > 8) return false;
+    return (a.l <= 16 && a.t <= 128) || (a.l <= 32 && a.t <= 64);
+}
+
 cspd_status launch_first_mfma(int dtype, const ScaleArgs &a, hipStream_t st)
 {
     using namespace first_impl;
-    if (dtype != CSPD_F32 || !a.first || a.last || a.kvec) return CSPD_E_UNSUPPORTED;
-    if (a.fold == kFold && a.n > NMAX) return CSPD_E_UNSUPPORTED;
+    if (!first_mfma_fits(dtype, a)) return CSPD_E_UNSUPPORTED;
     const int k = a.kuni < a.sup_count ? a.kuni : a.sup_count;
-    if (k > 8) return CSPD_E_UNSUPPORTED;
     if (a.b <= 0) return CSPD_OK;
     const bool k4 = k <= 4;
     if (a.l <= 16) {

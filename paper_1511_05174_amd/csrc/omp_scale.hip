@@ -73,4 +73,41 @@ cspd_status launch_scale(int dtype, const ScaleArgs &a, int max_cand, bool gram,
     return dispatch_scale_f32_k16(a, a.lp, nc, ppw, gram, mg, st);
 }
 
+int k_bucket(const ScaleArgs &a)
+{
+    const int k = a.sup_count < kMaxK ? a.sup_count : kMaxK;
+    const int kreq = a.kvec ? k : (a.kuni < k ? a.kuni : k);
+    return kreq <= 4 ? 0 : (kreq <= 8 ? 1 : 2);
+}
+
+int scale_choices(int dtype, const ScaleArgs &a, int max_cand, bool has_gram, KernelChoice *out, int cap)
+{
+    int n = 0;
+    auto add = [&](int kind, int nc, int ppw) {
+        if (n < cap) { out[n].kind = kind; out[n].nc = nc; out[n].ppw = ppw; ++n; }
+    };
+    if (dtype != CSPD_F32) return 0;
+    if (first_mfma_fits(dtype, a)) add(kChoiceFirstMfma, 1, 1);
+    if (max_cand <= 32 && a.lp <= 64) add(kChoiceMfmaGram, 1, 2);
+    for (const VecShape &v : kVec)
+        if (v.lp == a.lp && v.nc * (64 / v.ppw) >= max_cand) add(kChoiceVec, v.nc, v.ppw);
+    if (has_gram) {
+        const int nc = pow2_at_least((max_cand + 63) / 64);
+        if (nc <= 16 && a.lp <= 256) add(kChoiceGram, nc, 1);
+    }
+    return n;
+}
+
+cspd_status launch_choice(int dtype, const ScaleArgs &a, const KernelChoice &c, hipStream_t st)
+{
+    if (dtype != CSPD_F32) return CSPD_E_UNSUPPORTED;
+    if (a.b <= 0) return CSPD_OK;
+    if (c.kind == kChoiceFirstMfma) return launch_first_mfma(dtype, a, st);
+    const bool gram = c.kind == kChoiceGram, mg = c.kind == kChoiceMfmaGram;
+    const int kb = k_bucket(a);
+    if (kb == 0) return dispatch_scale_f32_k4(a, a.lp, c.nc, c.ppw, gram, mg, st);
+    if (kb == 1) return dispatch_scale_f32_k8(a, a.lp, c.nc, c.ppw, gram, mg, st);
+    return dispatch_scale_f32_k16(a, a.lp, c.nc, c.ppw, gram, mg, st);
+}
+
 }  // namespace cspd
