@@ -102,51 +102,116 @@ def snr_db(x, xhat):
     return float(20 * np.log10(np.linalg.norm(x) / np.linalg.norm(x - xhat)))
 
 
-def serve_phase(cspd, plan, w, ks, gpu_rate, jobs=300, seed=11):
-    """Jobs of log-uniform size in [1024, 16384] patches (slices of the
-    workload) arrive as a Poisson process; the offered load is half of the
-    serving loop's measured capacity.  Returns p50 / p99 job latency."""
+SERVE_SHAPES = ("c5a", "c5b", "c5c")
+
+
+def serve_phase(cspd, jobs=2000, loads=(0.5, 0.8, 0.95), budget=4 << 30, slots=4, pool=32768,
+                bmax=262144, burst=150, seed=11):
+    """Serving on the three job shapes (64-d image, 512-d video, 400-d light
+    field; Gaussian Phi at 25 %, K_low 4): job sizes log-uniform integers in
+    [1024, bmax] patches, shape uniform, each job's K_fine uniform in 6..16.
+    Capacity = patches/s of a burst of `burst` jobs submitted at once; then
+    `jobs` Poisson arrivals at each offered load (fraction of capacity).
+    Inputs and outputs are pinned host buffers; latency = finish - submit as
+    the server records it (queueing, admission, PCIe both ways, kernels)."""
+    import torch
+
+    import synth
+
     rng = np.random.default_rng(seed)
-    sizes = np.exp(rng.uniform(np.log(1024), np.log(16384), size=jobs)).astype(int)
-    starts = rng.integers(0, w.batch - 16384, size=jobs)
-    ndt = np.float32 if plan.dtype == "f32" else np.float64
-    y = np.ascontiguousarray(w.y.astype(ndt))
-    kf = w.k_fine
+    shapes = {}
+    for name in SERVE_SHAPES:
+        w = synth.make(name, batch=pool)
+        plan = cspd.plan_from_workload(w)
+        y = torch.empty((bmax, w.m), dtype=torch.float32, pin_memory=True).numpy()
+        y[:] = np.tile(w.y.astype(np.float32), (bmax // pool, 1))
+        shapes[name] = (w, plan, y)
 
-    def submit(srv, i):
-        a, n = int(starts[i]), int(sizes[i])
-        return cspd.cspd_serve_submit(srv, plan, y[a:a + n], None if w.mask is None else w.mask[a:a + n],
-                                      None if kf is None else kf[a:a + n], ks[-1], ks[:-1],
-                                      want_coef=True, want_xhat=True)
+    def draw(n):
+        size = np.floor(np.exp(rng.uniform(np.log(1024), np.log(bmax + 1), size=n))).astype(np.int64)
+        size = np.clip(size, 1024, bmax)
+        return dict(shape=rng.integers(0, len(SERVE_SHAPES), size=n), size=size,
+                    start=np.array([rng.integers(0, bmax - b + 1) for b in size]),
+                    k=rng.integers(6, 17, size=n))
 
-    srv = cspd.cspd_serve_create(0, 8 << 30, 4)
-    # capacity: a burst of the first 60 jobs
+    def pinned(shape, dt):
+        return torch.empty(shape, dtype=dt, pin_memory=True).numpy()
+
+    def submit(srv, d, i, held):
+        name = SERVE_SHAPES[int(d["shape"][i])]
+        w, plan, y = shapes[name]
+        n, a = int(d["size"][i]), int(d["start"][i])
+        out = {"support": pinned((n, plan.k_max), torch.int32), "k_used": pinned((n,), torch.int32),
+               "coef": pinned((n, plan.k_max), torch.float32), "xhat": pinned((n, plan.n), torch.float32)}
+        jid = cspd.cspd_serve_submit(srv, plan, y[a:a + n], None, None, int(d["k"][i]), w.k_scales[:-1], out=out)
+        held[jid] = (name, n)
+        return jid
+
+    def collect(srv, held, rows, block):
+        for jid in list(held):
+            r = cspd.cspd_serve_poll(srv, jid, -1 if block else 0)
+            if r is None:
+                continue
+            _, st = r
+            name, n = held.pop(jid)
+            rows.append((name, n, (st["finish_ns"] - st["submit_ns"]) * 1e-6,
+                         (st["admit_ns"] - st["submit_ns"]) * 1e-6, st["batched_with"] > 0))
+
+    srv = cspd.cspd_serve_create(0, budget, slots)
+    # warm-up: one small job per shape (plans' kernels, pinned-memory cache)
+    held, rows = {}, []
+    for si in range(len(SERVE_SHAPES)):
+        submit(srv, dict(shape=[si], size=[4096], start=[0], k=[8]), 0, held)
+    collect(srv, held, rows, True)
+    d = draw(burst)
+    rows = []
     t0 = time.perf_counter()
-    ids = [submit(srv, i) for i in range(60)]
-    for j in ids:
-        cspd.cspd_serve_poll(srv, j, -1)
-    cap = float(np.sum(sizes[:60])) / (time.perf_counter() - t0)
-    rate = 0.5 * cap / float(np.mean(sizes))          # jobs per second
-    gaps = rng.exponential(1.0 / rate, size=jobs)
-    lat = []
-    batched = 0
-    pending = []
-    t_next = time.perf_counter()
-    for i in range(jobs):
-        t_next += gaps[i]
-        while time.perf_counter() < t_next:
-            pass
-        pending.append(submit(srv, i))
-    for j in pending:
-        out, st = cspd.cspd_serve_poll(srv, j, -1)
-        lat.append((st["finish_ns"] - st["submit_ns"]) * 1e-6)
-        batched += st["batched_with"] > 0
+    for i in range(burst):
+        submit(srv, d, i, held)
+    collect(srv, held, rows, True)
+    cap = float(d["size"].sum()) / (time.perf_counter() - t0)
+    mean_size = (bmax + 1 - 1024) / np.log((bmax + 1) / 1024.0)
+    out = {"shapes": {n: f"{shapes[n][0].dims} atoms {shapes[n][0].atoms} M {shapes[n][0].m}"
+                      for n in SERVE_SHAPES},
+           "job_patches": f"log-uniform integer in [1024, {bmax}]", "k_fine": "uniform 6..16 per job",
+           "capacity_patches_per_s": cap, "capacity_burst_jobs": burst, "slots": slots,
+           "hbm_budget_bytes": budget, "jobs_per_load": jobs, "loads": {}}
+    for load in loads:
+        d = draw(jobs)
+        rate = load * cap / mean_size
+        gaps = rng.exponential(1.0 / rate, size=jobs)
+        rows = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        for i in range(jobs):
+            t_next += gaps[i]
+            while time.perf_counter() < t_next:
+                if held:
+                    collect(srv, held, rows, False)
+            submit(srv, d, i, held)
+        collect(srv, held, rows, True)
+        wall = time.perf_counter() - t_start
+        lat = np.array([r[2] for r in rows])
+        adm = np.array([r[3] for r in rows])
+        ent = {"rate_jobs_per_s": rate, "wall_s": wall, "patches_per_s": float(d["size"].sum()) / wall,
+               "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "mean_ms": float(lat.mean()), "admission_wait_p99_ms": float(np.percentile(adm, 99)),
+               "batched_jobs": int(sum(r[4] for r in rows)), "per_shape": {}}
+        for name in SERVE_SHAPES:
+            ls = np.array([r[2] for r in rows if r[0] == name])
+            if len(ls):
+                ent["per_shape"][name] = {"jobs": int(len(ls)), "p50_ms": float(np.percentile(ls, 50)),
+                                          "p99_ms": float(np.percentile(ls, 99))}
+        small = np.array([r[2] for r in rows if r[1] <= 8192])
+        if len(small):
+            ent["small_jobs_le_8192"] = {"jobs": int(len(small)), "p50_ms": float(np.percentile(small, 50)),
+                                         "p99_ms": float(np.percentile(small, 99))}
+        out["loads"][str(load)] = ent
+        print(f"[bench] serving load {load}: {json.dumps(ent)}", file=sys.stderr, flush=True)
     cspd.cspd_serve_destroy(srv)
-    lat = np.array(lat)
-    return {"jobs": jobs, "job_patches": "log-uniform 1024..16384", "capacity_patches_per_s": cap,
-            "offered_load": 0.5, "rate_jobs_per_s": rate, "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)), "batched_jobs": int(batched),
-            "slots": 4, "hbm_budget_bytes": 8 << 30, "note": "host buffers in pageable memory; latency includes PCIe copies"}
+    for name in SERVE_SHAPES:
+        cspd.cspd_plan_destroy(shapes[name][1])
+    return out
 
 
 def precision_phase(cspd, steps: int = 3):
@@ -356,6 +421,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=2000, help="Poisson arrivals per offered load")
     ap.add_argument("--cpu-sample", type=int, default=65536,
                     help="patches of the workload the oracle is timed on")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -519,11 +585,12 @@ def main():
                   f"{p['full']['patches_per_s']:.3e}/s -> cross {p['cross']} speedup {p['speedup']}",
                   file=sys.stderr, flush=True)
 
-    # ---- serving: Poisson arrivals of jobs of this workload's shape
+    # ---- serving: Poisson arrivals of jobs of three shapes
     serving = None
     if not args.no_serve:
-        serving = serve_phase(cspd, plan, w, ks, B / t_cross)
-        print(f"[bench] serving: {serving}", file=sys.stderr, flush=True)
+        serving = serve_phase(cspd, jobs=args.serve_jobs)
+        print(f"[bench] serving capacity {serving['capacity_patches_per_s']:.3e} patches/s",
+              file=sys.stderr, flush=True)
 
     # ---- batching: captured HIP graphs against eager calls
     graphs = None

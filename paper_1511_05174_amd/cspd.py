@@ -418,9 +418,11 @@ def cspd_serve_create(device: int = 0, hbm_budget_bytes: int = 16 << 30, max_slo
 def cspd_serve_submit(server: Server, plan: Plan, y: np.ndarray, mask: Optional[np.ndarray] = None,
                       k_fine: Optional[np.ndarray] = None, k_fine_uniform: int = 0,
                       k_scale: Sequence[int] = (), full: bool = False, want_coef: bool = True,
-                      want_xhat: bool = True) -> int:
+                      want_xhat: bool = True, out: Optional[dict] = None) -> int:
     """Queue a job on host arrays; returns its id.  Outputs are collected by
-    cspd_serve_poll."""
+    cspd_serve_poll.  `out` may hold caller-owned output arrays ("support",
+    "k_used", and "coef" / "xhat" when wanted; e.g. views of pinned memory);
+    the others are allocated here."""
     ndt = np.float64 if plan.dtype == "f64" else np.float32
     y = np.ascontiguousarray(y, dtype=ndt)
     B = y.shape[0]
@@ -431,12 +433,19 @@ def cspd_serve_submit(server: Server, plan: Plan, y: np.ndarray, mask: Optional[
         bufs["mask"] = np.ascontiguousarray(mask, dtype=np.uint8)
     if k_fine is not None:
         bufs["k_fine"] = np.ascontiguousarray(k_fine, dtype=np.int32)
-    bufs["support"] = np.empty((B, plan.k_max), dtype=np.int32)
-    bufs["k_used"] = np.empty((B,), dtype=np.int32)
+    shapes = {"support": ((B, plan.k_max), np.int32), "k_used": ((B,), np.int32)}
     if want_coef:
-        bufs["coef"] = np.empty((B, plan.k_max), dtype=ndt)
+        shapes["coef"] = ((B, plan.k_max), ndt)
     if want_xhat:
-        bufs["xhat"] = np.empty((B, plan.n), dtype=ndt)
+        shapes["xhat"] = ((B, plan.n), ndt)
+    out = out or {}
+    for name, (shape, dt) in shapes.items():
+        a = out.get(name)
+        if a is None:
+            a = np.empty(shape, dtype=dt)
+        elif a.shape != shape or a.dtype != dt or not a.flags.c_contiguous or not a.flags.writeable:
+            raise ValueError(f"out[{name!r}] must be a writeable contiguous {shape} {np.dtype(dt).name} array")
+        bufs[name] = a
     j = Job()
     j.plan = plan.handle
     j.B = B
