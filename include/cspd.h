@@ -264,27 +264,29 @@ typedef struct cspd_job {
 /* Timestamps (CLOCK_MONOTONIC nanoseconds) of one finished job. */
 typedef struct cspd_job_stats {
     int64_t submit_ns;   /* cspd_serve_submit called */
-    int64_t admit_ns;    /* device memory and a slot granted */
+    int64_t admit_ns;    /* device memory and a slot granted (first piece) */
     int64_t start_ns;    /* its first launch was enqueued */
     int64_t finish_ns;   /* its results were back in host memory */
     int64_t patches;
-    int32_t batched_with; /* other jobs that shared its launch */
+    int32_t batched_with; /* most other jobs that shared one of its launches */
     int32_t status;      /* CSPD_OK or the error that failed the job */
 } cspd_job_stats;
 
 /*
  * Create a server on `device` with an HBM budget for job buffers (bytes,
  * > 0) and at most `max_slots` (1..64) launches in flight, each on its own
- * stream.  A background thread admits queued jobs in arrival order when
- * their buffers fit in the budget, packs waiting jobs of the same plan and
- * kind into one launch, copies in, launches, copies out and retires them.
+ * stream.  Jobs are cut into pieces of at most 65,536 patches.  A
+ * background thread admits queued pieces in arrival order when their
+ * buffers fit in the budget, packs waiting pieces of the same plan and kind
+ * into one launch (at most 65,536 patches), copies in, launches, copies out
+ * and retires them; a job finishes with its last piece.
  * Errors: E_INVALID, E_DEVICE, E_NOMEM.
  */
 cspd_status cspd_serve_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slots,
                               cspd_server_t *out);
 
-/* Queue a job (non-blocking).  E_CAPACITY if it can never fit the budget;
- * E_INVALID / E_SHAPE for a malformed job. */
+/* Queue a job (non-blocking).  E_CAPACITY if one of its pieces can never
+ * fit the budget; E_INVALID / E_SHAPE for a malformed job. */
 cspd_status cspd_serve_submit(cspd_server_t server, const cspd_job *job, uint64_t *job_id);
 
 /* Wait up to timeout_us (0 = just look, < 0 = forever) for a job.  Returns

@@ -51,6 +51,20 @@ bool scale_vec_fits(int lp, int max_cand, bool f64)
     return scale_vec_shape(lp, max_cand, f64, &nc, &ppw);
 }
 
+// Whether the matrix-core Gram kernel has an instance for this shape.
+bool mg_fits(int lp, int max_cand, int ppw)
+{
+    if (ppw == 2) return max_cand <= 32 && lp >= 16 && lp <= 128;
+    return max_cand <= 64 && lp >= 32 && lp <= 128;
+}
+
+cspd_status dispatch_mg(const ScaleArgs &a, int ppw, int kreq, hipStream_t st)
+{
+    if (kreq <= 4) return dispatch_scale_f32_k4(a, a.lp, 1, ppw, false, true, st);
+    if (kreq <= 8) return dispatch_scale_f32_k8(a, a.lp, 1, ppw, false, true, st);
+    return dispatch_scale_f32_k16(a, a.lp, 1, ppw, false, true, st);
+}
+
 cspd_status launch_scale(int dtype, const ScaleArgs &a, int max_cand, bool gram, hipStream_t st)
 {
     if (a.b <= 0) return CSPD_OK;
@@ -64,10 +78,11 @@ cspd_status launch_scale(int dtype, const ScaleArgs &a, int max_cand, bool gram,
     const int k = a.sup_count < kMaxK ? a.sup_count : kMaxK;
     const int kreq = a.kvec ? k : (a.kuni < k ? a.kuni : k);
     if (dtype == CSPD_F64) return dispatch_scale_f64_k16(a, a.lp, nc, ppw, gram, st);
-    // up to 32 candidates of length <= 64: each patch's candidate Gram matrix
-    // on the matrix cores, two patches per wavefront
-    const bool mg = !gram && max_cand <= 32 && a.lp <= 64;
+    // each patch's candidate Gram matrix on the matrix cores: up to 32
+    // candidates with two patches per wavefront, up to 64 with one
+    const bool mg = !gram && mg_fits(a.lp, max_cand, 2);
     if (mg) { nc = 1; ppw = 2; }
+    else if (!gram && mg_fits(a.lp, max_cand, 1)) return dispatch_mg(a, 1, kreq, st);
     if (kreq <= 4) return dispatch_scale_f32_k4(a, a.lp, nc, ppw, gram, mg, st);
     if (kreq <= 8) return dispatch_scale_f32_k8(a, a.lp, nc, ppw, gram, mg, st);
     return dispatch_scale_f32_k16(a, a.lp, nc, ppw, gram, mg, st);
@@ -88,7 +103,8 @@ int scale_choices(int dtype, const ScaleArgs &a, int max_cand, bool has_gram, Ke
     };
     if (dtype != CSPD_F32) return 0;
     if (first_mfma_fits(dtype, a)) add(kChoiceFirstMfma, 1, 1);
-    if (max_cand <= 32 && a.lp <= 64) add(kChoiceMfmaGram, 1, 2);
+    if (mg_fits(a.lp, max_cand, 2)) add(kChoiceMfmaGram, 1, 2);
+    if (mg_fits(a.lp, max_cand, 1)) add(kChoiceMfmaGram, 1, 1);
     for (const VecShape &v : kVec)
         if (v.lp == a.lp && v.nc * (64 / v.ppw) >= max_cand) add(kChoiceVec, v.nc, v.ppw);
     if (has_gram) {

@@ -8,9 +8,16 @@ cspd_status dispatch_scale_f32_k16(const ScaleArgs &a, int lp, int nc, int ppw, 
 {
     using namespace scale_impl;
     if (mg) {
-        if (lp == 16) return launch_one<float, 16, 1, 2, 16, false, true>(a, st);
-        if (lp == 32) return launch_one<float, 32, 1, 2, 16, false, true>(a, st);
-        if (lp == 64) return launch_one<float, 64, 1, 2, 16, false, true>(a, st);
+        if (ppw == 2) {
+            if (lp == 16) return launch_one<float, 16, 1, 2, 16, false, true>(a, st);
+            if (lp == 32) return launch_one<float, 32, 1, 2, 16, false, true>(a, st);
+            if (lp == 64) return launch_one<float, 64, 1, 2, 16, false, true>(a, st);
+            if (lp == 128) return launch_one<float, 128, 1, 2, 16, false, true>(a, st);
+        } else if (ppw == 1) {
+            if (lp == 32) return launch_one<float, 32, 1, 1, 16, false, true>(a, st);
+            if (lp == 64) return launch_one<float, 64, 1, 1, 16, false, true>(a, st);
+            if (lp == 128) return launch_one<float, 128, 1, 1, 16, false, true>(a, st);
+        }
         return CSPD_E_UNSUPPORTED;
     }
     if (gram) {

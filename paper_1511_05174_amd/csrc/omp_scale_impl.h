@@ -333,12 +333,13 @@ template <typename T, int LP, int NC, int PPW, int KM, bool GRAM, bool MG>
 __global__ __launch_bounds__(64 * W)
 void k_omp_scale(ScaleArgs a)
 {
-    static_assert(!MG || (sizeof(T) == 4 && NC == 1 && PPW == 2 && !GRAM && LP <= 64),
-                  "matrix-core Gram: FP32, one slot, two patches per wavefront");
+    static_assert(!MG || (sizeof(T) == 4 && NC == 1 && (PPW == 1 || PPW == 2) && !GRAM && LP >= 16 && LP <= 128),
+                  "matrix-core Gram: FP32, one slot, one or two patches per wavefront");
     constexpr int G = 64 / PPW;
     constexpr int LPA = GRAM ? LP_GRAM : LP;
     constexpr int VL = (GRAM || MG) ? 1 : LP;   // per-slot vector registers
     constexpr int LH = MG ? LP / 2 : 1;         // coordinates per lane and patch (matrix-core Gram)
+    constexpr int NGM = (MG && PPW == 1) ? 4 : 2;   // 32 x 32 Gram blocks per wavefront
     __shared__ GroupLds<T, LPA, KM> lds[W * PPW];
     __shared__ double lds64[W][KX * KX + 4 * KX];
     extern __shared__ double dyn_lds[];     // block-fold staging (fold_lds_bytes)
@@ -346,6 +347,7 @@ void k_omp_scale(ScaleArgs a)
     const int wv = threadIdx.x >> 6;
     const int gi = lane / G;
     const int gl = lane % G;
+    const int hh = lane >> 5;   // lane half (matrix-core Gram)
     const int64_t wave_first = ((int64_t)blockIdx.x * W + wv) * PPW;
     if (wave_first >= a.b) return;          // the whole wavefront leaves together
     const int64_t b = wave_first + gi;
@@ -370,31 +372,42 @@ void k_omp_scale(ScaleArgs a)
     int atom[NC];
     bool live[NC];
     const T *src[NC];
-    // Matrix-core Gram: lane l holds candidate l % 32 of both patches of the
-    // wavefront, coordinates [(l / 32) LH, (l / 32 + 1) LH) of each (the
-    // MFMA's two k rows split the coordinates in halves).
-    T vm[MG ? 2 : 1][LH];
+    // Matrix-core Gram: with two patches per wavefront lane l holds candidate
+    // l % 32 of both patches; with one patch (up to 64 candidates) it holds
+    // candidates l % 32 and 32 + l % 32 (blocks 0 and 1).  Either way it holds
+    // coordinates [(l / 32) LH, (l / 32 + 1) LH) of each (the MFMA's two k
+    // rows split the coordinates in halves).
+    // Long vectors go through the matrix cores in chunks of MCH coordinates
+    // (loaded chunk by chunk), so that few registers hold them at a time.
+    constexpr int MCH = (MG && (PPW == 1 || LH >= 64)) ? 16 : LH;
+    T vm[MG ? 2 : 1][MCH];
+    T vn[MG && MCH < LH ? 2 : 1][MCH < LH ? MCH : 1];   // next chunk, in flight
+    const T *msrc[2] = {nullptr, nullptr};
     bool livep[2] = {false, false};
     int nc = 0;
     auto candidates = [&](int ncand, int pvv) {
         nc = ncand;
         if constexpr (MG) {
-            const int hh = lane >> 5;
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                const int ncp = __builtin_amdgcn_readlane(ncand, p * 32);
-                livep[p] = gl < ncp;
-                int at = gl;
+                // two patches: slot p is patch p's candidate gl; one patch:
+                // slot p is candidate 32 p + gl % 32
+                const int ncp = __builtin_amdgcn_readlane(ncand, PPW == 2 ? p * 32 : 0);
+                const int ci = PPW == 2 ? gl : 32 * p + (lane & 31);
+                livep[p] = ci < ncp;
+                int at = ci;
                 if (!a.first) {
-                    const int pj = livep[p] ? gl / a.q : 0;
-                    const int pi = __shfl(pvv, p * 32 + pj, 64);
-                    at = pi * a.q + gl % a.q;
+                    const int pj = livep[p] ? ci / a.q : 0;
+                    const int pi = __shfl(pvv, (PPW == 2 ? p * 32 : 0) + pj, 64);
+                    at = pi * a.q + ci % a.q;
                 }
-                const T *sp = (const T *)a.v + (int64_t)(livep[p] ? at : 0) * LP + hh * LH;
+                msrc[p] = (const T *)a.v + (int64_t)(livep[p] ? at : 0) * LP + hh * LH;
+                if constexpr (MCH == LH) {
 #pragma unroll
-                for (int j = 0; j < LH; j += 4) {
-                    const float4 q = *reinterpret_cast<const float4 *>(sp + j);
-                    vm[p][j] = q.x; vm[p][j + 1] = q.y; vm[p][j + 2] = q.z; vm[p][j + 3] = q.w;
+                    for (int j = 0; j < LH; j += 4) {
+                        const float4 q = *reinterpret_cast<const float4 *>(msrc[p] + j);
+                        vm[p][j] = q.x; vm[p][j + 1] = q.y; vm[p][j + 2] = q.z; vm[p][j + 3] = q.w;
+                    }
                 }
             }
         }
@@ -562,48 +575,84 @@ void k_omp_scale(ScaleArgs a)
 #pragma unroll
     for (int s = 0; s < NC; ++s) { h[s] = T(0); ee[s] = T(0); }
     typedef float gram_t __attribute__((ext_vector_type(16)));
-    gram_t gm[2];
+    gram_t gm[NGM];
     if constexpr (MG) {
         // weighted candidates, their correlations with y-hat and squared norms
         // (each lane sums its half of the coordinates, the halves are added)
-        const int hh = lane >> 5;
+        // Gram matrices on the matrix cores: lane l ends with column l % 32,
+        // rows 8 (r / 4) + 4 (l / 32) + r % 4 of each 32 x 32 block.  Two
+        // patches: block p is patch p's Gram matrix.  One patch: block 2 b + c
+        // holds the products of block-b candidates (rows) with block-c
+        // candidates (columns).
+        T hs[2] = {T(0), T(0)}, es[2] = {T(0), T(0)};
+#pragma unroll
+        for (int p = 0; p < NGM; ++p)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) gm[p][r] = 0.f;
+        // chunk c + 1 is requested before chunk c is used
+        auto load_chunk = [&](int c0, T (&dst)[2][MCH < LH ? MCH : 1]) {
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int j = 0; j < MCH; j += 4) {
+                    const float4 q = *reinterpret_cast<const float4 *>(msrc[p] + c0 + j);
+                    dst[p][j] = q.x; dst[p][j + 1] = q.y; dst[p][j + 2] = q.z; dst[p][j + 3] = q.w;
+                }
+        };
+        if constexpr (MCH < LH) load_chunk(0, vn);
+#pragma unroll
+        for (int c0 = 0; c0 < LH; c0 += MCH) {
+            if constexpr (MCH < LH) {
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int j = 0; j < MCH; ++j) vm[p][j] = vn[p][j];
+                if (c0 + MCH < LH) load_chunk(c0 + MCH, vn);
+            }
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const GroupLds<T, LPA, KM> &wp = lds[wv * PPW + (PPW == 2 ? p : 0)];
+#pragma unroll
+                for (int j = 0; j < MCH; ++j) {
+                    const T sw = wp.sqw[hh * LH + c0 + j], yh = wp.yhat[hh * LH + c0 + j];
+                    const T xv = vm[p][j] * sw;
+                    const T x = livep[p] ? xv : T(0);
+                    vm[p][j] = x;
+                    hs[p] += x * yh;
+                    es[p] += x * x;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < MCH; ++j) {
+                if constexpr (PPW == 2) {
+                    gm[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[0][j], vm[0][j], gm[0], 0, 0, 0);
+                    gm[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[1][j], vm[1][j], gm[1], 0, 0, 0);
+                } else {
+                    gm[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[0][j], vm[0][j], gm[0], 0, 0, 0);
+                    gm[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[0][j], vm[1][j], gm[1], 0, 0, 0);
+                    gm[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[1][j], vm[0][j], gm[2], 0, 0, 0);
+                    gm[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[1][j], vm[1][j], gm[3], 0, 0, 0);
+                }
+            }
+            // keep the chunks apart: at most one chunk in flight beyond this one
+            if constexpr (MCH < LH) __builtin_amdgcn_sched_barrier(0);
+        }
         T hf[2], ef[2];
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-            const GroupLds<T, LPA, KM> &wp = lds[wv * PPW + p];
-            T hs = 0, es = 0;
-#pragma unroll
-            for (int j = 0; j < LH; ++j) {
-                const T sw = wp.sqw[hh * LH + j], yh = wp.yhat[hh * LH + j];
-                const T xv = vm[p][j] * sw;
-                const T x = livep[p] ? xv : T(0);
-                vm[p][j] = x;
-                hs += x * yh;
-                es += x * x;
-            }
             T lo, hi;
-            swap_pair<32>(hs, lo, hi);
+            swap_pair<32>(hs[p], lo, hi);
             hf[p] = lo + hi;
-            swap_pair<32>(es, lo, hi);
+            swap_pair<32>(es[p], lo, hi);
             ef[p] = lo + hi;
         }
-        h[0] = gi ? hf[1] : hf[0];
-        ee[0] = gi ? ef[1] : ef[0];
-        // Gram matrices of both patches' candidates on the matrix cores:
-        // lane l ends with column l % 32, rows 8 (r / 4) + 4 (l / 32) + r % 4
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) gm[p][r] = 0.f;
-#pragma unroll
-        for (int j = 0; j < LH; ++j) {
-            gm[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[0][j], vm[0][j], gm[0], 0, 0, 0);
-            gm[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[1][j], vm[1][j], gm[1], 0, 0, 0);
-        }
+        // a lane's own candidate is in slot lane / 32 (patch or block)
+        h[0] = hh ? hf[1] : hf[0];
+        ee[0] = hh ? ef[1] : ef[0];
         // keep the Gram entries in ordinary VGPRs, where a row can be picked
         // by a wavefront-uniform register index
 #pragma unroll
-        for (int p = 0; p < 2; ++p)
+        for (int p = 0; p < NGM; ++p)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 float t = gm[p][r];
@@ -744,7 +793,7 @@ void k_omp_scale(ScaleArgs a)
         T gcol[NC];
 #pragma unroll
         for (int s = 0; s < NC; ++s) gcol[s] = T(0);
-        if constexpr (MG) {
+        if constexpr (MG && PPW == 2) {
             // the selected candidate's slot in each patch, then its row of the
             // Gram matrix (symmetric): row k, column gl lives in lane
             // gl + 32 ((k / 4) % 2), register 4 (k / 8) + k % 4
@@ -760,6 +809,25 @@ void k_omp_scale(ScaleArgs a)
             const float g0 = ((k0 >> 2) & 1) ? hi0 : lo0;
             const float g1 = ((k1 >> 2) & 1) ? hi1 : lo1;
             gcol[0] = gi ? g1 : g0;
+        } else if constexpr (MG) {
+            // one patch: the selected candidate k = 32 bk + kr; lane l needs
+            // entry (kr, l % 32) of block (bk, l / 32).  Row kr lives in lane
+            // half (kr / 4) % 2, register 4 (kr / 8) + kr % 4; a lane whose
+            // own half holds it reads it, the other lane of the pair gets it
+            // from its partner, which reads block (bk, 1 - partner half).
+            const unsigned long long own = __ballot(selected);
+            const int k = own ? __builtin_ctzll(own) : 0;
+            const int bk = k >> 5, kr = k & 31;
+            const int rk = 4 * (kr >> 3) + (kr & 3);
+            const int hk = (kr >> 2) & 1;
+            // block index by select: only the register index rk is dynamic
+            const float b00 = gm[0][rk], b01 = gm[1][rk], b10 = gm[2][rk], b11 = gm[3][rk];
+            const float b0 = bk ? b10 : b00, b1 = bk ? b11 : b01;
+            const float xo = hh ? b1 : b0;
+            const float xt = hh ? b0 : b1;
+            float lo, hi;
+            swap_pair<32>(xt, lo, hi);
+            gcol[0] = hk == hh ? xo : (hh ? lo : hi);
         } else if constexpr (!GRAM) {
             constexpr int CH = LP <= 16 ? LP : 8;
             T cur[CH], nxt[CH];
@@ -813,6 +881,9 @@ void k_omp_scale(ScaleArgs a)
         const T lw = act ? lnn : (n == 0 ? T(1) : lmin);
         lmin = n == 0 ? lw : (lw < lmin ? lw : lmin);
         nsel = act ? n + 1 : nsel;
+        // one patch per wavefront: iterations are strictly sequential, and
+        // keeping the scheduler within one bounds the registers in use
+        if constexpr (MG && PPW == 1) __builtin_amdgcn_sched_barrier(0);
     }
     wave_sync();
 
@@ -846,17 +917,35 @@ void k_omp_scale(ScaleArgs a)
                 alv[i] = in ? w.alpha[i] : T(0);
             }
             const T *vv = (const T *)a.v;
-            for (int t = gl; t < a.l; t += G) {
-                const double sq = (double)w.sqw[t];
-                double res = (double)w.yhat[t];
-                double av[KM];
+            // RU coordinates per lane at a time: all their loads are in
+            // flight together (one memory round trip per RU G coordinates)
+            constexpr int RU0 = GRAM ? 4 : ((LP + G - 1) / G > 4 ? 4 : (LP + G - 1) / G);
+            constexpr int RU = RU0 * KM > 16 ? (16 / KM > 0 ? 16 / KM : 1) : RU0;
+            static_assert(RU >= 1, "refinement batch");
+            for (int t0 = gl; t0 < a.l; t0 += G * RU) {
+                T raw[RU][KM];
+                // unconditional loads from valid addresses (atoms past nsel
+                // read atom 0 and carry alpha 0; coordinates past l are skipped
+                // below): a conditional load would become a branch and a wait
 #pragma unroll
-                for (int i = 0; i < KM; ++i) {
-                    av[i] = (double)vv[(int64_t)sid[i] * a.lp + t] * sq;
-                    res -= (double)alv[i] * av[i];
+                for (int u = 0; u < RU; ++u) {
+                    const int t = t0 + u * G;
+                    const int tc = t < a.l ? t : 0;
+#pragma unroll
+                    for (int i = 0; i < KM; ++i) raw[u][i] = vv[(int64_t)sid[i] * a.lp + tc];
                 }
 #pragma unroll
-                for (int i = 0; i < KM; ++i) part[i] += av[i] * res;
+                for (int u = 0; u < RU; ++u) {
+                    const int t = t0 + u * G;
+                    if (t < a.l) {
+                        const double sq = (double)w.sqw[t];
+                        double res = (double)w.yhat[t];
+#pragma unroll
+                        for (int i = 0; i < KM; ++i) res -= (double)alv[i] * ((double)raw[u][i] * sq);
+#pragma unroll
+                        for (int i = 0; i < KM; ++i) part[i] += ((double)raw[u][i] * sq) * res;
+                    }
+                }
             }
             T rme = 0;
 #pragma unroll
@@ -908,17 +997,35 @@ void k_omp_scale(ScaleArgs a)
     if (a.xhat) {
         const T *dh = (const T *)a.d_high;
         T *xh = (T *)a.xhat + b * (int64_t)a.n;
-        for (int j = gl; j < a.n; j += G) {
-            // every atom's sample is requested at once; unused terms add zero
-            T acc = 0;
+        int si[KM];
+        T alx[KM];
 #pragma unroll
-            for (int i = 0; i < KM; ++i) {
-                const bool in = i < nsel;
-                const int si = in ? w.sup[i] : 0;
-                const T al = in ? w.alpha[i] : T(0);
-                acc += al * dh[(int64_t)si * a.n + j];
+        for (int i = 0; i < KM; ++i) {
+            const bool in = i < nsel;
+            si[i] = in ? w.sup[i] : 0;
+            alx[i] = in ? w.alpha[i] : T(0);
+        }
+        // XU samples per lane at a time, every selected atom's sample of each
+        // requested before any is used (one memory round trip per XU G samples)
+        constexpr int XU = (32 / KM < 1 ? 1 : 32 / KM) / (sizeof(T) == 8 ? 2 : 1) > 0
+                               ? (32 / KM < 1 ? 1 : 32 / KM) / (sizeof(T) == 8 ? 2 : 1) : 1;
+        for (int j0 = gl; j0 < a.n; j0 += G * XU) {
+            T d[XU][KM];
+#pragma unroll
+            for (int u = 0; u < XU; ++u) {
+                const int j = j0 + u * G;
+                const int jc = j < a.n ? j : 0;   // a valid address; not stored
+#pragma unroll
+                for (int i = 0; i < KM; ++i) d[u][i] = dh[(int64_t)si[i] * a.n + jc];
             }
-            xh[j] = acc;
+#pragma unroll
+            for (int u = 0; u < XU; ++u) {
+                const int j = j0 + u * G;
+                T acc = 0;
+#pragma unroll
+                for (int i = 0; i < KM; ++i) acc += alx[i] * d[u][i];
+                if (j < a.n) xh[j] = acc;
+            }
         }
     }
 }

@@ -1,16 +1,20 @@
 // Serving loop: continuous batching of reconstruction jobs on one device.
 //
 // A background thread keeps up to `max_slots` launches in flight, each on its
-// own stream.  Jobs wait in arrival order; when a slot is free and the head
-// job's device buffers fit in the HBM budget, the head job and the jobs
-// queued right behind it that share its plan and its kind (zero-tree or full
-// OMP, same coarse sparsities) are packed into one launch, up to a patch cap.
-// Each launch copies its jobs' host inputs into fresh device buffers, runs
-// cspd_omp_cross_scale / cspd_omp_full over the packed batch, copies every
-// job's rows back to its own host buffers and records an event; the thread
-// retires launches whose events have completed and returns their memory to
-// the budget.  A patch's result does not depend on the other patches of a
-// launch, so a job gives the same result alone and in a mix.
+// own stream.  A job is cut into pieces of at most kPiece patches, so that
+// the copies in and out of one piece overlap the kernels of the others and a
+// large job spreads over several slots.  Pieces wait in arrival order; when a
+// slot is free and the head piece's device buffers fit in the HBM budget, the
+// head piece and the pieces queued right behind it that share its plan and
+// its kind (zero-tree or full OMP, same coarse sparsities) are packed into
+// one launch, up to kPiece patches.  Each launch copies its pieces' host
+// inputs into fresh device buffers, runs cspd_omp_cross_scale /
+// cspd_omp_full over the packed batch, copies every piece's rows back to its
+// job's host buffers and records an event; the thread retires launches whose
+// events have completed and returns their memory to the budget.  A job is
+// finished when its last piece is.  A patch's result does not depend on the
+// other patches of a launch, so a job gives the same result alone, in a mix
+// and cut into pieces.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,7 +33,7 @@ using namespace cspd;
 
 namespace {
 
-constexpr int64_t kMaxPatchesPerLaunch = 1 << 19;
+constexpr int64_t kPiece = 1 << 16;   // patches per piece and per launch
 
 int64_t now_ns()
 {
@@ -42,18 +46,28 @@ struct Job {
     cspd_job d{};
     uint64_t id = 0;
     cspd_job_stats st{};
-    int64_t bytes = 0;
+    int pieces_left = 0;
+    bool admitted = false;
+    bool started = false;
     bool done = false;
+};
+
+// Rows [row, row + b) of one job.
+struct Piece {
+    Job *job = nullptr;
+    int64_t row = 0;
+    int64_t b = 0;
+    int64_t bytes = 0;
 };
 
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
     bool busy = false;
-    std::vector<Job *> jobs;
+    std::vector<Piece> pieces;
     int64_t bytes = 0;
     int status = CSPD_OK;
-    std::vector<int32_t> kbuf;   // per-patch K of the packed batch (kept until retired)
+    int32_t *kbuf = nullptr;   // pinned: per-patch K of the packed batch (kept until retired)
 };
 
 size_t esize(const cspd_plan_s *p) { return p->dtype == CSPD_F64 ? sizeof(double) : sizeof(float); }
@@ -74,6 +88,7 @@ int64_t job_bytes(const cspd_plan_s *p, int64_t B)
 
 bool same_batch(const Job *a, const Job *b)
 {
+    if (a == b) return true;
     if (a->d.plan != b->d.plan || a->d.full != b->d.full) return false;
     if (a->d.full) return true;
     for (int s = 0; s + 1 < a->d.plan->s; ++s)
@@ -92,7 +107,7 @@ struct cspd_server_s {
     std::mutex mu;
     std::condition_variable wake;   // scheduler
     std::condition_variable fin;    // pollers
-    std::deque<Job *> queue;
+    std::deque<Piece> queue;
     std::unordered_map<uint64_t, Job *> jobs;
     std::vector<Slot> slots;
     std::thread worker;
@@ -104,31 +119,37 @@ struct cspd_server_s {
     void enqueue(Slot &sl);
 };
 
-// Pop the head job and the compatible jobs queued behind it into a free slot
-// (lock held).  Returns false when nothing can be admitted now.
+// Pop the head piece and the compatible pieces queued behind it into a free
+// slot (lock held).  Returns false when nothing can be admitted now.
 bool cspd_server_s::take_locked(Slot &sl)
 {
     if (queue.empty()) return false;
-    Job *head = queue.front();
-    if (used + head->bytes > budget) return false;   // wait for memory (arrival order is kept)
-    std::vector<Job *> take{head};
-    int64_t bytes = head->bytes, patches = head->d.B;
-    for (size_t i = 1; i < queue.size(); ++i) {
-        Job *j = queue[i];
-        if (!same_batch(head, j)) break;
-        if (patches + j->d.B > kMaxPatchesPerLaunch || used + bytes + j->bytes > budget) break;
-        take.push_back(j);
-        bytes += j->bytes;
-        patches += j->d.B;
+    const Piece &head = queue.front();
+    if (used + head.bytes > budget) return false;   // wait for memory (arrival order is kept)
+    size_t n = 1;
+    int64_t bytes = head.bytes, patches = head.b;
+    for (; n < queue.size(); ++n) {
+        const Piece &q = queue[n];
+        if (!same_batch(head.job, q.job)) break;
+        if (patches + q.b > kPiece || used + bytes + q.bytes > budget) break;
+        bytes += q.bytes;
+        patches += q.b;
     }
-    queue.erase(queue.begin(), queue.begin() + (long)take.size());
+    sl.pieces.assign(queue.begin(), queue.begin() + (long)n);
+    queue.erase(queue.begin(), queue.begin() + (long)n);
     used += bytes;
     const int64_t t_admit = now_ns();
-    for (Job *j : take) {
-        j->st.admit_ns = t_admit;
-        j->st.batched_with = (int32_t)take.size() - 1;
+    int jobs_here = 0;
+    for (size_t i = 0; i < n; ++i)
+        if (i == 0 || sl.pieces[i].job != sl.pieces[i - 1].job) ++jobs_here;
+    for (Piece &q : sl.pieces) {
+        Job *jb = q.job;
+        if (!jb->admitted) {
+            jb->admitted = true;
+            jb->st.admit_ns = t_admit;
+        }
+        if (jobs_here - 1 > jb->st.batched_with) jb->st.batched_with = jobs_here - 1;
     }
-    sl.jobs = take;
     sl.bytes = bytes;
     sl.busy = true;
     sl.status = CSPD_OK;
@@ -136,13 +157,13 @@ bool cspd_server_s::take_locked(Slot &sl)
 }
 
 // Copy in, launch and copy out one packed batch (lock not held; only the
-// scheduler thread touches slots).
+// scheduler thread touches slots and the started flags).
 void cspd_server_s::enqueue(Slot &sl)
 {
-    const std::vector<Job *> &take = sl.jobs;
-    Job *head = take.front();
+    const std::vector<Piece> &take = sl.pieces;
+    const Job *head = take.front().job;
     int64_t patches = 0;
-    for (Job *j : take) patches += j->d.B;
+    for (const Piece &q : take) patches += q.b;
     cspd_plan_s *p = head->d.plan;
     const int64_t B = patches;
     const size_t e = esize(p);
@@ -163,23 +184,26 @@ void cspd_server_s::enqueue(Slot &sl)
     char *dev = nullptr;
     if (hipMallocAsync((void **)&dev, off, sl.stream) != hipSuccess) rc = CSPD_E_NOMEM;
     const int64_t t_start = now_ns();
-    std::vector<int32_t> &kbuf = sl.kbuf;
-    kbuf.assign((size_t)B, 0);
+    int32_t *kbuf = sl.kbuf;
     if (rc == CSPD_OK) {
         int64_t row = 0;
-        for (Job *j : take) {
-            j->st.start_ns = t_start;
-            const int64_t b = j->d.B;
-            hipMemcpyAsync(dev + o_y + e * (size_t)row * p->m, j->d.y, e * (size_t)b * p->m,
-                           hipMemcpyHostToDevice, sl.stream);
+        for (const Piece &q : take) {
+            Job *j = q.job;
+            if (!j->started) {
+                j->started = true;
+                j->st.start_ns = t_start;
+            }
+            const int64_t b = q.b;
+            hipMemcpyAsync(dev + o_y + e * (size_t)row * p->m, (const char *)j->d.y + e * (size_t)q.row * p->m,
+                           e * (size_t)b * p->m, hipMemcpyHostToDevice, sl.stream);
             if (p->phi_kind == CSPD_PHI_MASK)
-                hipMemcpyAsync(dev + o_m + (size_t)row * p->n, j->d.mask, (size_t)b * p->n,
+                hipMemcpyAsync(dev + o_m + (size_t)row * p->n, j->d.mask + (size_t)q.row * p->n, (size_t)b * p->n,
                                hipMemcpyHostToDevice, sl.stream);
             for (int64_t i = 0; i < b; ++i)
-                kbuf[(size_t)(row + i)] = j->d.k_fine ? j->d.k_fine[i] : j->d.k_fine_uniform;
+                kbuf[row + i] = j->d.k_fine ? j->d.k_fine[q.row + i] : j->d.k_fine_uniform;
             row += b;
         }
-        hipMemcpyAsync(dev + o_k, kbuf.data(), sizeof(int32_t) * (size_t)B, hipMemcpyHostToDevice, sl.stream);
+        hipMemcpyAsync(dev + o_k, kbuf, sizeof(int32_t) * (size_t)B, hipMemcpyHostToDevice, sl.stream);
         if (head->d.full)
             rc = cspd_omp_full(p, B, dev + o_y, (const uint8_t *)(dev + o_m), (const int32_t *)(dev + o_k), 0,
                                (int32_t *)(dev + o_sup), dev + o_cf, (int32_t *)(dev + o_ku), dev + o_x,
@@ -189,19 +213,21 @@ void cspd_server_s::enqueue(Slot &sl)
                                       (const int32_t *)(dev + o_k), 0, (int32_t *)(dev + o_sup), dev + o_cf,
                                       (int32_t *)(dev + o_ku), dev + o_x, (int32_t *)(dev + o_sc), sl.stream);
         row = 0;
-        for (Job *j : take) {
-            const int64_t b = j->d.B;
+        for (const Piece &q : take) {
+            const Job *j = q.job;
+            const int64_t b = q.b;
+            const size_t r = (size_t)q.row;
             if (rc == CSPD_OK) {
-                hipMemcpyAsync(j->d.support, dev + o_sup + sizeof(int32_t) * (size_t)row * p->k_max,
+                hipMemcpyAsync(j->d.support + r * p->k_max, dev + o_sup + sizeof(int32_t) * (size_t)row * p->k_max,
                                sizeof(int32_t) * (size_t)b * p->k_max, hipMemcpyDeviceToHost, sl.stream);
-                hipMemcpyAsync(j->d.k_used, dev + o_ku + sizeof(int32_t) * (size_t)row,
+                hipMemcpyAsync(j->d.k_used + r, dev + o_ku + sizeof(int32_t) * (size_t)row,
                                sizeof(int32_t) * (size_t)b, hipMemcpyDeviceToHost, sl.stream);
                 if (j->d.coef)
-                    hipMemcpyAsync(j->d.coef, dev + o_cf + e * (size_t)row * p->k_max, e * (size_t)b * p->k_max,
-                                   hipMemcpyDeviceToHost, sl.stream);
+                    hipMemcpyAsync((char *)j->d.coef + e * r * p->k_max, dev + o_cf + e * (size_t)row * p->k_max,
+                                   e * (size_t)b * p->k_max, hipMemcpyDeviceToHost, sl.stream);
                 if (j->d.xhat)
-                    hipMemcpyAsync(j->d.xhat, dev + o_x + e * (size_t)row * p->n, e * (size_t)b * p->n,
-                                   hipMemcpyDeviceToHost, sl.stream);
+                    hipMemcpyAsync((char *)j->d.xhat + e * r * p->n, dev + o_x + e * (size_t)row * p->n,
+                                   e * (size_t)b * p->n, hipMemcpyDeviceToHost, sl.stream);
             }
             row += b;
         }
@@ -221,13 +247,16 @@ bool cspd_server_s::retire_locked()
         if (q == hipErrorNotReady) continue;
         const int status = q == hipSuccess ? sl.status : CSPD_E_DEVICE;
         const int64_t t = now_ns();
-        for (Job *j : sl.jobs) {
-            j->st.finish_ns = t;
-            j->st.status = status;
-            j->done = true;
+        for (Piece &pc : sl.pieces) {
+            Job *j = pc.job;
+            if (status != CSPD_OK && j->st.status == CSPD_OK) j->st.status = status;
+            if (--j->pieces_left == 0) {
+                j->st.finish_ns = t;
+                j->done = true;
+            }
         }
         used -= sl.bytes;
-        sl.jobs.clear();
+        sl.pieces.clear();
         sl.bytes = 0;
         sl.busy = false;
         any = true;
@@ -284,10 +313,12 @@ cspd_status cspd_serve_create(int32_t device, int64_t hbm_budget_bytes, int32_t 
     s->slots.resize((size_t)max_slots);
     for (Slot &sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) {
+            hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void **)&sl.kbuf, sizeof(int32_t) * kPiece, hipHostMallocDefault) != hipSuccess) {
             for (Slot &x : s->slots) {
                 if (x.stream) (void)hipStreamDestroy(x.stream);
                 if (x.ev) (void)hipEventDestroy(x.ev);
+                if (x.kbuf) (void)hipHostFree(x.kbuf);
             }
             delete s;
             (void)hipSetDevice(prev);
@@ -311,9 +342,6 @@ cspd_status cspd_serve_submit(cspd_server_t s, const cspd_job *job, uint64_t *jo
     if (job->B > 0 && (!job->y || !job->support || !job->k_used))
         return set_error(CSPD_E_INVALID, "y / support / k_used is NULL");
     if (job->B > 0 && p->phi_kind == CSPD_PHI_MASK && !job->mask) return set_error(CSPD_E_INVALID, "mask plan needs a mask");
-    if (job->B > kMaxPatchesPerLaunch)
-        return set_error(CSPD_E_CAPACITY, "job of %lld patches exceeds the %lld-patch launch cap", (long long)job->B,
-                         (long long)kMaxPatchesPerLaunch);
     if (!job->k_fine && (job->k_fine_uniform < 0 || job->k_fine_uniform > p->k_max))
         return set_error(CSPD_E_SHAPE, "k_fine_uniform %d outside [0, %d]", job->k_fine_uniform, p->k_max);
     if (!job->full)
@@ -324,13 +352,13 @@ cspd_status cspd_serve_submit(cspd_server_t s, const cspd_job *job, uint64_t *jo
         for (int64_t i = 0; i < job->B; ++i)
             if (job->k_fine[i] < 0 || job->k_fine[i] > p->k_max)
                 return set_error(CSPD_E_SHAPE, "k_fine[%lld] = %d outside [0, %d]", (long long)i, job->k_fine[i], p->k_max);
-    const int64_t bytes = job_bytes(p, job->B);
+    const int64_t bytes = job_bytes(p, job->B < kPiece ? job->B : kPiece);
     if (bytes > s->budget)
-        return set_error(CSPD_E_CAPACITY, "job needs %lld bytes, budget is %lld", (long long)bytes, (long long)s->budget);
+        return set_error(CSPD_E_CAPACITY, "a piece of the job needs %lld bytes, budget is %lld", (long long)bytes,
+                         (long long)s->budget);
     Job *j = new (std::nothrow) Job();
     if (!j) return set_error(CSPD_E_NOMEM, "host allocation failed");
     j->d = *job;
-    j->bytes = bytes;
     j->st.patches = job->B;
     j->st.submit_ns = now_ns();
     {
@@ -342,7 +370,15 @@ cspd_status cspd_serve_submit(cspd_server_t s, const cspd_job *job, uint64_t *jo
             j->st.admit_ns = j->st.start_ns = j->st.finish_ns = j->st.submit_ns;
             j->done = true;
         } else {
-            s->queue.push_back(j);
+            for (int64_t r = 0; r < job->B; r += kPiece) {
+                Piece q;
+                q.job = j;
+                q.row = r;
+                q.b = job->B - r < kPiece ? job->B - r : kPiece;
+                q.bytes = job_bytes(p, q.b);
+                s->queue.push_back(q);
+                ++j->pieces_left;
+            }
         }
         *job_id = j->id;
     }
@@ -388,6 +424,7 @@ void cspd_serve_destroy(cspd_server_t s)
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.ev) (void)hipEventDestroy(sl.ev);
+        if (sl.kbuf) (void)hipHostFree(sl.kbuf);
     }
     (void)hipSetDevice(prev);
     for (auto &kv : s->jobs) delete kv.second;

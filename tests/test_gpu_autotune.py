@@ -57,7 +57,8 @@ def _variants(plan, w, s):
     cand = _candidates(w, s)
     b = _bucket(w.k_scales[s])
     found = []
-    trials = [("first_mfma", 1, 1), ("mfma_gram", 1, 2), ("gram", 1, 1), ("gram", 2, 1), ("gram", 4, 1)]
+    trials = [("first_mfma", 1, 1), ("mfma_gram", 1, 2), ("mfma_gram", 1, 1), ("gram", 1, 1), ("gram", 2, 1),
+              ("gram", 4, 1)]
     trials += [("vec", nc, ppw) for lp, nc, ppw in VEC]
     for kind, nc, ppw in trials:
         try:
@@ -70,7 +71,7 @@ def _variants(plan, w, s):
     return cand, b, found
 
 
-@pytest.mark.parametrize("name,batch", [("c2", 1031), ("c4", 515)])
+@pytest.mark.parametrize("name,batch", [("c2", 1031), ("c4", 515), ("c3", 517), ("c5c", 263)])
 def test_every_pinned_variant_matches_oracle(name, batch):
     w = synth.make(name, batch=batch)
     plan = cspd.plan_from_workload(w)

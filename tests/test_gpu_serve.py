@@ -94,3 +94,27 @@ def test_many_small_jobs_are_batched():
     stats = [cspd.cspd_serve_poll(srv, j, -1)[1] for j in ids]
     assert max(s["batched_with"] for s in stats) > 0
     cspd.cspd_serve_destroy(srv)
+
+
+def test_large_job_cut_into_pieces():
+    """A job longer than one piece (65,536 patches) runs as several launches
+    over the slots; its rows land in place and equal the call alone."""
+    G.torch_mod()
+    w = synth.make("c5a", batch=150000)
+    plan = cspd.plan_from_workload(w)
+    srv = cspd.cspd_serve_create(0, 1 << 30, 2)
+    small = synth.subset(w, np.arange(0, 500))
+    j_big = _submit(srv, plan, w, w.k_scales, False)
+    j_small = _submit(srv, plan, small, w.k_scales, False)
+    out, st = cspd.cspd_serve_poll(srv, j_big, -1)
+    assert st["status"] == 0 and st["patches"] == w.batch
+    assert st["submit_ns"] <= st["admit_ns"] <= st["start_ns"] <= st["finish_ns"]
+    ref = G.run_cross(plan, w)
+    for k in ("support", "k_used"):
+        assert np.array_equal(out[k], ref[k]), k
+    assert np.array_equal(out["coef"].astype(np.float64), ref["coef"])
+    assert np.array_equal(out["xhat"].astype(np.float64), ref["xhat"])
+    out_s, st_s = cspd.cspd_serve_poll(srv, j_small, -1)
+    assert np.array_equal(out_s["support"], ref["support"][:500])
+    print(f"small job shared a launch with {st_s['batched_with']} other job(s)", flush=True)
+    cspd.cspd_serve_destroy(srv)
