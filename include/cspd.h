@@ -214,7 +214,9 @@ cspd_status cspd_autotune(cspd_plan_t plan, int64_t B, const void *y, const uint
  * The plan's tuned kernel for (scale, bucket 0..2): kind 0 = none (shape
  * rules), 1 = first-scale matrix-core, 2 = vector layout (nc column chunks,
  * ppw patches per wavefront), 3 = precomputed Gram, 4 = per-patch Gram on
- * the matrix cores; cand = candidate count it was timed on.
+ * the matrix cores, 5 = batched correlation GEMM then precomputed Gram
+ * (scale 0 under a shared dense operator); cand = candidate count it was
+ * timed on.
  * Errors: E_INVALID for a NULL argument or an index out of range.
  */
 cspd_status cspd_tuned_kernel(cspd_plan_t plan, int32_t scale, int32_t bucket, int32_t *kind, int32_t *nc,

@@ -344,7 +344,7 @@ def cspd_graph_destroy(graph: Graph):
         load().cspd_graph_destroy(h)
 
 
-TUNED_KINDS = {0: "rules", 1: "first_mfma", 2: "vec", 3: "gram", 4: "mfma_gram"}
+TUNED_KINDS = {0: "rules", 1: "first_mfma", 2: "vec", 3: "gram", 4: "mfma_gram", 5: "gemm_gram"}
 
 
 def cspd_autotune(plan: Plan, y, mask=None, k_scale: Sequence[int] = (), k_fine=None,

@@ -189,12 +189,30 @@ cspd_status prepare_cross(const cspd_plan_s *p, int64_t B, const void *y, const 
     return CSPD_OK;
 }
 
-// Workspace of a cross-scale call: the coarse scales' k_used, and their
-// supports unless the caller keeps them.
-size_t cross_workspace_bytes(const cspd_plan_s *p, int64_t B, int ksum, bool caller_keeps_supports)
+// Whether scale 0 runs as a batched GEMM of its correlations followed by the
+// Gram-table kernel (shared dense operator, FP32, precomputed Gram and norms).
+bool first_gemm_path(const cspd_plan_s *p)
+{
+    const ScalePlan &sc = p->sc[0];
+    int nc = 1;
+    while (nc * 64 < sc.t) nc *= 2;
+    return p->dtype == CSPD_F32 && p->s >= 2 && sc.fold == kDense && sc.gram && sc.nu2 && sc.lp >= 16 &&
+           sc.lp <= 128 && sc.l == p->m && nc <= 16;
+}
+
+// Workspace of a cross-scale call: the coarse scales' k_used, their supports
+// unless the caller keeps them, and scale 0's correlations on the GEMM path.
+size_t hpre_offset(const cspd_plan_s *p, int64_t B, int ksum, bool caller_keeps_supports)
 {
     const int64_t nk = B * (p->s - 1);
-    return sizeof(int32_t) * (size_t)(nk + (caller_keeps_supports ? 0 : B * (int64_t)ksum));
+    const size_t ints = sizeof(int32_t) * (size_t)(nk + (caller_keeps_supports ? 0 : B * (int64_t)ksum));
+    return (ints + 255) / 256 * 256;
+}
+
+size_t cross_workspace_bytes(const cspd_plan_s *p, int64_t B, int ksum, bool caller_keeps_supports)
+{
+    const size_t off = hpre_offset(p, B, ksum, caller_keeps_supports);
+    return off + (first_gemm_path(p) ? sizeof(float) * (size_t)B * (size_t)p->sc[0].t : 0);
 }
 
 // Arguments of scale s of a cross-scale call.
@@ -237,9 +255,16 @@ ScaleArgs cross_scale_args(const cspd_plan_s *p, int s, int64_t B, const void *y
 }
 
 // One scale with the plan's autotuned kernel if there is one, else by the
-// shape rules.
-cspd_status launch_cross_scale(const cspd_plan_s *p, int s, const ScaleArgs &a, const CrossCall &c, hipStream_t st)
+// shape rules.  `hpre` is the workspace of scale 0's correlations on the GEMM
+// path (else unused).
+cspd_status launch_cross_scale(const cspd_plan_s *p, int s, const ScaleArgs &a0, const CrossCall &c, float *hpre,
+                               hipStream_t st)
 {
+    ScaleArgs a = a0;
+    if (s == 0 && first_gemm_path(p)) {
+        a.hpre = hpre;   // workspace for the GEMM variant
+        a.nu2 = p->sc[0].nu2;
+    }
     KernelChoice tc;
     {
         std::lock_guard<std::mutex> lk(p->mu);
@@ -252,6 +277,13 @@ cspd_status launch_cross_scale(const cspd_plan_s *p, int s, const ScaleArgs &a, 
                              tc.nc, tc.ppw);
         return rc;
     }
+    if (s == 0 && first_gemm_path(p)) {
+        KernelChoice gg;
+        gg.kind = kChoiceGemmGram;
+        while (gg.nc * 64 < c.cand[0]) gg.nc *= 2;
+        return launch_choice(p->dtype, a, gg, st);
+    }
+    a.hpre = nullptr;
     cspd_status rc = s == 0 ? launch_first_mfma(p->dtype, a, st) : CSPD_E_UNSUPPORTED;
     if (rc == CSPD_E_UNSUPPORTED) rc = launch_scale(p->dtype, a, c.cand[s], c.gram[s], st);
     return rc;
@@ -266,16 +298,24 @@ cspd_status run_cross(const cspd_plan_s *p, int64_t B, const void *y, const uint
     const int64_t nk = B * (p->s - 1);
     int32_t *kused_c = work;
     int32_t *coarse = support_coarse ? support_coarse : work + nk;
+    float *hpre = (float *)((char *)work + hpre_offset(p, B, c.ksum, support_coarse != nullptr));
     cspd_status rc = CSPD_OK;
     for (int s = 0; s < p->s && rc == CSPD_OK; ++s) {
         const ScaleArgs a = cross_scale_args(p, s, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef,
                                              k_used, xhat, coarse, kused_c, c.ksum);
-        rc = launch_cross_scale(p, s, a, c, st);
+        rc = launch_cross_scale(p, s, a, c, hpre, st);
     }
     return rc;
 }
 
 }  // namespace
+
+int64_t cross_workspace_per_patch(const cspd_plan_s *p)
+{
+    int64_t per = (int64_t)sizeof(int32_t) * (p->s - 1);
+    if (first_gemm_path(p)) per += (int64_t)sizeof(float) * p->sc[0].t;
+    return per;
+}
 }  // namespace cspd
 
 struct cspd_graph_s {
@@ -539,8 +579,12 @@ cspd_status cspd_autotune(cspd_plan_t p, int64_t B, const void *y, const uint8_t
     if (rc != CSPD_OK) { cleanup(); return rc; }
     const int64_t nk = B * (p->s - 1);
     for (int s = 0; s < p->s; ++s) {
-        const ScaleArgs a = cross_scale_args(p, s, B, y, mask, k_scale, k_fine, k_fine_uniform, sup, coef, ku,
-                                             nullptr, work + nk, work, c.ksum);
+        ScaleArgs a = cross_scale_args(p, s, B, y, mask, k_scale, k_fine, k_fine_uniform, sup, coef, ku, nullptr,
+                                       work + nk, work, c.ksum);
+        if (s == 0 && first_gemm_path(p)) {
+            a.hpre = (char *)work + hpre_offset(p, B, c.ksum, false);
+            a.nu2 = p->sc[0].nu2;
+        }
         KernelChoice ch[24];
         const int nch = scale_choices(p->dtype, a, c.cand[s], p->sc[s].gram != nullptr, ch, 24);
         float best_ms = 0.f;

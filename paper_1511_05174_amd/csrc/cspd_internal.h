@@ -60,7 +60,9 @@ struct ScalePlan {
 
 namespace cspd {
 // A kernel variant for one scale (autotuned or chosen by shape rules).
-enum ChoiceKind { kChoiceAuto = 0, kChoiceFirstMfma = 1, kChoiceVec = 2, kChoiceGram = 3, kChoiceMfmaGram = 4 };
+enum ChoiceKind {
+    kChoiceAuto = 0, kChoiceFirstMfma = 1, kChoiceVec = 2, kChoiceGram = 3, kChoiceMfmaGram = 4, kChoiceGemmGram = 5
+};
 struct KernelChoice {
     int kind = kChoiceAuto;
     int nc = 1;
@@ -123,6 +125,9 @@ struct ScaleArgs {
     void *coef_out;             // b x sup_stride (last)
     void *xhat;                 // b x n (last, may be null)
     const void *d_high;         // T_high x n (last)
+    const void *hpre;           // b x t correlations with y (gram mode, first scale), or null;
+                                // for launch_choice: the workspace the GEMM variant writes them to
+    const void *nu2;            // t squared effective norms (with hpre)
 };
 
 // Kernel variants that can run one scale (FP32): the first-scale MFMA kernel,
@@ -141,6 +146,13 @@ cspd_status launch_scale(int dtype, const ScaleArgs &a, int max_candidates, bool
 
 // First scale of a cross-scale call on the matrix cores (shared dictionary,
 // 16 patches per wavefront); CSPD_E_UNSUPPORTED when the shape does not fit.
+// Device bytes per patch of a cross-scale call's own workspace (beyond the
+// caller's buffers and the coarse supports).
+int64_t cross_workspace_per_patch(const cspd_plan_s *p);
+// Batched first-scale correlations H = Y A_0 (b x t, FP32) of a shared dense
+// operator on the matrix cores, and whether a scale qualifies.
+bool proxy_gemm_fits(int dtype, const ScaleArgs &a);
+cspd_status launch_proxy_gemm(int dtype, const ScaleArgs &a, float *h, hipStream_t stream);
 // Whether the first-scale matrix-core kernel has an instance for this scale.
 bool first_mfma_fits(int dtype, const ScaleArgs &a);
 cspd_status launch_first_mfma(int dtype, const ScaleArgs &a, hipStream_t stream);

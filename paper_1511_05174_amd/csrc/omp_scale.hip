@@ -110,6 +110,7 @@ int scale_choices(int dtype, const ScaleArgs &a, int max_cand, bool has_gram, Ke
     if (has_gram) {
         const int nc = pow2_at_least((max_cand + 63) / 64);
         if (nc <= 16 && a.lp <= 256) add(kChoiceGram, nc, 1);
+        if (nc <= 16 && proxy_gemm_fits(dtype, a)) add(kChoiceGemmGram, nc, 1);
     }
     return n;
 }
@@ -118,12 +119,20 @@ cspd_status launch_choice(int dtype, const ScaleArgs &a, const KernelChoice &c, 
 {
     if (dtype != CSPD_F32) return CSPD_E_UNSUPPORTED;
     if (a.b <= 0) return CSPD_OK;
-    if (c.kind == kChoiceFirstMfma) return launch_first_mfma(dtype, a, st);
-    const bool gram = c.kind == kChoiceGram, mg = c.kind == kChoiceMfmaGram;
-    const int kb = k_bucket(a);
-    if (kb == 0) return dispatch_scale_f32_k4(a, a.lp, c.nc, c.ppw, gram, mg, st);
-    if (kb == 1) return dispatch_scale_f32_k8(a, a.lp, c.nc, c.ppw, gram, mg, st);
-    return dispatch_scale_f32_k16(a, a.lp, c.nc, c.ppw, gram, mg, st);
+    ScaleArgs b = a;
+    b.hpre = nullptr;   // only the GEMM variant has precomputed correlations
+    if (c.kind == kChoiceGemmGram) {
+        if (!a.hpre || !a.nu2) return CSPD_E_UNSUPPORTED;
+        const cspd_status rc = launch_proxy_gemm(dtype, a, (float *)a.hpre, st);
+        if (rc != CSPD_OK) return rc;
+        b.hpre = a.hpre;
+    }
+    if (c.kind == kChoiceFirstMfma) return launch_first_mfma(dtype, b, st);
+    const bool gram = c.kind == kChoiceGram || c.kind == kChoiceGemmGram, mg = c.kind == kChoiceMfmaGram;
+    const int kb = k_bucket(b);
+    if (kb == 0) return dispatch_scale_f32_k4(b, b.lp, c.nc, c.ppw, gram, mg, st);
+    if (kb == 1) return dispatch_scale_f32_k8(b, b.lp, c.nc, c.ppw, gram, mg, st);
+    return dispatch_scale_f32_k16(b, b.lp, c.nc, c.ppw, gram, mg, st);
 }
 
 }  // namespace cspd

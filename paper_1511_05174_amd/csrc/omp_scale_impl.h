@@ -672,6 +672,17 @@ void k_omp_scale(ScaleArgs a)
                 ee[s] += x * x;
             }
         }
+    } else if (a.hpre) {
+        // correlations with y from the batched first-scale GEMM, squared
+        // norms from the plan (shared operator: no weights)
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const int at = live[s] ? atom[s] : 0;
+            const T hv = ((const T *)a.hpre)[bb * (int64_t)a.t + at];
+            const T ev = ((const T *)a.nu2)[at];
+            h[s] = live[s] ? hv : T(0);
+            ee[s] = live[s] ? ev : T(0);
+        }
     } else {
         for (int j = 0; j < lp; ++j) {
             const T sw = w.sqw[j], yh = w.yhat[j];

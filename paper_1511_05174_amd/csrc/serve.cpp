@@ -83,6 +83,7 @@ int64_t job_bytes(const cspd_plan_s *p, int64_t B)
     int64_t coarse = 0;
     for (int s = 0; s + 1 < p->s; ++s) coarse += p->k_max;
     per += coarse * (int64_t)sizeof(int32_t);
+    per += cross_workspace_per_patch(p);   // the call's own workspace
     return per * B + 4096;
 }
 

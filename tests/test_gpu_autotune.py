@@ -58,7 +58,7 @@ def _variants(plan, w, s):
     b = _bucket(w.k_scales[s])
     found = []
     trials = [("first_mfma", 1, 1), ("mfma_gram", 1, 2), ("mfma_gram", 1, 1), ("gram", 1, 1), ("gram", 2, 1),
-              ("gram", 4, 1)]
+              ("gram", 4, 1), ("gemm_gram", 1, 1), ("gemm_gram", 2, 1), ("gemm_gram", 4, 1)]
     trials += [("vec", nc, ppw) for lp, nc, ppw in VEC]
     for kind, nc, ppw in trials:
         try:
