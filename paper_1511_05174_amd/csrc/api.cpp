@@ -58,6 +58,12 @@ cspd_status validate_desc(const cspd_plan_desc *d)
         if (s > 0 && d->atoms[s] % d->atoms[s - 1] != 0)
             return set_error(CSPD_E_SHAPE, "atoms[%d] = %d is not a multiple of atoms[%d] = %d", s,
                              d->atoms[s], s - 1, d->atoms[s - 1]);
+        // kernels index a dictionary with 32-bit offsets (rows padded to at
+        // most twice the length, and at least the measurement dimension)
+        const int64_t len = 2 * (int64_t)(d->dim[s] > d->m ? d->dim[s] : d->m) + 16;
+        if ((int64_t)d->atoms[s] * len >= ((int64_t)1 << 31))
+            return set_error(CSPD_E_SHAPE, "scale %d: %d atoms of length %d exceed 2^31 elements", s, d->atoms[s],
+                             d->dim[s]);
     }
     for (int s = 0; s + 1 < S; ++s) {
         if (!d->up_map[s]) return set_error(CSPD_E_INVALID, "up_map[%d] is NULL", s);

@@ -704,6 +704,15 @@ void k_omp_scale(ScaleArgs a)
         if (!(ee[s] > T(0))) live[s] = false;  // an effective column of zero is never picked
     }
 
+    // The refinement reads the support's vectors RU coordinates per lane at
+    // a time.  When one such batch covers every coordinate (KEEP), the values
+    // are kept in LDS (lane-major) for x-hat.
+    constexpr int RU0 = GRAM ? 4 : ((LP + G - 1) / G > 4 ? 4 : (LP + G - 1) / G);
+    constexpr int RU = RU0 * KM > 16 ? (16 / KM > 0 ? 16 / KM : 1) : RU0;
+    static_assert(RU >= 1, "refinement batch");
+    constexpr bool KEEP = sizeof(T) == 4 && !GRAM && G * RU >= LP;
+    __shared__ T keep_lds[KEEP ? W : 1][KEEP ? RU * KM : 1][64];
+
     // ---- OMP iterations (Algorithm 1), unrolled so u and x stay in VGPRs
     T x[KM];          // column gl of L^{-1}
 #pragma unroll
@@ -908,6 +917,9 @@ void k_omp_scale(ScaleArgs a)
     }
     // coefficients: lane j of the group holds alpha_j
     if (gl < nsel) w.alpha[gl] = al;
+    // x-hat reuses the refinement's vectors when they are D_high's atoms
+    // themselves (finest-scale coordinates that are the signal's samples)
+    const bool xkeep = KEEP && a.xhat && a.fold == kFold && a.blk_ident && a.n == a.l;
     if constexpr (sizeof(T) == 4) {
         // One step of mixed-precision refinement.  The FP32 normal equations
         // leave an error of about kappa(G) 2^-24; the residual of the normal
@@ -930,9 +942,6 @@ void k_omp_scale(ScaleArgs a)
             const T *vv = (const T *)a.v;
             // RU coordinates per lane at a time: all their loads are in
             // flight together (one memory round trip per RU G coordinates)
-            constexpr int RU0 = GRAM ? 4 : ((LP + G - 1) / G > 4 ? 4 : (LP + G - 1) / G);
-            constexpr int RU = RU0 * KM > 16 ? (16 / KM > 0 ? 16 / KM : 1) : RU0;
-            static_assert(RU >= 1, "refinement batch");
             for (int t0 = gl; t0 < a.l; t0 += G * RU) {
                 T raw[RU][KM];
                 // unconditional loads from valid addresses (atoms past nsel
@@ -943,7 +952,15 @@ void k_omp_scale(ScaleArgs a)
                     const int t = t0 + u * G;
                     const int tc = t < a.l ? t : 0;
 #pragma unroll
-                    for (int i = 0; i < KM; ++i) raw[u][i] = vv[(int64_t)sid[i] * a.lp + tc];
+                    for (int i = 0; i < KM; ++i) raw[u][i] = vv[(unsigned)(sid[i] * a.lp + tc)];   // t lp < 2^31
+                }
+                if constexpr (KEEP) {   // a single batch (G RU >= LP >= l)
+                    if (xkeep) {
+#pragma unroll
+                        for (int u = 0; u < RU; ++u)
+#pragma unroll
+                            for (int i = 0; i < KM; ++i) keep_lds[wv][u * KM + i][lane] = raw[u][i];
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < RU; ++u) {
@@ -1016,6 +1033,20 @@ void k_omp_scale(ScaleArgs a)
             si[i] = in ? w.sup[i] : 0;
             alx[i] = in ? w.alpha[i] : T(0);
         }
+        if constexpr (KEEP) {
+            if (xkeep) {
+                // the lanes past l wrote nothing and store nothing
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    const int j = gl + u * G;
+                    T acc = 0;
+#pragma unroll
+                    for (int i = 0; i < KM; ++i) acc += alx[i] * keep_lds[wv][u * KM + i][lane];
+                    if (j < a.n) xh[j] = acc;
+                }
+                return;
+            }
+        }
         // XU samples per lane at a time, every selected atom's sample of each
         // requested before any is used (one memory round trip per XU G samples)
         constexpr int XU = (32 / KM < 1 ? 1 : 32 / KM) / (sizeof(T) == 8 ? 2 : 1) > 0
@@ -1027,7 +1058,7 @@ void k_omp_scale(ScaleArgs a)
                 const int j = j0 + u * G;
                 const int jc = j < a.n ? j : 0;   // a valid address; not stored
 #pragma unroll
-                for (int i = 0; i < KM; ++i) d[u][i] = dh[(int64_t)si[i] * a.n + jc];
+                for (int i = 0; i < KM; ++i) d[u][i] = dh[(unsigned)(si[i] * a.n + jc)];   // T n < 2^31
             }
 #pragma unroll
             for (int u = 0; u < XU; ++u) {
