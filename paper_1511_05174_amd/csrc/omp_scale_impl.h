@@ -878,9 +878,17 @@ void k_omp_scale(ScaleArgs a)
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             const T g = gcol[s];
-            T dot = 0;
+            // u rows are zero past n: with up to 8 atoms the iterations are
+            // unrolled and the sum stops at n; beyond, it runs over all KM
+            // entries in four independent chains (no loop bound, short
+            // dependence)
+            T dp[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-            for (int m = 0; m < n; ++m) dot += w.uk[m] * u[s][m];
+            for (int m = 0; m < KM; ++m) {
+                if (KM <= 8 && m >= n) break;
+                dp[m & 3] += w.uk[m] * u[s][m];
+            }
+            const T dot = (dp[0] + dp[1]) + (dp[2] + dp[3]);
             const T un = (g - dot) * inv;
             u[s][n] = un;
             c[s] -= un * zn;
@@ -888,9 +896,13 @@ void k_omp_scale(ScaleArgs a)
             live[s] = live[s] & (atom[s] != kb);
         }
         // column gl of L^{-1}: new entry of the appended row
-        T xd = gl == n ? T(1) : T(0);
+        T xp[4] = {T(0), T(0), T(0), T(0)};   // x is zero past n as well
 #pragma unroll
-        for (int m = 0; m < n; ++m) xd -= w.uk[m] * x[m];
+        for (int m = 0; m < KM; ++m) {
+            if (KM <= 8 && m >= n) break;
+            xp[m & 3] += w.uk[m] * x[m];
+        }
+        const T xd = (gl == n ? T(1) : T(0)) - ((xp[0] + xp[1]) + (xp[2] + xp[3]));
         x[n] = xd * inv;
         al += x[n] * zn;
         col2 += x[n] * x[n];

@@ -165,6 +165,38 @@ def test_full_gram_path():
     check_full(w)
 
 
+def test_dense_first_scale_gemm_ragged():
+    """Scale 0 under a shared dense operator runs the batched correlation GEMM
+    and the Gram-table kernel: atoms not a multiple of the 32-atom block,
+    a measurement length not a multiple of 4 and a ragged last wavefront."""
+    w = synth.custom([16, 64], [48, 384], batch=1003, seed=12, k_scales=[3, 6], sigma=0.01,
+                     phi_kind="dense", m=36, dict_kind="model", dtype="f32")
+    cspd.cspd_profile_reset()
+    cspd.cspd_profile_enable(True)
+    try:
+        check_cross(w)
+        labels = list(cspd.cspd_profile_read())
+    finally:
+        cspd.cspd_profile_enable(False)
+    assert any(lab.startswith("proxy_gemm") for lab in labels), labels
+    assert any("gram" in lab and lab.endswith(":s0") for lab in labels), labels
+
+
+def test_one_patch_mfma_gram_partial_blocks():
+    """Up to 64 candidates on one patch per wavefront, vectors of 32
+    coordinates (16 per lane half, a single chunk)."""
+    w = synth.custom([16, 64], [32, 512], batch=777, seed=13, k_scales=[4, 10], sigma=0.02,
+                     phi_kind="dense", m=32, dict_kind="model", dtype="f32")
+    cspd.cspd_profile_reset()
+    cspd.cspd_profile_enable(True)
+    try:
+        check_cross(w)
+        labels = list(cspd.cspd_profile_read())
+    finally:
+        cspd.cspd_profile_enable(False)
+    assert any("mfma" in lab and "ppw1" in lab and lab.endswith(":s1") for lab in labels), labels
+
+
 def test_deterministic():
     w = synth.make("c3", batch=1500)
     plan = cspd.plan_from_workload(w)
