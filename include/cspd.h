@@ -281,7 +281,10 @@ typedef struct cspd_job_stats {
  * background thread admits queued pieces in arrival order when their
  * buffers fit in the budget, packs waiting pieces of the same plan and kind
  * into one launch (at most 65,536 patches), copies in, launches, copies out
- * and retires them; a job finishes with its last piece.
+ * and retires them; a job finishes with its last piece.  Each slot keeps its
+ * device buffers from launch to launch (grown to its largest launch, freed
+ * by cspd_serve_destroy); the budget bounds the bytes of launches in
+ * flight.
  * Errors: E_INVALID, E_DEVICE, E_NOMEM.
  */
 cspd_status cspd_serve_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slots,

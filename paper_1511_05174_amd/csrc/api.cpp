@@ -316,6 +316,34 @@ cspd_status run_cross(const cspd_plan_s *p, int64_t B, const void *y, const uint
 
 }  // namespace
 
+// A cross-scale call on a workspace the caller provides (the serving loop's
+// per-slot buffers): no allocation.  `work` must hold cross_call_workspace
+// bytes for the same arguments.
+size_t cross_call_workspace(const cspd_plan_s *p, int64_t B, const int32_t *k_scale, bool caller_keeps_supports)
+{
+    int ksum = 0;
+    for (int s = 0; s + 1 < p->s; ++s) ksum += k_scale[s];
+    return cross_workspace_bytes(p, B, ksum, caller_keeps_supports);
+}
+
+cspd_status cross_scale_on(cspd_plan_s *p, int64_t B, const void *y, const uint8_t *mask, const int32_t *k_scale,
+                           const int32_t *k_fine, int32_t k_fine_uniform, int32_t *support, void *coef,
+                           int32_t *k_used, void *xhat, int32_t *support_coarse, void *work, size_t work_bytes,
+                           hipStream_t st)
+{
+    clear_error();
+    if (p->s == 1) return cspd_omp_full(p, B, y, mask, k_fine, k_fine_uniform, support, coef, k_used, xhat, st);
+    CrossCall c;
+    cspd_status rc = prepare_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, c);
+    if (rc != CSPD_OK || B == 0) return rc;
+    if (work_bytes < cross_workspace_bytes(p, B, c.ksum, support_coarse != nullptr))
+        return set_error(CSPD_E_INVALID, "workspace of %zu bytes is too small", work_bytes);
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
+    return run_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat, support_coarse,
+                     (int32_t *)work, c, st);
+}
+
 int64_t cross_workspace_per_patch(const cspd_plan_s *p)
 {
     int64_t per = (int64_t)sizeof(int32_t) * (p->s - 1);

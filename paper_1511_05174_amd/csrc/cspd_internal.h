@@ -146,6 +146,13 @@ cspd_status launch_scale(int dtype, const ScaleArgs &a, int max_candidates, bool
 
 // First scale of a cross-scale call on the matrix cores (shared dictionary,
 // 16 patches per wavefront); CSPD_E_UNSUPPORTED when the shape does not fit.
+// Cross-scale call on a caller-provided workspace (no allocation), and the
+// bytes it needs.
+size_t cross_call_workspace(const cspd_plan_s *p, int64_t B, const int32_t *k_scale, bool caller_keeps_supports);
+cspd_status cross_scale_on(cspd_plan_s *p, int64_t B, const void *y, const uint8_t *mask, const int32_t *k_scale,
+                           const int32_t *k_fine, int32_t k_fine_uniform, int32_t *support, void *coef,
+                           int32_t *k_used, void *xhat, int32_t *support_coarse, void *work, size_t work_bytes,
+                           hipStream_t stream);
 // Device bytes per patch of a cross-scale call's own workspace (beyond the
 // caller's buffers and the coarse supports).
 int64_t cross_workspace_per_patch(const cspd_plan_s *p);

@@ -68,6 +68,8 @@ struct Slot {
     int64_t bytes = 0;
     int status = CSPD_OK;
     int32_t *kbuf = nullptr;   // pinned: per-patch K of the packed batch (kept until retired)
+    char *dev = nullptr;       // device buffers of a launch, kept and grown (never shrunk)
+    size_t dev_bytes = 0;
 };
 
 size_t esize(const cspd_plan_s *p) { return p->dtype == CSPD_F64 ? sizeof(double) : sizeof(float); }
@@ -181,9 +183,21 @@ void cspd_server_s::enqueue(Slot &sl)
     const size_t o_ku = carve(sizeof(int32_t) * (size_t)B);
     const size_t o_x = carve(e * (size_t)B * p->n);
     const size_t o_sc = carve(sizeof(int32_t) * (size_t)B * (ks > 0 ? ks : 1));
+    const size_t wbytes = head->d.full ? 0 : cross_call_workspace(p, B, head->d.k_scale, true);
+    const size_t o_ws = carve(wbytes);
     int rc = CSPD_OK;
-    char *dev = nullptr;
-    if (hipMallocAsync((void **)&dev, off, sl.stream) != hipSuccess) rc = CSPD_E_NOMEM;
+    // the slot's buffers are reused launch after launch (this slot's previous
+    // launch has retired, so its stream is idle); they grow when a launch
+    // needs more, with a synchronous allocation that only the first launches
+    // of each size pay
+    if (sl.dev_bytes < off) {
+        if (sl.dev) (void)hipFree(sl.dev);
+        sl.dev = nullptr;
+        sl.dev_bytes = 0;
+        if (hipMalloc((void **)&sl.dev, off) == hipSuccess) sl.dev_bytes = off;
+        else rc = CSPD_E_NOMEM;
+    }
+    char *dev = sl.dev;
     const int64_t t_start = now_ns();
     int32_t *kbuf = sl.kbuf;
     if (rc == CSPD_OK) {
@@ -210,9 +224,10 @@ void cspd_server_s::enqueue(Slot &sl)
                                (int32_t *)(dev + o_sup), dev + o_cf, (int32_t *)(dev + o_ku), dev + o_x,
                                sl.stream);
         else
-            rc = cspd_omp_cross_scale(p, B, dev + o_y, (const uint8_t *)(dev + o_m), head->d.k_scale,
-                                      (const int32_t *)(dev + o_k), 0, (int32_t *)(dev + o_sup), dev + o_cf,
-                                      (int32_t *)(dev + o_ku), dev + o_x, (int32_t *)(dev + o_sc), sl.stream);
+            rc = cross_scale_on(p, B, dev + o_y, (const uint8_t *)(dev + o_m), head->d.k_scale,
+                                (const int32_t *)(dev + o_k), 0, (int32_t *)(dev + o_sup), dev + o_cf,
+                                (int32_t *)(dev + o_ku), dev + o_x, (int32_t *)(dev + o_sc), dev + o_ws, wbytes,
+                                sl.stream);
         row = 0;
         for (const Piece &q : take) {
             const Job *j = q.job;
@@ -233,7 +248,6 @@ void cspd_server_s::enqueue(Slot &sl)
             row += b;
         }
     }
-    if (dev) hipFreeAsync(dev, sl.stream);
     sl.status = rc;
     hipEventRecord(sl.ev, sl.stream);
 }
@@ -426,6 +440,7 @@ void cspd_serve_destroy(cspd_server_t s)
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.ev) (void)hipEventDestroy(sl.ev);
         if (sl.kbuf) (void)hipHostFree(sl.kbuf);
+        if (sl.dev) (void)hipFree(sl.dev);
     }
     (void)hipSetDevice(prev);
     for (auto &kv : s->jobs) delete kv.second;
