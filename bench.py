@@ -360,6 +360,67 @@ def autotune_phase(cspd, w, ks, y, mask, kf, steps: int = 10):
     return res
 
 
+def pipeline_phase(cspd, w, ks, reps: int = 5):
+    """Whole-image inpainting: the workload's 65,536 patches tiled into a
+    2048 x 2048 image, half of its pixels kept (Bernoulli 1/2), then cut into
+    overlapping 8 x 8 patches at stride 4 (261,121 patches), zero-tree OMP
+    (and full OMP for comparison) on the inpainting plan, and averaging.
+    Times per stage on the device (events), image PSNR against the clean
+    image."""
+    import torch
+
+    side, tile = 2048, 8
+    per = side // tile
+    clean = w.x.reshape(per, per, tile, tile).transpose(0, 2, 1, 3).reshape(side, side).astype(np.float32)
+    rng = np.random.default_rng(21)
+    mask = (rng.random((side, side)) < 0.5).astype(np.uint8)
+    meas = (clean * mask).astype(np.float32)
+    grid = cspd.patch_grid((side, side), (tile, tile), (4, 4))
+    n = cspd.cspd_patch_count(grid)
+    plan = cspd.plan_from_workload(w)
+    dev = torch.device("cuda", 0)
+    m_t = torch.from_numpy(mask).to(dev)
+    s_t = torch.from_numpy(meas).to(dev)
+    y, pm = cspd.cspd_extract_patches(grid, s_t, m_t)
+    out = cspd.cspd_omp_cross_scale(plan, y, pm, ks[:-1], None, ks[-1])
+    img = cspd.cspd_aggregate_patches(grid, out[3])
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    times = {"extract_ms": 0.0, "omp_ms": 0.0, "aggregate_ms": 0.0}
+    for _ in range(reps):
+        ev[0].record()
+        cspd.cspd_extract_patches(grid, s_t, m_t, y=y, patch_mask=pm)
+        ev[1].record()
+        cspd.cspd_omp_cross_scale(plan, y, pm, ks[:-1], None, ks[-1], support=out[0], coef=out[1], k_used=out[2],
+                                  xhat=out[3])
+        ev[2].record()
+        cspd.cspd_aggregate_patches(grid, out[3], out=img)
+        ev[3].record()
+        torch.cuda.synchronize()
+        times["extract_ms"] += ev[0].elapsed_time(ev[1]) / reps
+        times["omp_ms"] += ev[1].elapsed_time(ev[2]) / reps
+        times["aggregate_ms"] += ev[2].elapsed_time(ev[3]) / reps
+    img_cross = img.cpu().numpy()
+    fo = cspd.cspd_omp_full(plan, y, pm, None, ks[-1])
+    fimg = cspd.cspd_aggregate_patches(grid, fo[3])
+    torch.cuda.synchronize()
+    ev[0].record()
+    cspd.cspd_omp_full(plan, y, pm, None, ks[-1], support=fo[0], coef=fo[1], k_used=fo[2], xhat=fo[3])
+    ev[1].record()
+    torch.cuda.synchronize()
+    full_ms = ev[0].elapsed_time(ev[1])
+    img_full = fimg.cpu().numpy()
+    total = sum(times.values())
+    res = {"image": f"{side} x {side}, 8x8 patches at stride 4, half of the pixels observed",
+           "patches": n, **{k: round(v, 4) for k, v in times.items()}, "total_ms": round(total, 4),
+           "megapixels_per_s": side * side / (total * 1e-3) / 1e6,
+           "psnr_db_cross": psnr_db(clean.astype(np.float64), img_cross.astype(np.float64)),
+           "psnr_db_full": psnr_db(clean.astype(np.float64), img_full.astype(np.float64)),
+           "full_omp_ms": round(full_ms, 4), "omp_speedup_vs_full": full_ms / times["omp_ms"]}
+    cspd.cspd_plan_destroy(plan)
+    return res
+
+
 def traffic_probe(workload: str, steps: int = 3):
     """A plain elementwise pass over a buffer of known size, then a few
     cross-scale steps: run under rocprofv3 --pmc FETCH_SIZE, and again under
@@ -445,6 +506,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=2000, help="Poisson arrivals per offered load")
     ap.add_argument("--serve-slots", type=int, default=4, help="server launches in flight")
     ap.add_argument("--serve-ring", type=int, default=8, help="client output sets (jobs outstanding)")
@@ -630,6 +692,12 @@ def main():
         autotune = autotune_phase(cspd, w, ks, y, mask, kf)
         print(f"[bench] autotune: {json.dumps(autotune)}", file=sys.stderr, flush=True)
 
+    # ---- whole-image pipeline: patches -> zero-tree OMP -> averaging
+    pipeline = None
+    if not args.no_pipeline and args.workload == "c2":
+        pipeline = pipeline_phase(cspd, w, ks)
+        print(f"[bench] pipeline: {json.dumps(pipeline)}", file=sys.stderr, flush=True)
+
     # ---- precision: bf16 / fp16 proxies with FP32 re-scoring (full OMP, 3-scale workload)
     precision = None
     if not args.no_precision:
@@ -685,6 +753,7 @@ def main():
         "precision": precision,
         "graphs": graphs,
         "autotune": autotune,
+        "pipeline": pipeline,
     }
     print(json.dumps(line))
 

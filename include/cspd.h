@@ -232,6 +232,55 @@ cspd_status cspd_set_tuned_kernel(cspd_plan_t plan, int32_t scale, int32_t bucke
                                   int32_t ppw, int32_t cand);
 
 /* ---------------------------------------------------------------------- */
+/* Whole signals: overlapping patches in, averaged estimates out.           */
+/* (Section V processes images, videos and light fields as overlapping     */
+/* patches; the grid and the averaging below are this library's reading.)  */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * A patch grid over a signal of ndim (1..4) axes, row-major (last axis
+ * fastest): along axis d patches of patch[d] samples start at 0, stride[d],
+ * 2 stride[d], ... and, when the last of these does not reach the end, once
+ * more at dims[d] - patch[d], so every sample is covered.  Patches are
+ * numbered row-major over the grid; a patch is vectorised row-major over its
+ * own axes (image (y, x), video (t, y, x), light field (u, v, y, x)), which
+ * is the coordinate order of the plan's finest dictionary.
+ */
+typedef struct cspd_patch_grid {
+    int32_t ndim;
+    int32_t dims[4];
+    int32_t patch[4];
+    int32_t stride[4];
+} cspd_patch_grid;
+
+/* Number of patches of the grid, or -1 for an invalid grid (message in
+ * cspd_last_error): 1 <= patch <= dims, stride >= 1, patch volume <= 65,536. */
+int64_t cspd_patch_count(const cspd_patch_grid *grid);
+
+/*
+ * Cut a signal into its patches (stream-ordered).
+ *   signal      device float, the signal (prod(dims) samples).
+ *   mask        device uint8 of the same shape (nonzero = observed), or NULL.
+ *   y           device float out, count x prod(patch), row-major.
+ *   patch_mask  device uint8 out of the same shape as y (the mask's samples,
+ *               or all 1 when mask is NULL), or NULL.
+ * Errors: E_INVALID, E_SHAPE, E_DEVICE.
+ */
+cspd_status cspd_extract_patches(const cspd_patch_grid *grid, const float *signal, const uint8_t *mask, float *y,
+                                 uint8_t *patch_mask, void *hip_stream);
+
+/*
+ * Put patch estimates back together (stream-ordered): every sample of
+ * signal_out is the mean (accumulated in FP64) of the estimates of all the
+ * patches that cover it, visited in grid order.
+ *   estimates   device float, count x prod(patch) (e.g. the x-hat of an OMP call).
+ *   signal_out  device float out, prod(dims) samples.
+ * Errors: E_INVALID, E_SHAPE, E_DEVICE.
+ */
+cspd_status cspd_aggregate_patches(const cspd_patch_grid *grid, const float *estimates, float *signal_out,
+                                   void *hip_stream);
+
+/* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of reconstruction jobs on one device.      */
 /* (Not in the paper: a request loop around the calls above.)             */
 /* ---------------------------------------------------------------------- */

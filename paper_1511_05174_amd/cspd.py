@@ -9,6 +9,7 @@ Names follow the C entry points:
   cspd_omp_full, cspd_omp_cross_scale,
   cspd_graph_cross_scale, cspd_graph_launch, cspd_graph_destroy,
   cspd_autotune, cspd_tuned_kernel, cspd_set_tuned_kernel,
+  cspd_patch_count, cspd_extract_patches, cspd_aggregate_patches,
   cspd_serve_create, cspd_serve_submit, cspd_serve_poll, cspd_serve_destroy,
   cspd_last_error, cspd_version.
 """
@@ -72,6 +73,15 @@ class Job(C.Structure):
     ]
 
 
+class PatchGrid(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int32),
+        ("dims", C.c_int32 * 4),
+        ("patch", C.c_int32 * 4),
+        ("stride", C.c_int32 * 4),
+    ]
+
+
 class JobStats(C.Structure):
     _fields_ = [
         ("submit_ns", C.c_int64),
@@ -109,6 +119,10 @@ SIGNATURES = {
     "cspd_serve_submit": (C.c_int32, [C.c_void_p, C.POINTER(Job), C.POINTER(C.c_uint64)]),
     "cspd_serve_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64, C.POINTER(JobStats)]),
     "cspd_serve_destroy": (None, [C.c_void_p]),
+    "cspd_patch_count": (C.c_int64, [C.POINTER(PatchGrid)]),
+    "cspd_extract_patches": (C.c_int32, [C.POINTER(PatchGrid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p]),
+    "cspd_aggregate_patches": (C.c_int32, [C.POINTER(PatchGrid), C.c_void_p, C.c_void_p, C.c_void_p]),
     "cspd_profile_enable": (C.c_int32, [C.c_int32]),
     "cspd_profile_read": (C.c_int32, [C.c_int32, C.c_char_p, C.c_int32, C.POINTER(C.c_int64),
                                       C.POINTER(C.c_double)]),
@@ -372,6 +386,60 @@ def cspd_set_tuned_kernel(plan: Plan, scale: int, bucket: int, kind, nc: int = 1
         kind = {v: k for k, v in TUNED_KINDS.items()}[kind]
     _check(load().cspd_set_tuned_kernel(plan.handle, int(scale), int(bucket), int(kind), int(nc), int(ppw),
                                         int(cand)))
+
+
+def patch_grid(dims: Sequence[int], patch: Sequence[int], stride: Sequence[int]) -> PatchGrid:
+    """A cspd_patch_grid for a signal of len(dims) axes (1..4)."""
+    if not (len(dims) == len(patch) == len(stride)) or not 1 <= len(dims) <= 4:
+        raise ValueError("dims, patch and stride need the same length, 1..4")
+    g = PatchGrid()
+    g.ndim = len(dims)
+    for i, (d, q, t) in enumerate(zip(dims, patch, stride)):
+        g.dims[i], g.patch[i], g.stride[i] = int(d), int(q), int(t)
+    return g
+
+
+def cspd_patch_count(grid: PatchGrid) -> int:
+    n = int(load().cspd_patch_count(C.byref(grid)))
+    if n < 0:
+        raise CspdError(E_SHAPE, cspd_last_error())
+    return n
+
+
+def cspd_extract_patches(grid: PatchGrid, signal, mask=None, y=None, patch_mask=None, want_mask: bool = True,
+                         stream=None):
+    """Patches of a device float signal (and of its uint8 mask); returns
+    (y, patch_mask)."""
+    torch = _torch()
+    n = cspd_patch_count(grid)
+    vol = int(np.prod([grid.patch[i] for i in range(grid.ndim)]))
+    dims = tuple(grid.dims[i] for i in range(grid.ndim))
+    if signal.dtype != torch.float32 or tuple(signal.shape) != dims or not signal.is_contiguous():
+        raise ValueError(f"signal must be a contiguous float32 tensor of shape {dims}")
+    if mask is not None and (mask.dtype != torch.uint8 or tuple(mask.shape) != dims or not mask.is_contiguous()):
+        raise ValueError(f"mask must be a contiguous uint8 tensor of shape {dims}")
+    if y is None:
+        y = torch.empty((n, vol), dtype=torch.float32, device=signal.device)
+    if patch_mask is None and want_mask:
+        patch_mask = torch.empty((n, vol), dtype=torch.uint8, device=signal.device)
+    _check(load().cspd_extract_patches(C.byref(grid), _ptr(signal), _ptr(mask), _ptr(y), _ptr(patch_mask),
+                                       _stream(stream)))
+    return y, patch_mask
+
+
+def cspd_aggregate_patches(grid: PatchGrid, estimates, out=None, stream=None):
+    """Mean of the covering patches' estimates at every sample; returns the
+    signal tensor."""
+    torch = _torch()
+    n = cspd_patch_count(grid)
+    vol = int(np.prod([grid.patch[i] for i in range(grid.ndim)]))
+    dims = tuple(grid.dims[i] for i in range(grid.ndim))
+    if estimates.dtype != torch.float32 or tuple(estimates.shape) != (n, vol) or not estimates.is_contiguous():
+        raise ValueError(f"estimates must be a contiguous float32 tensor of shape {(n, vol)}")
+    if out is None:
+        out = torch.empty(dims, dtype=torch.float32, device=estimates.device)
+    _check(load().cspd_aggregate_patches(C.byref(grid), _ptr(estimates), _ptr(out), _stream(stream)))
+    return out
 
 
 def cspd_profile_enable(on: bool = True):
