@@ -421,6 +421,56 @@ def pipeline_phase(cspd, w, ks, reps: int = 5):
     return res
 
 
+def learning_phase(cspd, w, iters: int = 3):
+    """Section IV on the workload's 65,536 clean patches: cross-scale
+    learning (K-SVD on the down-sampled set for D_low, then K-SVD with
+    zero-tree OMP for D_high: T 128 / 1024, K 4 / 8) against plain K-SVD of a
+    1024-atom dictionary with full OMP (K 8).  Per-iteration time of the
+    sparse-approximation step and of the dictionary update, and the relative
+    representation error ||X - D S|| / ||X|| after the last iteration."""
+    import torch
+
+    from paper_1511_05174_amd import train
+
+    x = w.x.astype(np.float64)
+    n_low, t_low, q = w.dims[0], w.atoms[0], w.atoms[1] // w.atoms[0]
+    k_low, k_high = w.k_scales
+    tm = {}
+    d_low, d_high = train.cross_scale(x, w.up_maps[0], n_low, t_low, q, k_low, k_high, iters, iters, seed=5,
+                                      timings=tm)
+    rng = np.random.default_rng(6)
+    d0 = train._unit_rows(x[rng.choice(len(x), size=w.atoms[1], replace=False)])
+    tp = []
+    d_plain, sup_p, coef_p = train.ksvd(x, d0, k_high, iters, tp)
+
+    def rel_err(D, sup, coef):
+        rec = np.zeros_like(x)
+        for j in range(sup.shape[1]):
+            a = sup[:, j]
+            ok = a >= 0
+            rec[ok] += coef[ok, j:j + 1] * D[a[ok]]
+        return float(np.linalg.norm(x - rec) / np.linalg.norm(x))
+
+    # representation error of the learned pair: one more zero-tree coding
+    plan = train._plan([n_low, w.dims[1]], [t_low, t_low * q], [d_low.astype(np.float64), d_high.astype(np.float64)],
+                       [w.up_maps[0]], max(k_low, k_high))
+    X = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    sup_c, coef_c, _, _ = cspd.cspd_omp_cross_scale(plan, X, None, [k_low], None, k_high, want_xhat=False)
+    err_cross = rel_err(d_high.astype(np.float64), sup_c.cpu().numpy(), coef_c.cpu().numpy().astype(np.float64))
+    cspd.cspd_plan_destroy(plan)
+    err_plain = rel_err(d_plain.astype(np.float64), sup_p, coef_p.astype(np.float64))
+    hi = np.array(tm["high"])
+    pl = np.array(tp)
+    return {"signals": int(len(x)), "iterations": iters,
+            "cross_scale": {"coding_ms": float(hi[:, 0].mean() * 1e3), "update_ms": float(hi[:, 1].mean() * 1e3),
+                            "step1_iter_ms": float(np.array(tm["low"]).sum(axis=1).mean() * 1e3),
+                            "rel_error": err_cross},
+            "plain_ksvd": {"coding_ms": float(pl[:, 0].mean() * 1e3), "update_ms": float(pl[:, 1].mean() * 1e3),
+                           "rel_error": err_plain},
+            "coding_speedup": float(pl[:, 0].mean() / hi[:, 0].mean()),
+            "iteration_speedup": float(pl.sum(axis=1).mean() / hi.sum(axis=1).mean())}
+
+
 def traffic_probe(workload: str, steps: int = 3):
     """A plain elementwise pass over a buffer of known size, then a few
     cross-scale steps: run under rocprofv3 --pmc FETCH_SIZE, and again under
@@ -507,6 +557,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-pipeline", action="store_true")
+    ap.add_argument("--no-learning", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=2000, help="Poisson arrivals per offered load")
     ap.add_argument("--serve-slots", type=int, default=4, help="server launches in flight")
     ap.add_argument("--serve-ring", type=int, default=8, help="client output sets (jobs outstanding)")
@@ -698,6 +749,12 @@ def main():
         pipeline = pipeline_phase(cspd, w, ks)
         print(f"[bench] pipeline: {json.dumps(pipeline)}", file=sys.stderr, flush=True)
 
+    # ---- dictionary learning (Section IV): cross-scale vs plain K-SVD
+    learning = None
+    if not args.no_learning and args.workload == "c2":
+        learning = learning_phase(cspd, w)
+        print(f"[bench] learning: {json.dumps(learning)}", file=sys.stderr, flush=True)
+
     # ---- precision: bf16 / fp16 proxies with FP32 re-scoring (full OMP, 3-scale workload)
     precision = None
     if not args.no_precision:
@@ -754,6 +811,7 @@ def main():
         "graphs": graphs,
         "autotune": autotune,
         "pipeline": pipeline,
+        "learning": learning,
     }
     print(json.dumps(line))
 

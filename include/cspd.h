@@ -281,6 +281,33 @@ cspd_status cspd_aggregate_patches(const cspd_patch_grid *grid, const float *est
                                    void *hip_stream);
 
 /* ---------------------------------------------------------------------- */
+/* Learning the dictionaries (Section IV-A): the K-SVD dictionary update.  */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * One sweep of the K-SVD dictionary update after a sparse-approximation step
+ * (cspd_omp_full for plain K-SVD, cspd_omp_cross_scale for the cross-scale
+ * variant whose supports stay inside the children of the coarse support).
+ * Atoms are updated in index order, each seeing the previous updates: the
+ * users of atom k (signals whose support holds it), the error without it
+ * E_k = R_users + s_k d_k^T, the new atom = leading left singular vector of
+ * E_k^T (sign kept towards the old atom), the users' coefficients E_k d_k,
+ * and the residual minus the new rank-1 term.  An atom without users keeps
+ * its value.  The sweep is deterministic.
+ *   x        device float, row-major P x N training signals.
+ *   dict     device float, row-major T x N atoms (one atom per row), in/out;
+ *            N <= 64.
+ *   support  device int32, row-major P x kstride (the OMP call's support,
+ *            -1 padded; entries must be distinct per row).
+ *   coef     device float, row-major P x kstride, in/out (the OMP call's
+ *            coefficients; updated for every used slot).
+ * Stream-ordered (workspace allocated and freed on the stream).
+ * Errors: E_INVALID, E_SHAPE, E_NOMEM, E_DEVICE.
+ */
+cspd_status cspd_ksvd_update(const float *x, int64_t P, int32_t N, float *dict, int32_t T, const int32_t *support,
+                             float *coef, int32_t kstride, void *hip_stream);
+
+/* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of reconstruction jobs on one device.      */
 /* (Not in the paper: a request loop around the calls above.)             */
 /* ---------------------------------------------------------------------- */

@@ -10,6 +10,7 @@ Names follow the C entry points:
   cspd_graph_cross_scale, cspd_graph_launch, cspd_graph_destroy,
   cspd_autotune, cspd_tuned_kernel, cspd_set_tuned_kernel,
   cspd_patch_count, cspd_extract_patches, cspd_aggregate_patches,
+  cspd_ksvd_update,
   cspd_serve_create, cspd_serve_submit, cspd_serve_poll, cspd_serve_destroy,
   cspd_last_error, cspd_version.
 """
@@ -123,6 +124,8 @@ SIGNATURES = {
     "cspd_extract_patches": (C.c_int32, [C.POINTER(PatchGrid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_void_p]),
     "cspd_aggregate_patches": (C.c_int32, [C.POINTER(PatchGrid), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cspd_ksvd_update": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                     C.c_void_p, C.c_int32, C.c_void_p]),
     "cspd_profile_enable": (C.c_int32, [C.c_int32]),
     "cspd_profile_read": (C.c_int32, [C.c_int32, C.c_char_p, C.c_int32, C.POINTER(C.c_int64),
                                       C.POINTER(C.c_double)]),
@@ -440,6 +443,22 @@ def cspd_aggregate_patches(grid: PatchGrid, estimates, out=None, stream=None):
         out = torch.empty(dims, dtype=torch.float32, device=estimates.device)
     _check(load().cspd_aggregate_patches(C.byref(grid), _ptr(estimates), _ptr(out), _stream(stream)))
     return out
+
+
+def cspd_ksvd_update(x, dict_rows, support, coef, stream=None):
+    """One K-SVD dictionary-update sweep in place: x (P, N) float32, dict_rows
+    (T, N) float32 (one atom per row), support (P, k) int32, coef (P, k)
+    float32 -- all contiguous device tensors."""
+    torch = _torch()
+    P, N = x.shape
+    T = dict_rows.shape[0]
+    k = support.shape[1]
+    for name, t, shape, dt in (("x", x, (P, N), torch.float32), ("dict_rows", dict_rows, (T, N), torch.float32),
+                               ("support", support, (P, k), torch.int32), ("coef", coef, (P, k), torch.float32)):
+        if t.dtype != dt or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dt} tensor of shape {shape}")
+    _check(load().cspd_ksvd_update(_ptr(x), P, N, _ptr(dict_rows), T, _ptr(support), _ptr(coef), k,
+                                   _stream(stream)))
 
 
 def cspd_profile_enable(on: bool = True):
