@@ -339,8 +339,13 @@ void k_omp_scale(ScaleArgs a)
     constexpr int LPA = GRAM ? LP_GRAM : LP;
     constexpr int VL = (GRAM || MG) ? 1 : LP;   // per-slot vector registers
     constexpr int LH = MG ? LP / 2 : 1;         // coordinates per lane and patch (matrix-core Gram)
-    constexpr int NGM = (MG && PPW == 1) ? 4 : 2;   // 32 x 32 Gram blocks per wavefront
+    // 32 x 32 Gram blocks kept per wavefront: two patches, or one patch's
+    // (0,0), (0,1) and (1,1) blocks; (1,0) is the transpose of (0,1)
+    constexpr int NGM = (MG && PPW == 1) ? 3 : 2;
+    constexpr bool G01T = MG && PPW == 1;       // (0,1) block also in LDS, column-major
+    constexpr int G01S = 36;                    // its column stride (16-byte rows, banks spread)
     __shared__ GroupLds<T, LPA, KM> lds[W * PPW];
+    __shared__ __attribute__((aligned(16))) float g01_lds[G01T ? W : 1][G01T ? 32 * G01S : 1];
     __shared__ double lds64[W][KX * KX + 4 * KX];
     extern __shared__ double dyn_lds[];     // block-fold staging (fold_lds_bytes)
     const int lane = threadIdx.x & 63;
@@ -581,9 +586,9 @@ void k_omp_scale(ScaleArgs a)
         // (each lane sums its half of the coordinates, the halves are added)
         // Gram matrices on the matrix cores: lane l ends with column l % 32,
         // rows 8 (r / 4) + 4 (l / 32) + r % 4 of each 32 x 32 block.  Two
-        // patches: block p is patch p's Gram matrix.  One patch: block 2 b + c
-        // holds the products of block-b candidates (rows) with block-c
-        // candidates (columns).
+        // patches: block p is patch p's Gram matrix.  One patch: blocks 0, 1
+        // and 2 hold the products of candidate blocks (0,0), (0,1), (1,1)
+        // (rows from the first block named, columns from the second).
         T hs[2] = {T(0), T(0)}, es[2] = {T(0), T(0)};
 #pragma unroll
         for (int p = 0; p < NGM; ++p)
@@ -630,8 +635,7 @@ void k_omp_scale(ScaleArgs a)
                 } else {
                     gm[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[0][j], vm[0][j], gm[0], 0, 0, 0);
                     gm[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[0][j], vm[1][j], gm[1], 0, 0, 0);
-                    gm[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[1][j], vm[0][j], gm[2], 0, 0, 0);
-                    gm[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[1][j], vm[1][j], gm[3], 0, 0, 0);
+                    gm[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[1][j], vm[1][j], gm[2], 0, 0, 0);
                 }
             }
             // keep the chunks apart: at most one chunk in flight beyond this one
@@ -659,6 +663,16 @@ void k_omp_scale(ScaleArgs a)
                 asm volatile("" : "+v"(t));
                 gm[p][r] = t;
             }
+        if constexpr (G01T) {
+            // block (0,1) column-major: lane (c, half) writes its rows of
+            // column c, four contiguous rows per 16-byte store
+            float *gt = &g01_lds[wv][(lane & 31) * G01S + 4 * hh];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                *reinterpret_cast<float4 *>(gt + 8 * q) =
+                    make_float4(gm[1][4 * q], gm[1][4 * q + 1], gm[1][4 * q + 2], gm[1][4 * q + 3]);
+            wave_sync();
+        }
     } else if constexpr (!GRAM) {
 #pragma unroll
         for (int j = 0; j < LP; ++j) {
@@ -835,19 +849,25 @@ void k_omp_scale(ScaleArgs a)
             // half (kr / 4) % 2, register 4 (kr / 8) + kr % 4; a lane whose
             // own half holds it reads it, the other lane of the pair gets it
             // from its partner, which reads block (bk, 1 - partner half).
+            // Block (1,0) is not kept: its row kr is column kr of block
+            // (0,1), read from LDS.
             const unsigned long long own = __ballot(selected);
             const int k = own ? __builtin_ctzll(own) : 0;
             const int bk = k >> 5, kr = k & 31;
             const int rk = 4 * (kr >> 3) + (kr & 3);
             const int hk = (kr >> 2) & 1;
             // block index by select: only the register index rk is dynamic
-            const float b00 = gm[0][rk], b01 = gm[1][rk], b10 = gm[2][rk], b11 = gm[3][rk];
-            const float b0 = bk ? b10 : b00, b1 = bk ? b11 : b01;
-            const float xo = hh ? b1 : b0;
-            const float xt = hh ? b0 : b1;
+            const float b00 = gm[0][rk], b01 = gm[1][rk], b11 = gm[2][rk];
+            const float b1 = bk ? b11 : b01;
+            const float xo = hh ? b1 : b00;
+            const float xt = hh ? b00 : b1;
             float lo, hi;
             swap_pair<32>(xt, lo, hi);
             gcol[0] = hk == hh ? xo : (hh ? lo : hi);
+            if (bk) {
+                const float t = g01_lds[wv][kr * G01S + (lane & 31)];
+                if (!hh) gcol[0] = t;
+            }
         } else if constexpr (!GRAM) {
             constexpr int CH = LP <= 16 ? LP : 8;
             T cur[CH], nxt[CH];
