@@ -111,7 +111,9 @@ __device__ __attribute__((noinline)) double pivot64(const float *v, int stride, 
 // LQ coordinates per lane (4 LQ per patch), NT tiles of 16 atoms, KM
 // iterations at most.
 template <int LQ, int NT, int KM>
-__global__ __launch_bounds__(64 * W)
+// Four coordinates per lane and K <= 4: three wavefronts per SIMD (a few
+// registers spill, outside the iterations' inner work)
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((LQ == 4 && KM == 4) ? 3 : 1)))
 void k_omp_first(ScaleArgs a)
 {
     constexpr int L = 4 * LQ;
@@ -170,8 +172,8 @@ void k_omp_first(ScaleArgs a)
                     cnt += obs ? 1.f : 0.f;
                     acc += obs ? sh.ys[wv][pj][j] : 0.f;
                 }
-                s_ = sqrtf(cnt);
-                y_ = cnt > 0.f ? acc / s_ : 0.f;
+                s_ = scale_impl::fast_sqrt(cnt);
+                y_ = cnt > 0.f ? acc * __builtin_amdgcn_rsqf(cnt) : 0.f;
                 nz += cnt > 0.f;
             } else {
                 s_ = 1.f;
@@ -192,7 +194,7 @@ void k_omp_first(ScaleArgs a)
         for (int m = 0; m < LQ; ++m)
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(dv[t][m] * dv[t][m], sw[m] * sw[m], acc, 0, 0, 0);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) inv_nu[t][r] = acc[r] > 0.f ? 1.f / sqrtf(acc[r]) : -1.f;
+        for (int r = 0; r < 4; ++r) inv_nu[t][r] = acc[r] > 0.f ? __builtin_amdgcn_rsqf(acc[r]) : -1.f;
     }
 
     int K = 0;
@@ -288,7 +290,7 @@ void k_omp_first(ScaleArgs a)
             else if (!(rho2 > 0.f)) rho2 = (float)piv;
         }
         // new basis vector and the residual's component along it
-        const float inv = act ? 1.f / sqrtf(rho2) : 0.f;
+        const float inv = act ? __builtin_amdgcn_rsqf(rho2) : 0.f;
         float zc = 0.f;
 #pragma unroll
         for (int m = 0; m < LQ; ++m) {
