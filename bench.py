@@ -73,6 +73,8 @@ def kernel_source_hash():
     for name in sorted(os.listdir(csrc)):
         if name.startswith(("omp_scale", "omp_first", "proxy_gemm", "cspd_internal")) and name.endswith((".hip", ".h")):
             h.update(open(os.path.join(csrc, name), "rb").read())
+    # per-file compiler flags change the kernels too
+    h.update(open(os.path.join(ROOT, "paper_1511_05174_amd", "build.py"), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -543,6 +545,47 @@ def traffic_summarize(fetch_db: str, write_db: str, workload: str, command: str)
     print(json.dumps(out))
 
 
+def counters_summarize(dbs, command: str):
+    """Markdown table of the SQ / GRBM counters of the OMP kernels from
+    rocprofv3 --pmc runs over --traffic-probe: per-wavefront instruction
+    counts, and the matrix-core and VALU busy fractions over the launch:
+    busy cycles summed over wavefronts / (SIMDs x launch cycles), the launch
+    cycles being GRBM_GUI_ACTIVE / 8 (the counter adds up the 8 XCDs)."""
+    import collections
+    import sqlite3
+
+    simds = 256 * 4
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    for db in dbs:
+        c = sqlite3.connect(db)
+        for kn, cn, v in c.execute("select kernel_name, counter_name, sum(value) from counters_collection "
+                                   "group by dispatch_id, counter_name"):
+            if "k_omp_" in kn:
+                per[kn.split("(")[0]][cn].append(float(v))
+    lines = ["Command (on the GPU box; `$R` is the repository root), one run per counter set:", "", "```",
+             command, "```", "",
+             "Per launch (median over launches); per-wavefront figures divide by `SQ_WAVES`.  `SQ_*_CYCLES` and "
+             "`SQ_ACTIVE_INST_*` count in units of 4 cycles except `SQ_VALU_MFMA_BUSY_CYCLES` (cycles).", ""]
+    for kn, m in per.items():
+        med = {cn: float(np.median(v)) for cn, v in m.items()}
+        waves = med.get("SQ_WAVES", 1.0)
+        lines.append(f"**`{kn}`** ({waves:.0f} wavefronts)")
+        lines.append("")
+        lines.append("| counter | per launch | per wavefront |")
+        lines.append("|---|---:|---:|")
+        for cn in sorted(med):
+            lines.append(f"| `{cn}` | {med[cn]:.0f} | {med[cn] / waves:.1f} |")
+        gui = med.get("GRBM_GUI_ACTIVE", 0.0) / 8
+        if gui:
+            lines.append(f"| launch cycles (GRBM_GUI_ACTIVE / 8) | {gui:.0f} | |")
+            if "SQ_VALU_MFMA_BUSY_CYCLES" in med:
+                lines.append(f"| matrix cores busy | {med['SQ_VALU_MFMA_BUSY_CYCLES'] / (simds * gui):.3f} | |")
+            if "SQ_ACTIVE_INST_VALU" in med:
+                lines.append(f"| VALU issuing | {4 * med['SQ_ACTIVE_INST_VALU'] / (simds * gui):.3f} | |")
+        lines.append("")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -567,11 +610,16 @@ def main():
                     help="known-size elementwise pass plus cross-scale steps, for rocprofv3 --pmc")
     ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write profiles/traffic_<workload>.json from the two counter runs")
+    ap.add_argument("--counters-summarize", nargs="+", metavar="DB",
+                    help="markdown summary of SQ / GRBM counter runs over --traffic-probe")
     ap.add_argument("--traffic-command", default="",
                     help="the commands that produced the counter runs (recorded in the summary)")
     args = ap.parse_args()
     if args.traffic_probe:
         traffic_probe(args.workload)
+        return
+    if args.counters_summarize:
+        counters_summarize(args.counters_summarize, args.traffic_command)
         return
     if args.traffic_summarize:
         traffic_summarize(args.traffic_summarize[0], args.traffic_summarize[1], args.workload,
