@@ -121,7 +121,7 @@ void k_omp_first(ScaleArgs a)
     static_assert(NT <= 8, "atom bits of a lane fit one word");
     __shared__ FirstLds<L, T> sh;
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wavefront-uniform
     const int pj = lane & 15;           // patch within the wavefront
     const int qd = lane >> 4;           // coordinate quarter
     const int64_t first_patch = ((int64_t)blockIdx.x * W + wv) * PW;
@@ -129,21 +129,48 @@ void k_omp_first(ScaleArgs a)
     const bool valid = b < a.b;
     const bool fold = a.fold == kFold;
 
-    // ---- workgroup: dictionary and block table into LDS ------------------
-    for (int i = threadIdx.x; i < T * L; i += 64 * W) {
+    // ---- staging: every load is issued before the first LDS store (one
+    // round trip to memory) --------------------------------------------------
+    // workgroup: the dictionary, DV values per thread
+    constexpr int DV = T * L / (64 * W);
+    static_assert(T * L % (64 * W) == 0, "dictionary staging: whole passes of the workgroup");
+    float dst[DV];
+#pragma unroll
+    for (int r = 0; r < DV; ++r) {
+        const int i = threadIdx.x + r * 64 * W;
         const int t = i / L, j = i % L;
-        sh.v[t][j] = (t < a.t && j < a.l) ? ((const float *)a.v)[(int64_t)t * a.lp + j] : 0.f;
+        dst[r] = (t < a.t && j < a.l) ? ((const float *)a.v)[(int64_t)t * a.lp + j] : 0.f;
     }
-    const int ntab = fold ? a.l + 1 + a.n : 0;
-    for (int i = threadIdx.x; i < ntab; i += 64 * W)
-        sh.tab[i] = i <= a.l ? a.blk_off[i] : a.blk_idx[i - a.l - 1];
-    // ---- wavefront: its patches' samples, row after row (coalesced) ------
+    // wavefront: its patches' samples, one row per patch, a lane per sample
+    // (ny <= 64; each row coalesced)
     const int ny = fold ? a.n : a.l;
-    for (int i = lane; i < PW * ny; i += 64) {
-        const int p = i / ny, j = i % ny;
+    const bool lin = lane < ny;
+    const int jl = lin ? lane : 0;
+    const bool has_mask = fold && a.mask;
+    float yst[PW];
+    unsigned char mst[PW];
+#pragma unroll
+    for (int p = 0; p < PW; ++p) {
         const int64_t row = first_patch + p < a.b ? first_patch + p : a.b - 1;
-        sh.ys[wv][p][j] = ((const float *)a.y)[row * (int64_t)a.y_stride + j];
-        sh.ms[wv][p][j] = (fold && a.mask) ? a.mask[row * (int64_t)a.n + j] : (unsigned char)1;
+        yst[p] = ((const float *)a.y)[row * (int64_t)a.y_stride + jl];
+        mst[p] = has_mask ? a.mask[row * (int64_t)a.n + jl] : (unsigned char)1;
+    }
+    // the fold's block table (at most 1 + 2 NMAX entries: one pass)
+    const int ntab = fold ? a.l + 1 + a.n : 0;
+    const int it = threadIdx.x;
+    const int tabv = it < ntab ? (it <= a.l ? a.blk_off[it] : a.blk_idx[it - a.l - 1]) : 0;
+#pragma unroll
+    for (int r = 0; r < DV; ++r) {
+        const int i = threadIdx.x + r * 64 * W;
+        sh.v[i / L][i % L] = dst[r];
+    }
+    if (it < ntab) sh.tab[it] = tabv;
+    if (lin) {
+#pragma unroll
+        for (int p = 0; p < PW; ++p) {
+            sh.ys[wv][p][lane] = yst[p];
+            sh.ms[wv][p][lane] = mst[p];
+        }
     }
     __syncthreads();
 
