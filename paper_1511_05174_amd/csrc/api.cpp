@@ -141,6 +141,7 @@ ScaleArgs base_args(const cspd_plan_s *p, int s, int64_t B, const void *y, const
     a.blk_off = sc.blk_off;
     a.blk_idx = sc.blk_idx;
     a.blk_ident = sc.blk_ident;
+    a.gsplit = sc.gsplit;
     a.q = sc.q;
     a.d_high = p->d_high;
     return a;

@@ -54,6 +54,7 @@ struct ScalePlan {
     int *blk_off = nullptr;   // l + 1 (fold only): fine samples of each coarse sample
     int *blk_idx = nullptr;   // N (fold only)
     int blk_ident = 0;        // fold whose blocks are single samples in signal order
+    float gsplit = 2048.f;    // power of two: scale of the matrix-core Gram's FP16 split
 };
 
 }  // namespace cspd
@@ -128,6 +129,7 @@ struct ScaleArgs {
     const void *hpre;           // b x t correlations with y (gram mode, first scale), or null;
                                 // for launch_choice: the workspace the GEMM variant writes them to
     const void *nu2;            // t squared effective norms (with hpre)
+    float gsplit;               // power of two: candidates times it fit FP16 (split Gram)
 };
 
 // Kernel variants that can run one scale (FP32): the first-scale MFMA kernel,

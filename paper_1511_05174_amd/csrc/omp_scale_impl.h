@@ -330,7 +330,7 @@ __device__ __attribute__((noinline)) void gram64_chol(const T *v, int lp, int l,
 }
 
 template <typename T, int LP, int NC, int PPW, int KM, bool GRAM, bool MG>
-__global__ __launch_bounds__(64 * W)
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((MG && PPW == 2 && LP <= 64 && KM <= 8) ? 4 : 1)))
 void k_omp_scale(ScaleArgs a)
 {
     static_assert(!MG || (sizeof(T) == 4 && NC == 1 && (PPW == 1 || PPW == 2) && !GRAM && LP >= 16 && LP <= 128),
@@ -343,6 +343,7 @@ void k_omp_scale(ScaleArgs a)
     // (0,0), (0,1) and (1,1) blocks; (1,0) is the transpose of (0,1)
     constexpr int NGM = (MG && PPW == 1) ? 3 : 2;
     constexpr bool G01T = MG && PPW == 1;       // (0,1) block also in LDS, column-major
+    constexpr bool F16G = MG && PPW == 2;       // Gram from a split into FP16 products
     constexpr int G01S = 36;                    // its column stride (16-byte rows, banks spread)
     __shared__ GroupLds<T, LPA, KM> lds[W * PPW];
     __shared__ __attribute__((aligned(16))) float g01_lds[G01T ? W : 1][G01T ? 32 * G01S : 1];
@@ -580,6 +581,9 @@ void k_omp_scale(ScaleArgs a)
 #pragma unroll
     for (int s = 0; s < NC; ++s) { h[s] = T(0); ee[s] = T(0); }
     typedef float gram_t __attribute__((ext_vector_type(16)));
+    typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+    typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+    typedef float float2v __attribute__((ext_vector_type(2)));
     gram_t gm[NGM];
     if constexpr (MG) {
         // weighted candidates, their correlations with y-hat and squared norms
@@ -620,22 +624,52 @@ void k_omp_scale(ScaleArgs a)
 #pragma unroll
                 for (int j = 0; j < MCH; ++j) {
                     const T sw = wp.sqw[hh * LH + c0 + j], yh = wp.yhat[hh * LH + c0 + j];
-                    const T xv = vm[p][j] * sw;
+                    // split Gram: candidates scaled by a power of two (exact), see below
+                    const T xv = vm[p][j] * (F16G ? sw * a.gsplit : sw);
                     const T x = livep[p] ? xv : T(0);
                     vm[p][j] = x;
                     hs[p] += x * yh;
                     es[p] += x * x;
                 }
             }
+            if constexpr (F16G) {
+                // Two patches: each Gram matrix from FP16 matrix-core products
+                // of a two-term split, x' = s x = h + l with h = fp16(x')
+                // (nearest) and l = fp16(x' - h): G' = H H^T + H L^T + L H^T
+                // (the dropped L L^T and the rounding of l are ~2^-22 of
+                // |x_i| |x_j|, the size of FP32 accumulation error); G = G' / s^2.
+                // s (a power of two, from the plan) keeps |x'| <= 2^14.
+                // Lane l supplies k-slots 8 (l / 32) .. + 7 of candidate l % 32
+                // from its own half of the coordinates, the same for A and B.
 #pragma unroll
-            for (int j = 0; j < MCH; ++j) {
-                if constexpr (PPW == 2) {
-                    gm[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[0][j], vm[0][j], gm[0], 0, 0, 0);
-                    gm[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[1][j], vm[1][j], gm[1], 0, 0, 0);
-                } else {
-                    gm[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[0][j], vm[0][j], gm[0], 0, 0, 0);
-                    gm[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[0][j], vm[1][j], gm[1], 0, 0, 0);
-                    gm[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[1][j], vm[1][j], gm[2], 0, 0, 0);
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int c = 0; c < MCH; c += 8) {
+                        half8 hv, lv;
+#pragma unroll
+                        for (int e = 0; e < 8; e += 2) {
+                            const float2v xp = {vm[p][c + e], vm[p][c + e + 1]};
+                            const half2v hp = __builtin_convertvector(xp, half2v);
+                            const float2v hb = __builtin_convertvector(hp, float2v);
+                            const half2v lp = __builtin_convertvector(xp - hb, half2v);
+                            hv[e] = hp[0]; hv[e + 1] = hp[1];
+                            lv[e] = lp[0]; lv[e + 1] = lp[1];
+                        }
+                        gm[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv, hv, gm[p], 0, 0, 0);
+                        gm[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv, lv, gm[p], 0, 0, 0);
+                        gm[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(lv, hv, gm[p], 0, 0, 0);
+                    }
+            } else {
+#pragma unroll
+                for (int j = 0; j < MCH; ++j) {
+                    if constexpr (PPW == 2) {
+                        gm[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[0][j], vm[0][j], gm[0], 0, 0, 0);
+                        gm[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[1][j], vm[1][j], gm[1], 0, 0, 0);
+                    } else {
+                        gm[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[0][j], vm[0][j], gm[0], 0, 0, 0);
+                        gm[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[0][j], vm[1][j], gm[1], 0, 0, 0);
+                        gm[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[1][j], vm[1][j], gm[2], 0, 0, 0);
+                    }
                 }
             }
             // keep the chunks apart: at most one chunk in flight beyond this one
@@ -650,16 +684,18 @@ void k_omp_scale(ScaleArgs a)
             swap_pair<32>(es[p], lo, hi);
             ef[p] = lo + hi;
         }
-        // a lane's own candidate is in slot lane / 32 (patch or block)
-        h[0] = hh ? hf[1] : hf[0];
-        ee[0] = hh ? ef[1] : ef[0];
+        // a lane's own candidate is in slot lane / 32 (patch or block); the
+        // split Gram's scaling comes off exactly (powers of two)
+        const float gi1 = F16G ? 1.f / a.gsplit : 1.f, gi2 = gi1 * gi1;   // exact
+        h[0] = (hh ? hf[1] : hf[0]) * gi1;
+        ee[0] = (hh ? ef[1] : ef[0]) * gi2;
         // keep the Gram entries in ordinary VGPRs, where a row can be picked
         // by a wavefront-uniform register index
 #pragma unroll
         for (int p = 0; p < NGM; ++p)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                float t = gm[p][r];
+                float t = F16G ? gm[p][r] * gi2 : gm[p][r];
                 asm volatile("" : "+v"(t));
                 gm[p][r] = t;
             }

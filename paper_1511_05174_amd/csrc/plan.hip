@@ -107,6 +107,21 @@ __global__ void k_gram(const double *__restrict__ w64, int t_atoms, int l, T *__
     g[idx] = (T)s;
 }
 
+// Largest |entry| of n values (one workgroup of 256; plan time only).
+__global__ void k_absmax(const double *__restrict__ a, int64_t n, double *__restrict__ out)
+{
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, fabs(a[i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 template <typename T>
@@ -223,6 +238,26 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
         sc.lp = 16;
         while (sc.lp < l) sc.lp *= 2;   // row stride = the kernels' register bucket
         sc.fold = dense ? kDense : kFold;
+        // scale of the matrix-core Gram's FP16 split: the largest weighted
+        // candidate entry (|v| times the square root of the largest block)
+        // becomes at most 2^14, well inside FP16's range
+        DevBuf amax_d;
+        CSPD_HIP_CHECK(hipMalloc(&amax_d.p, sizeof(double)));
+        k_absmax<<<1, 256, 0, st>>>((const double *)a64.p, (int64_t)l * T, (double *)amax_d.p);
+        CSPD_HIP_CHECK(hipGetLastError());
+        double vmax = 0.0;
+        CSPD_HIP_CHECK(hipMemcpyAsync(&vmax, amax_d.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        CSPD_HIP_CHECK(hipStreamSynchronize(st));
+        int cmax = 1;
+        if (!dense)
+            for (int t = 0; t < ns; ++t) cmax = std::max(cmax, off[t + 1] - off[t]);
+        const double xmax = vmax * std::sqrt((double)cmax);
+        int ex = 11;
+        if (xmax > 0.0 && std::isfinite(xmax)) {
+            ex = (int)std::floor(std::log2(16384.0 / xmax));
+            ex = std::min(60, std::max(-60, ex));   // its square stays a normal float
+        }
+        sc.gsplit = std::ldexp(1.0f, ex);
         const double *wsrc = dense ? (const double *)a64.p : (const double *)w64.p;
         const bool norms = !mask;
         const bool gram = !mask && T <= kMaxGramAtoms && (s == 0 || s == S - 1);

@@ -197,6 +197,17 @@ def test_one_patch_mfma_gram_partial_blocks():
     assert any("mfma" in lab and "ppw1" in lab and lab.endswith(":s1") for lab in labels), labels
 
 
+@pytest.mark.parametrize("alpha", [1e-5, 1e5])
+def test_split_gram_dictionary_scale(alpha):
+    # the two-patch matrix-core Gram works on FP16 parts of the weighted
+    # candidates scaled by a power of two chosen at plan time: dictionaries
+    # far from unit norm (and measurements of their size) keep the FP32 bar
+    import dataclasses
+    w = synth.make("c2", batch=2048)
+    ws = dataclasses.replace(w, dicts=[d * alpha for d in w.dicts], y=w.y * alpha, x=w.x * alpha)
+    check_cross(ws)
+
+
 def test_deterministic():
     w = synth.make("c3", batch=1500)
     plan = cspd.plan_from_workload(w)
