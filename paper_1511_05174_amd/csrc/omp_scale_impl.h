@@ -343,7 +343,7 @@ void k_omp_scale(ScaleArgs a)
     // (0,0), (0,1) and (1,1) blocks; (1,0) is the transpose of (0,1)
     constexpr int NGM = (MG && PPW == 1) ? 3 : 2;
     constexpr bool G01T = MG && PPW == 1;       // (0,1) block also in LDS, column-major
-    constexpr bool F16G = MG && PPW == 2;       // Gram from a split into FP16 products
+    constexpr bool F16G = MG;                   // Gram from a split into FP16 products
     constexpr int G01S = 36;                    // its column stride (16-byte rows, banks spread)
     __shared__ GroupLds<T, LPA, KM> lds[W * PPW];
     __shared__ __attribute__((aligned(16))) float g01_lds[G01T ? W : 1][G01T ? 32 * G01S : 1];
@@ -385,7 +385,7 @@ void k_omp_scale(ScaleArgs a)
     // rows split the coordinates in halves).
     // Long vectors go through the matrix cores in chunks of MCH coordinates
     // (loaded chunk by chunk), so that few registers hold them at a time.
-    constexpr int MCH = (MG && (PPW == 1 || LH >= 64)) ? 16 : LH;
+    constexpr int MCH = (MG && (PPW == 1 || LH >= 64)) ? (PPW == 1 && LH >= 64 ? 8 : 16) : LH;
     T vm[MG ? 2 : 1][MCH];
     T vn[MG && MCH < LH ? 2 : 1][MCH < LH ? MCH : 1];   // next chunk, in flight
     const T *msrc[2] = {nullptr, nullptr};
@@ -632,7 +632,34 @@ void k_omp_scale(ScaleArgs a)
                     es[p] += x * x;
                 }
             }
-            if constexpr (F16G) {
+            if constexpr (F16G && PPW == 1) {
+                // One patch: blocks (0,0), (0,1), (1,1) from the same split
+                // (see the two-patch case below), three products each.
+#pragma unroll
+                for (int c = 0; c < MCH; c += 8) {
+                    half8 hv[2], lv[2];
+#pragma unroll
+                    for (int p = 0; p < 2; ++p)
+#pragma unroll
+                        for (int e = 0; e < 8; e += 2) {
+                            const float2v xp = {vm[p][c + e], vm[p][c + e + 1]};
+                            const half2v hp = __builtin_convertvector(xp, half2v);
+                            const float2v hb = __builtin_convertvector(hp, float2v);
+                            const half2v lp = __builtin_convertvector(xp - hb, half2v);
+                            hv[p][e] = hp[0]; hv[p][e + 1] = hp[1];
+                            lv[p][e] = lp[0]; lv[p][e + 1] = lp[1];
+                        }
+                    gm[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[0], hv[0], gm[0], 0, 0, 0);
+                    gm[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[0], lv[0], gm[0], 0, 0, 0);
+                    gm[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(lv[0], hv[0], gm[0], 0, 0, 0);
+                    gm[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[0], hv[1], gm[1], 0, 0, 0);
+                    gm[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[0], lv[1], gm[1], 0, 0, 0);
+                    gm[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(lv[0], hv[1], gm[1], 0, 0, 0);
+                    gm[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[1], hv[1], gm[2], 0, 0, 0);
+                    gm[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[1], lv[1], gm[2], 0, 0, 0);
+                    gm[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(lv[1], hv[1], gm[2], 0, 0, 0);
+                }
+            } else if constexpr (F16G) {
                 // Two patches: each Gram matrix from FP16 matrix-core products
                 // of a two-term split, x' = s x = h + l with h = fp16(x')
                 // (nearest) and l = fp16(x' - h): G' = H H^T + H L^T + L H^T
