@@ -243,6 +243,69 @@ __device__ __forceinline__ T group_sum(T v)
     return v;
 }
 
+// The lanes of a 16-row pair (WIDTH 16) or of two 32-lane halves (WIDTH 32)
+// exchange a (lower row / half) and b (upper): lane r of the lower one ends
+// with (its a, the partner's a), of the upper one with (the partner's b, its
+// b) -- so lo + hi sums a over the pair in the lower and b in the upper.
+template <int WIDTH>
+__device__ __forceinline__ void split_pair(double a, double b, double &lo, double &hi)
+{
+    const long long ba = __double_as_longlong(a), bb = __double_as_longlong(b);
+    int l0, l1, h0, h1;
+    if constexpr (WIDTH == 16) {
+        auto rl = __builtin_amdgcn_permlane16_swap((int)ba, (int)bb, false, false);
+        auto rh = __builtin_amdgcn_permlane16_swap((int)(ba >> 32), (int)(bb >> 32), false, false);
+        l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
+    } else {
+        auto rl = __builtin_amdgcn_permlane32_swap((int)ba, (int)bb, false, false);
+        auto rh = __builtin_amdgcn_permlane32_swap((int)(ba >> 32), (int)(bb >> 32), false, false);
+        l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
+    }
+    lo = __longlong_as_double(((long long)h0 << 32) | (unsigned)l0);
+    hi = __longlong_as_double(((long long)h1 << 32) | (unsigned)l1);
+}
+
+// Sums over a group of G = 32 or 64 lanes of KM per-lane values, sum i
+// returned (as FP32) to lane i of the group (i < KM; other lanes get one of
+// them).  Reduce-scatter: each exchange across 32-lane halves and across
+// 16-lane rows splits the values between the partners, so the rows then
+// sum only KM / 2 (G 32) or KM / 4 (G 64) values; one permute delivers them.
+template <int G, int KM>
+__device__ __forceinline__ float sums_to_lanes(const double (&v)[KM], int lane)
+{
+    static_assert((G == 32 || G == 64) && KM % (G / 16) == 0, "group of 32 or 64 lanes");
+    constexpr int K1 = G == 64 ? KM / 2 : KM;   // after the step across halves
+    constexpr int K2 = K1 / 2;                  // after the step across rows
+    double a1[K1];
+    if constexpr (G == 64) {
+#pragma unroll
+        for (int j = 0; j < K1; ++j) {
+            double lo, hi;
+            split_pair<32>(v[j], v[K1 + j], lo, hi);
+            a1[j] = lo + hi;              // half h holds sums h K1 + j
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < K1; ++j) a1[j] = v[j];
+    }
+    float a2[K2];
+#pragma unroll
+    for (int j = 0; j < K2; ++j) {
+        double lo, hi;
+        split_pair<16>(a1[j], a1[K2 + j], lo, hi);
+        a2[j] = (float)group_sum<16>(lo + hi);   // row r (of its half) holds r K2 + j
+    }
+    // sum i lives on every lane q of row (i / K2) % 2 of half i / K1 as entry
+    // i % K2; lane q offers entry q % K2 (K2 divides 16)
+    const int q = lane & 15;
+    float sel = a2[0];
+#pragma unroll
+    for (int j = 1; j < K2; ++j) sel = (q % K2) == j ? a2[j] : sel;
+    const int i = (lane % G) < KM ? lane % G : 0;
+    const int src = (lane / G) * G + (i / K1) * 32 + ((i / K2) & 1) * 16 + q;
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(sel)));
+}
+
 template <int G>
 __device__ __forceinline__ int group_count(bool pred, int lane)
 {
@@ -777,7 +840,9 @@ void k_omp_scale(ScaleArgs a)
         c[s] = h[s];
         e[s] = ee[s];
         e0[s] = ee[s];
-        nu[s] = T(1) / sqrt(ee[s]);   // inverse norm
+        // inverse norm (FP32: the hardware reciprocal square root, 1 ulp)
+        if constexpr (sizeof(T) == 4) nu[s] = __builtin_amdgcn_rsqf(ee[s]);
+        else nu[s] = T(1) / sqrt(ee[s]);
         if (!(ee[s] > T(0))) live[s] = false;  // an effective column of zero is never picked
     }
 
@@ -1071,10 +1136,14 @@ void k_omp_scale(ScaleArgs a)
                 }
             }
             T rme = 0;
+            if constexpr (G >= 32 && KM >= 4) {
+                rme = sums_to_lanes<G, KM>(part, lane);
+            } else {
 #pragma unroll
-            for (int i = 0; i < KM; ++i) {
-                const double ri = group_sum<G>(part[i]);
-                rme = gl == i ? (T)ri : rme;
+                for (int i = 0; i < KM; ++i) {
+                    const double ri = group_sum<G>(part[i]);
+                    rme = gl == i ? (T)ri : rme;
+                }
             }
             T dl = 0;
 #pragma unroll
