@@ -3,23 +3,13 @@
 
 namespace cspd {
 
+cspd_status dispatch_scale_f32_k16_mg(const ScaleArgs &a, int lp, int ppw, hipStream_t st);
+
 cspd_status dispatch_scale_f32_k16(const ScaleArgs &a, int lp, int nc, int ppw, bool gram, bool mg,
                                      hipStream_t st)
 {
     using namespace scale_impl;
-    if (mg) {
-        if (ppw == 2) {
-            if (lp == 16) return launch_one<float, 16, 1, 2, 16, false, true>(a, st);
-            if (lp == 32) return launch_one<float, 32, 1, 2, 16, false, true>(a, st);
-            if (lp == 64) return launch_one<float, 64, 1, 2, 16, false, true>(a, st);
-            if (lp == 128) return launch_one<float, 128, 1, 2, 16, false, true>(a, st);
-        } else if (ppw == 1) {
-            if (lp == 32) return launch_one<float, 32, 1, 1, 16, false, true>(a, st);
-            if (lp == 64) return launch_one<float, 64, 1, 1, 16, false, true>(a, st);
-            if (lp == 128) return launch_one<float, 128, 1, 1, 16, false, true>(a, st);
-        }
-        return CSPD_E_UNSUPPORTED;
-    }
+    if (mg) return dispatch_scale_f32_k16_mg(a, lp, ppw, st);
     if (gram) {
         switch (nc) {
             case 1: return launch_one<float, 0, 1, 1, 16, true>(a, st);

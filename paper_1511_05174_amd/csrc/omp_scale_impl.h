@@ -1026,14 +1026,14 @@ void k_omp_scale(ScaleArgs a)
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             const T g = gcol[s];
-            // u rows are zero past n: with up to 8 atoms the iterations are
-            // unrolled and the sum stops at n; beyond, it runs over all KM
-            // entries in four independent chains (no loop bound, short
-            // dependence)
+            // u rows are zero past n: with up to 8 atoms (and for the
+            // matrix-core kernels, built unrolled) the iterations are unrolled
+            // and the sum stops at n; otherwise it runs over all KM entries
+            // in four independent chains (no loop bound, short dependence)
             T dp[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
             for (int m = 0; m < KM; ++m) {
-                if (KM <= 8 && m >= n) break;
+                if ((KM <= 8 || MG) && m >= n) break;
                 dp[m & 3] += w.uk[m] * u[s][m];
             }
             const T dot = (dp[0] + dp[1]) + (dp[2] + dp[3]);
@@ -1047,7 +1047,7 @@ void k_omp_scale(ScaleArgs a)
         T xp[4] = {T(0), T(0), T(0), T(0)};   // x is zero past n as well
 #pragma unroll
         for (int m = 0; m < KM; ++m) {
-            if (KM <= 8 && m >= n) break;
+            if ((KM <= 8 || MG) && m >= n) break;
             xp[m & 3] += w.uk[m] * x[m];
         }
         const T xd = (gl == n ? T(1) : T(0)) - ((xp[0] + xp[1]) + (xp[2] + xp[3]));
