@@ -250,9 +250,10 @@ void k_omp_first(ScaleArgs a)
     for (int n = 0; n < KM; ++n) {
         if (n >= kwave) break;
         bool act = active && n < K;
-        // proxy of every atom; lane rows ascend, so '>' keeps the lower atom on ties
-        float bsc = -1.f;
-        int bidx = INT_MAX;
+        // proxy of every atom of this lane (slot 4 t + r is atom 16 t + 4 qd + r:
+        // slots ascend with the atom index)
+        float scs[4 * NT];
+        int sid[4 * NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -262,12 +263,22 @@ void k_omp_first(ScaleArgs a)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const bool ok = inv_nu[t][r] > 0.f && !((used >> (4 * t + r)) & 1u);
-                const float sc = ok ? fabsf(acc[r]) * inv_nu[t][r] : -1.f;
-                const bool up = sc > bsc;
-                bsc = up ? sc : bsc;
-                bidx = up ? 16 * t + 4 * qd + r : bidx;
+                scs[4 * t + r] = ok ? fabsf(acc[r]) * inv_nu[t][r] : -1.f;
+                sid[4 * t + r] = 4 * t + r;
             }
         }
+        // best slot by a pairwise tree (depth log2(4 NT) instead of a chain):
+        // the left slot of a pair is the lower atom, so '>' keeps it on ties
+#pragma unroll
+        for (int wd = 1; wd < 4 * NT; wd *= 2)
+#pragma unroll
+            for (int f = 0; f + wd < 4 * NT; f += 2 * wd) {
+                const bool up = scs[f + wd] > scs[f];
+                scs[f] = up ? scs[f + wd] : scs[f];
+                sid[f] = up ? sid[f + wd] : sid[f];
+            }
+        float bsc = scs[0];
+        int bidx = 16 * (sid[0] >> 2) + 4 * qd + (sid[0] & 3);
         quad_argmax(bsc, bidx);
         act = act && bsc >= 0.f && n < rank_bound;
         const int k = act ? bidx : 0;
