@@ -265,6 +265,21 @@ __device__ __forceinline__ void split_pair(double a, double b, double &lo, doubl
     hi = __longlong_as_double(((long long)h1 << 32) | (unsigned)l1);
 }
 
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+// Low parts of a two-term FP16 split: fp16(x - h) for the pair x with high
+// parts h = fp16(x).  x - h is exact in FP32; v_fma_mix_f32 forms it from the
+// packed FP16 h directly (h * -1 + x), one instruction per element.
+__device__ __forceinline__ half2v split_lo(float2v x, half2v h)
+{
+    float r0, r1;
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r0) : "v"(h), "v"(x[0]));
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r1) : "v"(h), "v"(x[1]));
+    const float2v r = {r0, r1};
+    return __builtin_convertvector(r, half2v);
+}
+
 // Sums over a group of G = 32 or 64 lanes of KM per-lane values, sum i
 // returned (as FP32) to lane i of the group (i < KM; other lanes get one of
 // them).  Reduce-scatter: each exchange across 32-lane halves and across
@@ -645,8 +660,6 @@ void k_omp_scale(ScaleArgs a)
     for (int s = 0; s < NC; ++s) { h[s] = T(0); ee[s] = T(0); }
     typedef float gram_t __attribute__((ext_vector_type(16)));
     typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-    typedef _Float16 half2v __attribute__((ext_vector_type(2)));
-    typedef float float2v __attribute__((ext_vector_type(2)));
     gram_t gm[NGM];
     if constexpr (MG) {
         // weighted candidates, their correlations with y-hat and squared norms
@@ -707,8 +720,7 @@ void k_omp_scale(ScaleArgs a)
                         for (int e = 0; e < 8; e += 2) {
                             const float2v xp = {vm[p][c + e], vm[p][c + e + 1]};
                             const half2v hp = __builtin_convertvector(xp, half2v);
-                            const float2v hb = __builtin_convertvector(hp, float2v);
-                            const half2v lp = __builtin_convertvector(xp - hb, half2v);
+                            const half2v lp = split_lo(xp, hp);
                             hv[p][e] = hp[0]; hv[p][e + 1] = hp[1];
                             lv[p][e] = lp[0]; lv[p][e + 1] = lp[1];
                         }
@@ -740,8 +752,7 @@ void k_omp_scale(ScaleArgs a)
                         for (int e = 0; e < 8; e += 2) {
                             const float2v xp = {vm[p][c + e], vm[p][c + e + 1]};
                             const half2v hp = __builtin_convertvector(xp, half2v);
-                            const float2v hb = __builtin_convertvector(hp, float2v);
-                            const half2v lp = __builtin_convertvector(xp - hb, half2v);
+                            const half2v lp = split_lo(xp, hp);
                             hv[e] = hp[0]; hv[e + 1] = hp[1];
                             lv[e] = lp[0]; lv[e + 1] = lp[1];
                         }
