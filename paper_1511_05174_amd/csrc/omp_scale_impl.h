@@ -700,9 +700,11 @@ void k_omp_scale(ScaleArgs a)
 #pragma unroll
                 for (int j = 0; j < MCH; ++j) {
                     const T sw = wp.sqw[hh * LH + c0 + j], yh = wp.yhat[hh * LH + c0 + j];
-                    // split Gram: candidates scaled by a power of two (exact), see below
+                    // split Gram: candidates scaled by a power of two (exact), see
+                    // below.  With two patches a dead slot keeps atom 0's vector:
+                    // its Gram row and column, h and e are never read (score -1)
                     const T xv = vm[p][j] * (F16G ? sw * a.gsplit : sw);
-                    const T x = livep[p] ? xv : T(0);
+                    const T x = (PPW == 2 || livep[p]) ? xv : T(0);
                     vm[p][j] = x;
                     hs[p] += x * yh;
                     es[p] += x * x;
@@ -720,7 +722,7 @@ void k_omp_scale(ScaleArgs a)
                         for (int e = 0; e < 8; e += 2) {
                             const float2v xp = {vm[p][c + e], vm[p][c + e + 1]};
                             const half2v hp = __builtin_convertvector(xp, half2v);
-                            const half2v lp = split_lo(xp, hp);
+                            const half2v lp = __builtin_convertvector(xp - __builtin_convertvector(hp, float2v), half2v);
                             hv[p][e] = hp[0]; hv[p][e + 1] = hp[1];
                             lv[p][e] = lp[0]; lv[p][e + 1] = lp[1];
                         }
@@ -1147,7 +1149,7 @@ void k_omp_scale(ScaleArgs a)
                 }
             }
             T rme = 0;
-            if constexpr (G >= 32 && KM >= 4) {
+            if constexpr (G >= 32 && KM >= 8) {
                 rme = sums_to_lanes<G, KM>(part, lane);
             } else {
 #pragma unroll
