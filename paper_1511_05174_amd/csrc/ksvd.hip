@@ -168,16 +168,19 @@ __global__ __launch_bounds__(BS) void k_atom(int k, int n, const int *__restrict
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // C is stored in full and symmetric: lane i reads column i
+            // (c[j n + i]), so the wavefront's reads of one j are consecutive
+            // words, not one bank 64 times over
             double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
             if (i < n) {
                 int j = 0;
                 for (; j + 4 <= n; j += 4) {
-                    a0 += c[i * n + j] * v[j];
-                    a1 += c[i * n + j + 1] * v[j + 1];
-                    a2 += c[i * n + j + 2] * v[j + 2];
-                    a3 += c[i * n + j + 3] * v[j + 3];
+                    a0 += c[j * n + i] * v[j];
+                    a1 += c[(j + 1) * n + i] * v[j + 1];
+                    a2 += c[(j + 2) * n + i] * v[j + 2];
+                    a3 += c[(j + 3) * n + i] * v[j + 3];
                 }
-                for (; j < n; ++j) a0 += c[i * n + j] * v[j];
+                for (; j < n; ++j) a0 += c[j * n + i] * v[j];
             }
             const double wi = (a0 + a1) + (a2 + a3);
             double nn = wi * wi;
