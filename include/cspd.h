@@ -123,7 +123,8 @@ typedef struct cspd_graph_s *cspd_graph_t;
  * (Section III-C, (P_low) / (P_high)) with their column norms, plus the
  * block tables of U.  Blocks until the plan is resident.  The plan owns all
  * of its device memory; release it with cspd_plan_destroy.
- * Errors: E_INVALID, E_SHAPE, E_NOMEM, E_DEVICE.
+ * Errors: E_INVALID, E_SHAPE (among others: atoms[s] not a multiple of
+ * atoms[s-1], or 2^22 or more children per atom), E_NOMEM, E_DEVICE.
  */
 cspd_status cspd_plan(const cspd_plan_desc *desc, cspd_plan_t *out);
 

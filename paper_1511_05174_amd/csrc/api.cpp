@@ -58,6 +58,10 @@ cspd_status validate_desc(const cspd_plan_desc *d)
         if (s > 0 && d->atoms[s] % d->atoms[s - 1] != 0)
             return set_error(CSPD_E_SHAPE, "atoms[%d] = %d is not a multiple of atoms[%d] = %d", s,
                              d->atoms[s], s - 1, d->atoms[s - 1]);
+        // the kernels divide candidate indices by q with a 32-bit high multiply
+        if (s > 0 && d->atoms[s] / d->atoms[s - 1] >= (1 << 22))
+            return set_error(CSPD_E_SHAPE, "scale %d: %d children per atom (at most 2^22 - 1)", s,
+                             d->atoms[s] / d->atoms[s - 1]);
         // kernels index a dictionary with 32-bit offsets (rows padded to at
         // most twice the length, and at least the measurement dimension)
         const int64_t len = 2 * (int64_t)(d->dim[s] > d->m ? d->dim[s] : d->m) + 16;
@@ -143,6 +147,7 @@ ScaleArgs base_args(const cspd_plan_s *p, int s, int64_t B, const void *y, const
     a.blk_ident = sc.blk_ident;
     a.gsplit = sc.gsplit;
     a.q = sc.q;
+    a.qmagic = sc.q > 1 ? (unsigned)((((uint64_t)1 << 32) + (uint64_t)sc.q - 1) / (uint64_t)sc.q) : 0u;
     a.d_high = p->d_high;
     return a;
 }

@@ -115,6 +115,7 @@ struct ScaleArgs {
     int prev_count;             // entries of the previous scale in each prev_sup row
     const int *prev_kused;      // b
     int q;                      // children per parent
+    unsigned qmagic;            // ceil(2^32 / q) for q > 1 (division by q as a high multiply)
     const int *kvec;            // b or null
     int kuni;                   // uniform k
     int last;                   // 1: write coefficients / x-hat

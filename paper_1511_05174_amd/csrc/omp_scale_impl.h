@@ -268,6 +268,13 @@ __device__ __forceinline__ void split_pair(double a, double b, double &lo, doubl
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef float float2v __attribute__((ext_vector_type(2)));
 
+// ci / q for a candidate index ci < 2^16 (the parent slot of child ci): one
+// high multiply by the plan's ceil(2^32 / q), exact while q < 2^16
+__device__ __forceinline__ int child_parent(int ci, const ScaleArgs &a)
+{
+    return a.q == 1 ? ci : (int)__umulhi((unsigned)ci, a.qmagic);
+}
+
 // Low parts of a two-term FP16 split: fp16(x - h) for the pair x with high
 // parts h = fp16(x).  x - h is exact in FP32; v_fma_mix_f32 forms it from the
 // packed FP16 h directly (h * -1 + x), one instruction per element.
@@ -481,9 +488,9 @@ void k_omp_scale(ScaleArgs a)
                 livep[p] = ci < ncp;
                 int at = ci;
                 if (!a.first) {
-                    const int pj = livep[p] ? ci / a.q : 0;
+                    const int pj = livep[p] ? child_parent(ci, a) : 0;
                     const int pi = __shfl(pvv, (PPW == 2 ? p * 32 : 0) + pj, 64);
-                    at = pi * a.q + ci % a.q;
+                    at = pi * a.q + (ci - pj * a.q);
                 }
                 msrc[p] = (const T *)a.v + (int64_t)(livep[p] ? at : 0) * LP + hh * LH;
                 if constexpr (MCH == LH) {
@@ -502,9 +509,9 @@ void k_omp_scale(ScaleArgs a)
             int at = ci;
             if (!a.first) {
                 // parent ci / q of the previous support, from the lane that loaded it
-                const int pj = live[s] ? ci / a.q : 0;
+                const int pj = live[s] ? child_parent(ci, a) : 0;
                 const int pi = __shfl(pvv, pj, G);
-                at = pi * a.q + ci % a.q;
+                at = pi * a.q + (ci - pj * a.q);
             }
             atom[s] = live[s] ? at : INT_MAX;
             src[s] = (const T *)a.v + (int64_t)(live[s] ? at : 0) * (GRAM ? lp : LP);

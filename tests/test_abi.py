@@ -55,6 +55,8 @@ def _desc(**over):
     (dict(up_maps=[np.full(16, 7, dtype=np.int32)]), cspd.E_SHAPE),   # outside [0, N_0)
     (dict(up_maps=[np.zeros(16, dtype=np.int32)]), cspd.E_SHAPE),     # not onto
     (dict(dtype="f64", corr_mode="bf16"), cspd.E_INVALID),
+    (dict(dims=[1, 1], atoms=[1, 1 << 22], dicts=[np.ones((1, 1)), np.ones((1 << 22, 1))],
+          up_maps=[np.zeros(1, dtype=np.int32)], m=1, k_max=1), cspd.E_SHAPE),   # 2^22 children per atom
 ])
 def test_plan_validation(over, code):
     with pytest.raises(cspd.CspdError) as ei:
