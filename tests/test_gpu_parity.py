@@ -208,6 +208,15 @@ def test_split_gram_dictionary_scale(alpha):
     check_cross(ws)
 
 
+def test_children_not_a_power_of_two():
+    # q = 3 children per coarse atom: the child map's division by q is a
+    # high multiply by a plan-time reciprocal
+    import dataclasses
+    w = synth.make("c1", batch=2048)
+    w3 = dataclasses.replace(w, atoms=[64, 192], dicts=[w.dicts[0], w.dicts[1][:192]])
+    check_cross(w3, dtype="f32")
+
+
 def test_deterministic():
     w = synth.make("c3", batch=1500)
     plan = cspd.plan_from_workload(w)
