@@ -69,8 +69,15 @@ ProfileToken *profile_begin(const char *label, hipStream_t stream)
 {
     if (!g_on.load(std::memory_order_relaxed) || t_suspended) return nullptr;
     ProfileToken *t = new ProfileToken();
-    if (hipEventCreate(&t->start) != hipSuccess) { delete t; return nullptr; }
-    if (hipEventCreate(&t->stop) != hipSuccess) { (void)hipEventDestroy(t->start); delete t; return nullptr; }
+    // timing-only events: no system-scope fence (cache writeback and
+    // invalidation) at each record, which would slow the kernels that follow
+    constexpr unsigned kFlags = hipEventDisableSystemFence;
+    if (hipEventCreateWithFlags(&t->start, kFlags) != hipSuccess) { delete t; return nullptr; }
+    if (hipEventCreateWithFlags(&t->stop, kFlags) != hipSuccess) {
+        (void)hipEventDestroy(t->start);
+        delete t;
+        return nullptr;
+    }
     {
         std::lock_guard<std::mutex> g(g_mu);
         t->entry = entry_for(label);
