@@ -208,6 +208,22 @@ def test_split_gram_dictionary_scale(alpha):
     check_cross(ws)
 
 
+def test_three_scale_mask_blocks_split_gram():
+    # a masked 3-scale plan whose middle scale folds blocks of four fine
+    # samples (weights sqrt(observed) up to 2): the split Gram's scale covers
+    # the weights, and the middle scale runs the two-patch matrix-core Gram
+    import dataclasses
+    from synth.workloads import box_map
+    w = synth.make("c2", batch=4096)
+    rng = np.random.default_rng(11)
+    d0 = rng.standard_normal((32, 4))
+    d0 /= np.linalg.norm(d0, axis=1, keepdims=True)
+    up01 = box_map((4, 4), (2, 2))[0].astype(np.int32)
+    w3 = dataclasses.replace(w, dims=[4, 16, 64], atoms=[32, 128, 1024], dicts=[d0, w.dicts[0], w.dicts[1]],
+                             up_maps=[up01, w.up_maps[0]], k_scales=[2, 4, 8])
+    check_cross(w3)
+
+
 def test_children_not_a_power_of_two():
     # q = 3 children per coarse atom: the child map's division by q is a
     # high multiply by a plan-time reciprocal
