@@ -1,6 +1,7 @@
 // Internal declarations shared by the cspd HIP sources (not installed).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -177,6 +178,28 @@ cspd_status launch_full_mfma(const cspd_plan_s *p, int64_t b, const void *y, con
 struct ProfileToken;
 ProfileToken *profile_begin(const char *label, hipStream_t stream);
 void profile_end(ProfileToken *tok, hipStream_t stream);
+// The same for a launch that records the token's events itself (the
+// dispatch's own start and end timestamps, no extra packets on the stream):
+// profile_open gives the events to pass to hipExtLaunchKernel, profile_close
+// files the token.
+ProfileToken *profile_open(const char *label, hipEvent_t *start, hipEvent_t *stop);
+void profile_close(ProfileToken *tok);
+
+// Launches a kernel on `stream`, timed by profile_open / profile_close when
+// recording is on (the kernel's own dispatch records the events).
+template <typename K, typename... Args>
+inline void launch_timed(const char *label, K kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t stream,
+                         Args... args)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ProfileToken *tok = profile_open(label, &e0, &e1);
+    if (tok) {
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, stream, e0, e1, 0, args...);
+        profile_close(tok);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shm, stream, args...);
+    }
+}
 // While alive, this thread's launches record no profiling events (graph capture).
 struct ProfileSuspend {
     ProfileSuspend();

@@ -367,9 +367,7 @@ cspd_status launch(const ScaleArgs &a, hipStream_t st)
     const unsigned grid = (unsigned)((waves + W - 1) / W);
     char label[112];
     snprintf(label, sizeof(label), "omp_first_mfma<f32,l%d,t%d,k%d>:s%d", 4 * LQ, 16 * NT, KM, a.scale);
-    ProfileToken *tok = profile_begin(label, st);
-    hipLaunchKernelGGL((k_omp_first<LQ, NT, KM>), dim3(grid), dim3(64 * W), 0, st, a);
-    profile_end(tok, st);
+    launch_timed(label, k_omp_first<LQ, NT, KM>, dim3(grid), dim3(64 * W), 0u, st, a);
     CSPD_HIP_CHECK(hipGetLastError());
     return CSPD_OK;
 }

@@ -485,9 +485,7 @@ cspd_status launch(const FullArgs &a, hipStream_t st)
     const char *ty = CM == CM_BF16 ? "bf16" : (CM == CM_F16 ? "f16" : "f32");
     snprintf(label, sizeof(label), "omp_full_mfma<%s,lp%d,k%d%s,m%d>:full", ty, LP, KM, MASK ? ",mask" : "",
              CM == CM_NATIVE ? 0 : 8 * RR);
-    ProfileToken *tok = profile_begin(label, st);
-    hipLaunchKernelGGL((k_omp_full<LP, KM, MASK, CM, RR>), dim3(grid), dim3(64 * NW), 0, st, a);
-    profile_end(tok, st);
+    launch_timed(label, k_omp_full<LP, KM, MASK, CM, RR>, dim3(grid), dim3(64 * NW), 0u, st, a);
     CSPD_HIP_CHECK(hipGetLastError());
     return CSPD_OK;
 }

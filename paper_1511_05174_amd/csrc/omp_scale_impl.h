@@ -1277,10 +1277,8 @@ cspd_status launch_one(const ScaleArgs &a, hipStream_t st)
     else
         snprintf(label, sizeof(label), "omp_scale<%s,%s,lp%d,nc%d,ppw%d,k%d>:s%d", sizeof(T) == 8 ? "f64" : "f32",
                  mode, GRAM ? a.lp : LP, NC, PPW, KM, a.scale);
-    ProfileToken *tok = profile_begin(label, st);
-    hipLaunchKernelGGL((k_omp_scale<T, LP, NC, PPW, KM, GRAM, MG>), dim3(grid), dim3(64 * W),
-                       fold_lds_bytes(a, sizeof(T), PPW), st, a);
-    profile_end(tok, st);
+    launch_timed(label, k_omp_scale<T, LP, NC, PPW, KM, GRAM, MG>, dim3(grid), dim3(64 * W),
+                 (uint32_t)fold_lds_bytes(a, sizeof(T), PPW), st, a);
     CSPD_HIP_CHECK(hipGetLastError());
     return CSPD_OK;
 }

@@ -94,6 +94,35 @@ void profile_end(ProfileToken *t, hipStream_t stream)
     g_entries[t->entry].pending.push_back(t);
 }
 
+ProfileToken *profile_open(const char *label, hipEvent_t *start, hipEvent_t *stop)
+{
+    *start = nullptr;
+    *stop = nullptr;
+    if (!g_on.load(std::memory_order_relaxed) || t_suspended) return nullptr;
+    ProfileToken *t = new ProfileToken();
+    constexpr unsigned kFlags = hipEventDisableSystemFence;
+    if (hipEventCreateWithFlags(&t->start, kFlags) != hipSuccess) { delete t; return nullptr; }
+    if (hipEventCreateWithFlags(&t->stop, kFlags) != hipSuccess) {
+        (void)hipEventDestroy(t->start);
+        delete t;
+        return nullptr;
+    }
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        t->entry = entry_for(label);
+    }
+    *start = t->start;
+    *stop = t->stop;
+    return t;
+}
+
+void profile_close(ProfileToken *t)
+{
+    if (!t) return;
+    std::lock_guard<std::mutex> g(g_mu);
+    g_entries[t->entry].pending.push_back(t);
+}
+
 }  // namespace cspd
 
 using namespace cspd;

@@ -79,10 +79,8 @@ cspd_status launch(const ScaleArgs &a, float *h, hipStream_t st)
 {
     const int64_t waves = (a.b + 31) / 32;
     const unsigned grid = (unsigned)((waves + W - 1) / W);
-    ProfileToken *tok = profile_begin("proxy_gemm<f32>:s0", st);
-    hipLaunchKernelGGL((k_proxy_gemm<LP>), dim3(grid), dim3(64 * W), 0, st, (const float *)a.y, a.y_stride,
-                       a.m_dense, a.b, (const float *)a.v, a.lp, a.t, h);
-    profile_end(tok, st);
+    launch_timed("proxy_gemm<f32>:s0", k_proxy_gemm<LP>, dim3(grid), dim3(64 * W), 0u, st, (const float *)a.y,
+                 a.y_stride, a.m_dense, a.b, (const float *)a.v, a.lp, a.t, h);
     return hipGetLastError() == hipSuccess ? CSPD_OK : CSPD_E_DEVICE;
 }
 
