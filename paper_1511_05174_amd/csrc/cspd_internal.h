@@ -16,8 +16,9 @@ namespace cspd {
 constexpr int kMaxK = 16;
 // Per-patch Gram tables are precomputed for shared operators up to this size.
 constexpr int kMaxGramAtoms = 1024;
-// Patches (waves) per workgroup of the per-patch kernels.
-constexpr int kWavesPerBlock = 4;
+// Wavefronts per workgroup of the per-scale kernels (two measured faster than
+// four or eight: finer scheduling, less LDS per workgroup).
+constexpr int kWavesPerBlock = 2;
 
 cspd_status set_error(cspd_status code, const char *fmt, ...);
 void clear_error();
