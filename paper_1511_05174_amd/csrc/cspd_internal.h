@@ -16,9 +16,10 @@ namespace cspd {
 constexpr int kMaxK = 16;
 // Per-patch Gram tables are precomputed for shared operators up to this size.
 constexpr int kMaxGramAtoms = 1024;
-// Wavefronts per workgroup of the per-scale kernels (two measured faster than
-// four or eight: finer scheduling, less LDS per workgroup).
-constexpr int kWavesPerBlock = 2;
+// Wavefronts per workgroup of the per-scale kernels (their wavefronts share
+// nothing; one measured faster than two, four or eight: finer scheduling,
+// less LDS per workgroup).
+constexpr int kWavesPerBlock = 1;
 
 cspd_status set_error(cspd_status code, const char *fmt, ...);
 void clear_error();
