@@ -16,10 +16,9 @@ namespace cspd {
 constexpr int kMaxK = 16;
 // Per-patch Gram tables are precomputed for shared operators up to this size.
 constexpr int kMaxGramAtoms = 1024;
-// Wavefronts per workgroup of the per-scale kernels (their wavefronts share
-// nothing; one measured faster than two, four or eight: finer scheduling,
-// less LDS per workgroup).
-constexpr int kWavesPerBlock = 1;
+// Wavefronts per workgroup of the per-patch kernels (the matrix-core Gram
+// kernels use one; see waves_per_block).
+constexpr int kWavesPerBlock = 4;
 
 cspd_status set_error(cspd_status code, const char *fmt, ...);
 void clear_error();

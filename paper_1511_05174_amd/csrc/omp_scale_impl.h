@@ -35,7 +35,12 @@
 namespace cspd {
 namespace scale_impl {
 
-constexpr int W = kWavesPerBlock;
+// Wavefronts per workgroup: one for the matrix-core Gram kernels (their
+// wavefronts share nothing; measured faster than two, four or eight), the
+// library's default for the others (one was 1.5x slower for the Gram-table
+// kernel over 1,024 atoms).
+template <bool MG>
+constexpr int waves_per_block() { return MG ? 1 : kWavesPerBlock; }
 constexpr int KX = kMaxK;        // FP64 rare-path table size
 constexpr int LP_GRAM = 256;     // LDS row length for gram-mode kernels
 
@@ -415,9 +420,11 @@ __device__ __attribute__((noinline)) void gram64_chol(const T *v, int lp, int l,
 }
 
 template <typename T, int LP, int NC, int PPW, int KM, bool GRAM, bool MG>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((MG && PPW == 2 && LP <= 64 && KM <= 8) ? 4 : 1)))
+__global__ __launch_bounds__(64 * waves_per_block<MG>())
+__attribute__((amdgpu_waves_per_eu((MG && PPW == 2 && LP <= 64 && KM <= 8) ? 4 : 1)))
 void k_omp_scale(ScaleArgs a)
 {
+    constexpr int W = waves_per_block<MG>();
     static_assert(!MG || (sizeof(T) == 4 && NC == 1 && (PPW == 1 || PPW == 2) && !GRAM && LP >= 16 && LP <= 128),
                   "matrix-core Gram: FP32, one slot, one or two patches per wavefront");
     constexpr int G = 64 / PPW;
@@ -1258,15 +1265,16 @@ void k_omp_scale(ScaleArgs a)
 
 // Dynamic LDS of one workgroup: per group the patch's observed samples and
 // their indicators (2 n values), per wavefront the block table (l + 1 + n).
-inline size_t fold_lds_bytes(const ScaleArgs &a, size_t elem, int ppw)
+inline size_t fold_lds_bytes(const ScaleArgs &a, size_t elem, int ppw, int w)
 {
     if (a.fold != kFold || a.blk_ident) return 0;
-    return elem * (size_t)(W * ppw * 2 * a.n) + sizeof(int) * (size_t)(W * (a.l + 1 + a.n));
+    return elem * (size_t)(w * ppw * 2 * a.n) + sizeof(int) * (size_t)(w * (a.l + 1 + a.n));
 }
 
 template <typename T, int LP, int NC, int PPW, int KM, bool GRAM, bool MG = false>
 cspd_status launch_one(const ScaleArgs &a, hipStream_t st)
 {
+    constexpr int W = waves_per_block<MG>();
     const int64_t waves = (a.b + PPW - 1) / PPW;
     const unsigned grid = (unsigned)((waves + W - 1) / W);
     char label[112];
@@ -1278,7 +1286,7 @@ cspd_status launch_one(const ScaleArgs &a, hipStream_t st)
         snprintf(label, sizeof(label), "omp_scale<%s,%s,lp%d,nc%d,ppw%d,k%d>:s%d", sizeof(T) == 8 ? "f64" : "f32",
                  mode, GRAM ? a.lp : LP, NC, PPW, KM, a.scale);
     launch_timed(label, k_omp_scale<T, LP, NC, PPW, KM, GRAM, MG>, dim3(grid), dim3(64 * W),
-                 (uint32_t)fold_lds_bytes(a, sizeof(T), PPW), st, a);
+                 (uint32_t)fold_lds_bytes(a, sizeof(T), PPW, W), st, a);
     CSPD_HIP_CHECK(hipGetLastError());
     return CSPD_OK;
 }
