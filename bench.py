@@ -562,7 +562,7 @@ def counters_summarize(dbs, command: str):
                                    "group by dispatch_id, counter_name"):
             if "k_omp_" in kn:
                 per[kn.split("(")[0]][cn].append(float(v))
-    lines = ["Command (on the GPU box; `$R` is the repository root), one run per counter set:", "", "```",
+    lines = ["Command (on the MI355X machine; `$R` is the repository root), one run per counter set:", "", "```",
              command, "```", "",
              "Per launch (median over launches); per-wavefront figures divide by `SQ_WAVES`.  `SQ_*_CYCLES` and "
              "`SQ_ACTIVE_INST_*` count in units of 4 cycles except `SQ_VALU_MFMA_BUSY_CYCLES` (cycles).", ""]
