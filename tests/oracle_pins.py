@@ -355,11 +355,103 @@ def pin_stopping(lib, seed=20):
 
 
 # --------------------------------------------------------------------------
-# Forced prefix: replaying another solver's choices.
+# Forced prefix and per-step trace: replaying another solver's choices.
+# The near-tie rule that excuses a GPU pick reads the trace (best score,
+# runner-up, score of the pick, step-1 maximum), so both are pinned.
 # --------------------------------------------------------------------------
+FORCED_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "omp_forced.json")
+
+
+def pin_golden_forced(lib):
+    """Hand-worked runs with imposed picks (tests/golden/omp_forced.json):
+    supports, coefficients and all four trace values of every step."""
+    g = json.load(open(FORCED_GOLDEN))
+    for case in g["cases"]:
+        k = case["k"]
+        forced = np.asarray(case["forced"], dtype=np.int32).reshape(1, 1, k)
+        out = _single(case["dict_atoms"], case["y"], k, lib, forced=forced, kstride=k, with_trace=True)
+        ku = int(out["k_used"][0, 0])
+        assert ku == case["k_used"], (case["name"], ku)
+        assert list(out["support"][0, :ku]) == case["support"], (case["name"], out["support"][0])
+        np.testing.assert_allclose(out["coef"][0, :ku], case["coef"], rtol=1e-12, atol=1e-12,
+                                   err_msg=case["name"])
+        tr = out["trace"][0, 0]
+        want = np.asarray(case["trace"], dtype=np.float64)
+        np.testing.assert_allclose(tr[:len(want)], want, rtol=1e-12, atol=1e-12, err_msg=case["name"])
+
+
+def _greedy_trace(a, y, k, forced):
+    """Independent re-derivation of Algorithm 1 with imposed steps: the residue
+    of every step from LAPACK least squares on the support so far, the scores
+    of the remaining atoms, and the four trace values."""
+    t = a.shape[1]
+    nu = np.linalg.norm(a, axis=0)
+    sup, rows = [], []
+    first = None
+    for n in range(k):
+        r = y if not sup else _lstsq_residual(a[:, sup], y)[0]
+        sc = np.abs(a.T @ r) / nu
+        avail = np.ones(t, dtype=bool)
+        avail[sup] = False
+        order = np.argsort(-np.where(avail, sc, -np.inf), kind="stable")
+        best = sc[order[0]]
+        runner = sc[order[1]] if avail.sum() > 1 else -1.0
+        if first is None:
+            first = best
+        f = int(forced[n])
+        if f >= 0 and not avail[f]:
+            rows.append([0.0, 0.0, 0.0, 0.0])
+            break
+        pick = f if f >= 0 else int(order[0])
+        rows.append([best, runner, sc[pick], first])
+        sup.append(pick)
+    return sup, np.asarray(rows)
+
+
+def pin_trace_bruteforce(lib, trials=60, seed=24):
+    """Random tiny problems with random imposed steps (the runner-up, any
+    other remaining atom, or an atom already chosen): the oracle's supports,
+    coefficients and trace rows equal an independent re-derivation that
+    recomputes every residue with LAPACK least squares."""
+    rng = np.random.default_rng(seed)
+    for trial in range(trials):
+        m, t = int(rng.integers(5, 9)), int(rng.integers(6, 12))
+        k = int(rng.integers(2, min(m, t) - 1))
+        d = rng.standard_normal((t, m))
+        d[rng.integers(0, t)] *= 2.5
+        y = rng.standard_normal(m)
+        a = d.T
+        free, _ = _greedy_trace(a, y, k, [-1] * k)
+        forced = np.full(k, -1, dtype=np.int32)
+        for n in range(k):
+            u = rng.random()
+            if u < 0.3:
+                forced[n] = int(rng.integers(0, t))          # any atom (maybe chosen already)
+            elif u < 0.5 and n == 0:
+                nu = np.linalg.norm(a, axis=0)
+                forced[n] = int(np.argsort(-np.abs(a.T @ y) / nu, kind="stable")[1])   # runner-up
+        sup, rows = _greedy_trace(a, y, k, forced)
+        out = _single(d, y, k, lib, forced=forced.reshape(1, 1, k), kstride=k, with_trace=True)
+        ku = int(out["k_used"][0, 0])
+        assert ku == len(sup), (trial, ku, sup, forced)
+        assert list(out["support"][0, :ku]) == sup, (trial, out["support"][0], sup)
+        tr = out["trace"][0, 0]
+        np.testing.assert_allclose(tr[:len(rows)], rows, rtol=1e-10, atol=1e-12, err_msg=str(trial))
+        assert np.all(tr[len(rows):] == 0.0)
+        if ku:
+            _, beta = _lstsq_residual(a[:, sup], y)
+            np.testing.assert_allclose(out["coef"][0, :ku], beta, rtol=1e-9, atol=1e-12)
+        # without imposed steps the trace's picked score is its best score
+        out0 = _single(d, y, k, lib, with_trace=True)
+        assert list(out0["support"][0, :k]) == free
+        np.testing.assert_array_equal(out0["trace"][0, 0, :, 0], out0["trace"][0, 0, :, 2])
+
+
 def pin_forced(lib, seed=21):
     """Forcing the oracle's own choices reproduces it bit for bit; forcing the
-    runner-up at step 1 yields a run whose later steps are again greedy."""
+    runner-up at the first step of the fine scale gives a trace whose picked
+    score is the runner-up's and whose later steps are greedy again (checked
+    against LAPACK least squares on the forced prefix)."""
     import synth
     w = synth.make("c2", batch=32)
     base = oracle.omp_cross_scale(w, with_trace=True, lib_path=lib)
@@ -367,6 +459,31 @@ def pin_forced(lib, seed=21):
     again = oracle.omp_cross_scale(w, forced=forced, kstride=forced.shape[2], lib_path=lib)
     assert np.array_equal(again["supports"], base["supports"])
     assert np.array_equal(again["coefs"], base["coefs"])
+    S, kst = base["supports"].shape[1], base["supports"].shape[2]
+    for b in range(w.batch):
+        f = np.full((1, S, kst), -1, dtype=np.int32)
+        f[0, 0] = base["supports"][b, 0]                     # keep the coarse scale
+        cand = sorted(p * 8 + j for p in base["supports"][b, 0, :base["k_used"][b, 0]] for j in range(8))
+        a = np.where(w.mask[b][:, None] != 0, w.dicts[1].T, 0.0)
+        nu = np.linalg.norm(a, axis=0)
+        sc = np.full(a.shape[1], -1.0)
+        sc[cand] = np.abs(a[:, cand].T @ w.y[b]) / nu[cand]
+        ru = int(np.argsort(-sc, kind="stable")[1])
+        f[0, 1, 0] = ru
+        sub = synth.subset(w, [b])
+        out = oracle.omp_cross_scale(sub, forced=f, kstride=kst, with_trace=True, lib_path=lib)
+        tr = out["trace"][0, 1]
+        assert out["supports"][0, 1, 0] == ru
+        np.testing.assert_allclose(tr[0, :3], [sc.max(), sc[ru], sc[ru]], rtol=1e-10)
+        np.testing.assert_allclose(tr[:, 3][:out["k_used"][0, 1]], sc.max(), rtol=1e-10)
+        fine = list(out["supports"][0, 1, :out["k_used"][0, 1]])
+        for n in range(1, len(fine)):
+            r = _lstsq_residual(a[:, fine[:n]], w.y[b])[0]
+            s2 = np.full(a.shape[1], -1.0)
+            s2[cand] = np.abs(a[:, cand].T @ r) / nu[cand]
+            s2[fine[:n]] = -1.0
+            assert s2[fine[n]] >= s2.max() - 1e-12, (b, n)
+            np.testing.assert_allclose(tr[n, 2], s2[fine[n]], rtol=1e-9, atol=1e-14)
 
 
 # --------------------------------------------------------------------------
@@ -421,4 +538,5 @@ def pin_three_scales(lib, trials=20, seed=22):
 
 ALL_PINS = [pin_golden, pin_bruteforce_greedy, pin_bruteforce_cross_scale, pin_exact_recovery,
             pin_exact_recovery_cross_scale, pin_orthonormal, pin_invariants, pin_reductions,
-            pin_identity_fold, pin_operators, pin_stopping, pin_forced, pin_three_scales]
+            pin_identity_fold, pin_operators, pin_stopping, pin_forced, pin_golden_forced,
+             pin_trace_bruteforce, pin_three_scales]

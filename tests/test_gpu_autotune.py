@@ -46,9 +46,7 @@ def _check(w, plan, label):
     sup = parity.gpu_scales(w, out["support"], out["k_used"], out["support_coarse"], ks[:-1])
     rep = parity.compare(wo, sup, out["coef"], out["k_used"], out["xhat"], k_scales=ks, tie_tol=TIE)
     _say(f"[{label}] {rep.summary()}")
-    assert not rep.mismatched, rep.mismatched[:10]
-    assert rep.k_used_diff == 0
-    assert rep.coef_rel_max <= COEF and rep.xhat_rel_max <= XHAT
+    rep.check(COEF, XHAT)
     return out
 
 

@@ -1,9 +1,11 @@
 """HIP path against the FP64 oracle, through the C-ABI (MI355X only).
 
 Tolerances: FP32 supports identical to the oracle's except near-ties whose
-FP64 score gap is below 1e-6 of the largest step-1 score of that scale;
-FP32 coefficients and reconstructions within 1e-5 relative (norm-wise per
-patch); FP64 runs within 1e-10 relative with near-ties below 1e-9.
+FP64 score gap is below 1e-6 of the largest step-1 score of that scale, at
+most 1 + B/500 of them per run unless a test states its own bound; FP32
+coefficients within 1e-5 of the patch's largest coefficient magnitude, entry
+by entry; reconstructions within 1e-5 relative (norm-wise per patch); FP64
+runs within 1e-10 with near-ties below 1e-9.
 """
 import sys
 
@@ -25,7 +27,7 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def check_cross(w, dtype=None, k_scales=None, max_mismatch=0):
+def check_cross(w, dtype=None, k_scales=None, max_mismatch=0, max_excused=None):
     dtype = dtype or w.dtype
     plan = cspd.plan_from_workload(w, dtype=dtype)
     out = G.run_cross(plan, w, k_scales=k_scales, dtype=dtype)
@@ -35,14 +37,11 @@ def check_cross(w, dtype=None, k_scales=None, max_mismatch=0):
     rep = parity.compare(wo, sup, out["coef"], out["k_used"], out["xhat"], k_scales=ks,
                          tie_tol=TOL[dtype]["tie"])
     _say(f"[cross {w.name} B={w.batch} {dtype}] {rep.summary()}")
-    assert len(rep.mismatched) <= max_mismatch, rep.mismatched[:10]
-    assert rep.k_used_diff == 0
-    assert rep.coef_rel_max <= TOL[dtype]["coef"]
-    assert rep.xhat_rel_max <= TOL[dtype]["xhat"]
+    rep.check(TOL[dtype]["coef"], TOL[dtype]["xhat"], max_excused=max_excused, max_mismatch=max_mismatch)
     return out, rep
 
 
-def check_full(w, dtype=None, k=None):
+def check_full(w, dtype=None, k=None, max_excused=None):
     dtype = dtype or w.dtype
     plan = cspd.plan_from_workload(w, dtype=dtype)
     out = G.run_full(plan, w, k=k, dtype=dtype)
@@ -54,10 +53,7 @@ def check_full(w, dtype=None, k=None):
     rep = parity.compare(wo, sup, out["coef"], out["k_used"], out["xhat"], full=True, k_scales=ks,
                          tie_tol=TOL[dtype]["tie"])
     _say(f"[full {w.name} B={w.batch} {dtype}] {rep.summary()}")
-    assert len(rep.mismatched) == 0, rep.mismatched[:10]
-    assert rep.k_used_diff == 0
-    assert rep.coef_rel_max <= TOL[dtype]["coef"]
-    assert rep.xhat_rel_max <= TOL[dtype]["xhat"]
+    rep.check(TOL[dtype]["coef"], TOL[dtype]["xhat"], max_excused=max_excused)
     return out, rep
 
 
@@ -139,7 +135,9 @@ def test_dependent_atoms_stop():
     w = synth.custom([8, 16], [4, 16], batch=129, seed=9, k_scales=[2, 8], sigma=0.1, dtype="f32")
     w.dicts[1][1] = w.dicts[1][0]
     w.dicts[1][5] = -w.dicts[1][4]
-    out, _ = check_cross(w)
+    # a duplicate ties its original exactly (gap 0) whenever either is the best
+    # remaining atom, so these patches are allowed more excusals
+    out, _ = check_cross(w, max_excused=12)
     for b in range(w.batch):
         s = set(out["support"][b, :out["k_used"][b]])
         assert not ({0, 1} <= s) and not ({4, 5} <= s)
@@ -266,7 +264,7 @@ def test_c2_full_size_sampled():
     sup = parity.gpu_scales(ws, out["support"][idx], out["k_used"][idx], out["support_coarse"][idx], ks[:-1])
     rep = parity.compare(ws, sup, out["coef"][idx], out["k_used"][idx], out["xhat"][idx], tie_tol=1e-6)
     _say(f"[cross c2 full-size sampled] {rep.summary()}")
-    assert not rep.mismatched and rep.coef_rel_max <= 1e-5 and rep.xhat_rel_max <= 1e-5
+    rep.check(1e-5, 1e-5)
 
 
 # ------------------------------------------- full OMP on matrix cores (large T)
@@ -333,6 +331,5 @@ def test_c3_full_reduced_precision(mode):
     sup = parity.gpu_scales(w, out["support"], out["k_used"])
     rep = parity.compare(wo, sup, out["coef"], out["k_used"], out["xhat"], full=True, tie_tol=1e-6)
     _say(f"[full c3 {mode} B={w.batch}] {rep.summary()}")
-    assert len(rep.mismatched) <= 2, rep.mismatched[:10]
-    assert rep.coef_rel_max <= 1e-5
-    assert rep.xhat_rel_max <= 1e-3
+    rep.check(1e-5, 1e-3, max_mismatch=2)
+    assert rep.xhat_rel_max_mismatched <= 1e-3

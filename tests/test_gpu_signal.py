@@ -78,7 +78,7 @@ def test_inpainting_pipeline_stages():
     rep = parity.compare(wp, gs, coef.double().cpu().numpy(), ku.cpu().numpy(), xh.double().cpu().numpy(),
                          tie_tol=1e-6)
     print(f"[pipeline omp] {rep.summary()}", flush=True)
-    assert not rep.mismatched and rep.coef_rel_max <= 1e-5 and rep.xhat_rel_max <= 1e-5
+    rep.check(1e-5, 1e-5)
     # averaging stage
     assert np.array_equal(img.cpu().numpy(), S.aggregate(xhh, shape, patch, stride).astype(np.float32))
     err = float(np.sqrt(np.mean((img.cpu().numpy() - clean) ** 2)) / np.sqrt(np.mean(clean ** 2)))

@@ -28,6 +28,13 @@ MUTANTS = [
     ("xhat_wrong_atom", "xb[j] += Df[(size_t)sup[k] * N + j] * cf[k];", "xb[j] += Df[(size_t)k * N + j] * cf[k];"),
     ("map_not_composed", "maps[s][j] = md->up_map[s][maps[s + 1][j]];", "maps[s][j] = md->up_map[s][j % md->dim[s + 1]];"),
     ("no_restart_of_residue", "memcpy(r, y, sizeof(double) * (size_t)M);\n    int n = 0;", "if (nc < 0) memcpy(r, y, sizeof(double) * (size_t)M);\n    int n = 0;"),
+    # the per-step trace and the forced prefix behind the near-tie rule
+    ("picked_score_is_best", "picked_score = fabs(dot) / nu[pick];", "picked_score = bs;"),
+    ("first_max_every_step", "if (it == 0) first_max = bs;", "first_max = bs;"),
+    ("forced_ignores_chosen", "if (cand[c] == want && !chosen[c] && nu[c] != 0.0) pick = c;",
+     "if (cand[c] == want && nu[c] != 0.0) pick = c;"),
+    ("runner_up_not_tracked", "else if (score > ss) { ss = score; second = c; }", "else if (0) { ss = score; second = c; }"),
+    ("forced_ignored", "if (io->forced && io->forced[it] >= 0) {", "if (io->forced && io->forced[it] >= 0 && 0) {"),
 ]
 
 RUNNER = r"""
