@@ -173,6 +173,30 @@ cspd_status cspd_omp_cross_scale(cspd_plan_t plan, int64_t B, const void *y, con
                                  void *hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as cspd_omp_cross_scale, same arguments, same kernels and results,
+ * but its workspace (the coarse scales' k_used and supports, and scale 0's
+ * correlations under a shared dense Phi) lives in a static device array of
+ * CSPD_NOALLOC_SCRATCH_BYTES per GPU, reserved when the library's code loads
+ * and held until the process ends; its address on a device is resolved once,
+ * by the first cspd_plan on that device.  The call allocates nothing.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from different threads) race and must be serialised
+ * by the caller (e.g. one stream).  Passing support_coarse lowers the
+ * workspace to 4 (S - 1) bytes per patch (plus 4 T_0 under a dense Phi).
+ * Errors: as for cspd_omp_cross_scale (no E_NOMEM), and E_CAPACITY when the
+ * call's workspace exceeds CSPD_NOALLOC_SCRATCH_BYTES (checked on the host,
+ * before anything is launched).
+ */
+#define CSPD_NOALLOC_SCRATCH_BYTES 33554432 /* 32 MiB */
+cspd_status cspd_omp_cross_scale_noalloc(cspd_plan_t plan, int64_t B, const void *y, const uint8_t *mask,
+                                         const int32_t *k_scale, const int32_t *k_fine,
+                                         int32_t k_fine_uniform, int32_t *support, void *coef,
+                                         int32_t *k_used, void *xhat, int32_t *support_coarse,
+                                         void *hip_stream);
+
+/*
  * A cross-scale call (or, for S = 1, a full-dictionary call) captured once
  * into a HIP graph for a fixed batch and fixed buffers: every scale's kernel
  * is one node, and a replay launches them all with one graph launch, without

@@ -25,6 +25,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcspd.so")
 MAX_SCALES = 4
+NOALLOC_SCRATCH_BYTES = 32 << 20     # CSPD_NOALLOC_SCRATCH_BYTES
 
 OK, E_INVALID, E_SHAPE, E_NOMEM, E_DEVICE, E_BUSY, E_NOTFOUND, E_CAPACITY, E_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
@@ -105,6 +106,9 @@ SIGNATURES = {
     "cspd_omp_cross_scale": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cspd_omp_cross_scale_noalloc": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                                 C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                                 C.c_void_p, C.c_void_p, C.c_void_p]),
     "cspd_graph_cross_scale": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -317,6 +321,22 @@ def cspd_omp_cross_scale(plan: Plan, y, mask=None, k_scale: Sequence[int] = (), 
     _check(load().cspd_omp_cross_scale(plan.handle, B, _ptr(y), _ptr(mask), ks, _ptr(k_fine),
                                        int(k_fine_uniform), _ptr(support), _ptr(coef), _ptr(k_used),
                                        _ptr(xhat), _ptr(support_coarse), _stream(stream)))
+    return support, coef, k_used, xhat
+
+
+def cspd_omp_cross_scale_noalloc(plan: Plan, y, mask=None, k_scale: Sequence[int] = (), k_fine=None,
+                                 k_fine_uniform: int = 0, support=None, coef=None, k_used=None, xhat=None,
+                                 support_coarse=None, want_xhat: bool = True, stream=None):
+    """cspd_omp_cross_scale on the library's static workspace (the C call
+    allocates nothing; outputs the caller does not pass are allocated here,
+    by torch, before the call)."""
+    _check_inputs(plan, y, mask, k_fine)
+    B = y.shape[0]
+    support, coef, k_used, xhat = _outputs(plan, B, support, coef, k_used, xhat, want_xhat)
+    ks = (C.c_int32 * MAX_SCALES)(*([int(v) for v in k_scale] + [0] * (MAX_SCALES - len(k_scale))))
+    _check(load().cspd_omp_cross_scale_noalloc(plan.handle, B, _ptr(y), _ptr(mask), ks, _ptr(k_fine),
+                                               int(k_fine_uniform), _ptr(support), _ptr(coef), _ptr(k_used),
+                                               _ptr(xhat), _ptr(support_coarse), _stream(stream)))
     return support, coef, k_used, xhat
 
 

@@ -13,20 +13,22 @@
 
 namespace cspd {
 
-static thread_local std::string g_err;
+// Message of the last error on this thread: a fixed buffer, so that setting
+// it neither allocates nor throws.
+static thread_local char g_err[512];
 
 cspd_status set_error(cspd_status code, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
-void clear_error() { g_err.clear(); }
+void clear_error() { g_err[0] = 0; }
+
+bool has_error() { return g_err[0] != 0; }
 
 bool scale_vec_fits(int lp, int max_cand, bool f64);
 
@@ -165,8 +167,8 @@ int max_candidates(const cspd_plan_s *p, int s, bool first, int k_prev)
 // Validated scalars of one cross-scale call.
 struct CrossCall {
     int ksum = 0;
-    std::vector<int> cand;
-    std::vector<char> gram;
+    int cand[CSPD_MAX_SCALES] = {};
+    char gram[CSPD_MAX_SCALES] = {};
 };
 
 cspd_status prepare_cross(const cspd_plan_s *p, int64_t B, const void *y, const uint8_t *mask,
@@ -187,8 +189,6 @@ cspd_status prepare_cross(const cspd_plan_s *p, int64_t B, const void *y, const 
     if (!y || !support || !coef || !k_used) return set_error(CSPD_E_INVALID, "y / support / coef / k_used is NULL");
     if (p->phi_kind == CSPD_PHI_MASK && !mask) return set_error(CSPD_E_INVALID, "mask plan needs a mask");
     // candidate counts per scale must have kernels before anything is launched
-    c.cand.assign(p->s, 0);
-    c.gram.assign(p->s, 0);
     for (int s = 0; s < p->s; ++s) {
         const int kprev = s == 0 ? 0 : k_scale[s - 1];
         c.cand[s] = max_candidates(p, s, s == 0, kprev);
@@ -284,7 +284,7 @@ cspd_status launch_cross_scale(const cspd_plan_s *p, int s, const ScaleArgs &a0,
     }
     if (tc.kind != kChoiceAuto && tc.cand == c.cand[s]) {
         const cspd_status rc = launch_choice(p->dtype, a, tc, st);
-        if (rc == CSPD_E_UNSUPPORTED && cspd::g_err.empty())
+        if (rc == CSPD_E_UNSUPPORTED && !has_error())
             return set_error(rc, "scale %d: tuned kernel kind %d (nc %d, ppw %d) cannot run this call", s, tc.kind,
                              tc.nc, tc.ppw);
         return rc;
@@ -370,7 +370,7 @@ using namespace cspd;
 
 extern "C" {
 
-const char *cspd_last_error(void) { return cspd::g_err.c_str(); }
+const char *cspd_last_error(void) { return cspd::g_err; }
 
 const char *cspd_version(void) { return "cspd 0.1 (gfx950)"; }
 
@@ -387,6 +387,7 @@ cspd_status cspd_plan(const cspd_plan_desc *d, cspd_plan_t *out)
     if (d->device >= ndev) return set_error(CSPD_E_INVALID, "device %d of %d", d->device, ndev);
     DeviceGuard g(d->device);
     if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", d->device);
+    noalloc_setup(d->device);
     cspd_plan_s *p = new (std::nothrow) cspd_plan_s();
     if (!p) return set_error(CSPD_E_NOMEM, "host allocation failed");
     p->s = d->n_scales;
@@ -460,7 +461,7 @@ cspd_status cspd_omp_full(cspd_plan_t p, int64_t B, const void *y, const uint8_t
     const bool lowp = p->corr_mode != CSPD_CORR_NATIVE && sc.v_lo != nullptr;
     if ((fits || sc.gram) && !lowp) rc = launch_scale(p->dtype, a, cand, !fits, st);
     else rc = launch_full_mfma(p, B, y, mask, k, k_uniform, support, coef, k_used, xhat, st);
-    if (rc == CSPD_E_UNSUPPORTED && cspd::g_err.empty())
+    if (rc == CSPD_E_UNSUPPORTED && !has_error())
         return set_error(rc, "no full-search kernel for T = %d, length %d", sc.t, sc.l);
     return rc;
 }
@@ -511,7 +512,8 @@ cspd_status cspd_graph_cross_scale(cspd_plan_t p, int64_t B, const void *y, cons
     }
     DeviceGuard g(p->device);
     if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
-    cspd_graph_s *gr = new cspd_graph_s();
+    cspd_graph_s *gr = new (std::nothrow) cspd_graph_s();
+    if (!gr) return set_error(CSPD_E_NOMEM, "host allocation failed");
     gr->device = p->device;
     auto fail = [&](cspd_status code, const char *what) {
         cspd_graph_destroy(gr);
@@ -536,9 +538,10 @@ cspd_status cspd_graph_cross_scale(cspd_plan_t p, int64_t B, const void *y, cons
     const hipError_t ce = hipStreamEndCapture(gr->capture, &graph);
     gr->graph = graph;
     if (rc != CSPD_OK) {
-        const std::string msg = cspd::g_err;
+        char msg[sizeof(cspd::g_err)];
+        std::memcpy(msg, cspd::g_err, sizeof(msg));
         cspd_graph_destroy(gr);
-        return set_error(rc, "%s", msg.c_str());
+        return set_error(rc, "%s", msg);
     }
     if (ce != hipSuccess || !graph) return fail(CSPD_E_DEVICE, "hipStreamEndCapture failed");
     if (hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) != hipSuccess)

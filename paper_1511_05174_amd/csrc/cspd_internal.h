@@ -22,6 +22,10 @@ constexpr int kWavesPerBlock = 4;
 
 cspd_status set_error(cspd_status code, const char *fmt, ...);
 void clear_error();
+bool has_error();
+// Resolves this device's address of the no-allocation entry point's static
+// workspace (once per device; the device must be current).
+void noalloc_setup(int device);
 
 #define CSPD_HIP_CHECK(expr)                                                        \
     do {                                                                            \
