@@ -115,6 +115,7 @@ void free_plan(cspd_plan_s *p)
         ScalePlan &sc = p->sc[s];
         if (sc.v) (void)hipFree(sc.v);
         if (sc.v_lo) (void)hipFree(sc.v_lo);
+        if (sc.v_split) (void)hipFree(sc.v_split);
         if (sc.nu2) (void)hipFree(sc.nu2);
         if (sc.inv_nu) (void)hipFree(sc.inv_nu);
         if (sc.gram) (void)hipFree(sc.gram);
@@ -148,6 +149,7 @@ ScaleArgs base_args(const cspd_plan_s *p, int s, int64_t B, const void *y, const
     a.blk_idx = sc.blk_idx;
     a.blk_ident = sc.blk_ident;
     a.gsplit = sc.gsplit;
+    a.vsplit = sc.v_split;
     a.q = sc.q;
     a.qmagic = sc.q > 1 ? (unsigned)((((uint64_t)1 << 32) + (uint64_t)sc.q - 1) / (uint64_t)sc.q) : 0u;
     a.d_high = p->d_high;

@@ -61,6 +61,10 @@ struct ScalePlan {
     int *blk_idx = nullptr;   // N (fold only)
     int blk_ident = 0;        // fold whose blocks are single samples in signal order
     float gsplit = 2048.f;    // power of two: scale of the matrix-core Gram's FP16 split
+    // FP16 split of gsplit times v (FP32 plans, scales whose candidates carry
+    // weights 0 or 1): per 8 coordinates the four high-part pairs, then the
+    // four low-part pairs; t x lp 32-bit words, or null
+    void *v_split = nullptr;
 };
 
 }  // namespace cspd
@@ -137,6 +141,7 @@ struct ScaleArgs {
                                 // for launch_choice: the workspace the GEMM variant writes them to
     const void *nu2;            // t squared effective norms (with hpre)
     float gsplit;               // power of two: candidates times it fit FP16 (split Gram)
+    const void *vsplit;         // t x lp 32-bit words: the candidates split at plan time, or null
 };
 
 // Kernel variants that can run one scale (FP32): the first-scale MFMA kernel,

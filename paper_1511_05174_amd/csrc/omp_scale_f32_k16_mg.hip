@@ -10,14 +10,14 @@ cspd_status dispatch_scale_f32_k16_mg(const ScaleArgs &a, int lp, int ppw, hipSt
 {
     using namespace scale_impl;
     if (ppw == 2) {
-        if (lp == 16) return launch_one<float, 16, 1, 2, 16, false, true>(a, st);
-        if (lp == 32) return launch_one<float, 32, 1, 2, 16, false, true>(a, st);
-        if (lp == 64) return launch_one<float, 64, 1, 2, 16, false, true>(a, st);
-        if (lp == 128) return launch_one<float, 128, 1, 2, 16, false, true>(a, st);
+        if (lp == 16) return launch_mg<16, 2, 16>(a, st);
+        if (lp == 32) return launch_mg<32, 2, 16>(a, st);
+        if (lp == 64) return launch_mg<64, 2, 16>(a, st);
+        if (lp == 128) return launch_mg<128, 2, 16>(a, st);
     } else if (ppw == 1) {
-        if (lp == 32) return launch_one<float, 32, 1, 1, 16, false, true>(a, st);
-        if (lp == 64) return launch_one<float, 64, 1, 1, 16, false, true>(a, st);
-        if (lp == 128) return launch_one<float, 128, 1, 1, 16, false, true>(a, st);
+        if (lp == 32) return launch_mg<32, 1, 16>(a, st);
+        if (lp == 64) return launch_mg<64, 1, 16>(a, st);
+        if (lp == 128) return launch_mg<128, 1, 16>(a, st);
     }
     return CSPD_E_UNSUPPORTED;
 }

@@ -9,14 +9,14 @@ cspd_status dispatch_scale_f32_k4(const ScaleArgs &a, int lp, int nc, int ppw, b
     using namespace scale_impl;
     if (mg) {
         if (ppw == 2) {
-            if (lp == 16) return launch_one<float, 16, 1, 2, 4, false, true>(a, st);
-            if (lp == 32) return launch_one<float, 32, 1, 2, 4, false, true>(a, st);
-            if (lp == 64) return launch_one<float, 64, 1, 2, 4, false, true>(a, st);
-            if (lp == 128) return launch_one<float, 128, 1, 2, 4, false, true>(a, st);
+            if (lp == 16) return launch_mg<16, 2, 4>(a, st);
+            if (lp == 32) return launch_mg<32, 2, 4>(a, st);
+            if (lp == 64) return launch_mg<64, 2, 4>(a, st);
+            if (lp == 128) return launch_mg<128, 2, 4>(a, st);
         } else if (ppw == 1) {
-            if (lp == 32) return launch_one<float, 32, 1, 1, 4, false, true>(a, st);
-            if (lp == 64) return launch_one<float, 64, 1, 1, 4, false, true>(a, st);
-            if (lp == 128) return launch_one<float, 128, 1, 1, 4, false, true>(a, st);
+            if (lp == 32) return launch_mg<32, 1, 4>(a, st);
+            if (lp == 64) return launch_mg<64, 1, 4>(a, st);
+            if (lp == 128) return launch_mg<128, 1, 4>(a, st);
         }
         return CSPD_E_UNSUPPORTED;
     }

@@ -42,6 +42,11 @@ namespace scale_impl {
 template <bool MG>
 constexpr int waves_per_block() { return MG ? 1 : kWavesPerBlock; }
 constexpr int KX = kMaxK;        // FP64 rare-path table size
+// Condition estimates tr(G) tr(G^{-1}) / n of the final support's Gram
+// matrix above which the coefficients take one step of mixed-precision
+// refinement, and above which they are re-solved in FP64 altogether.
+constexpr double kRefineEst = 20.0;
+constexpr double kBackSubEst = 1e4;
 constexpr int LP_GRAM = 256;     // LDS row length for gram-mode kernels
 
 // LDS exchange between lanes of one wavefront.  Every LDS record of these
@@ -343,8 +348,13 @@ __device__ __forceinline__ int group_count(bool pred, int lane)
 }
 
 // ---- LDS layout: one record per patch group --------------------------------
-template <typename T, int LPA, int KM>
-struct GroupLds {
+template <typename T, int LPA, int KM, int PSN = 1>
+struct alignas(16) GroupLds {
+    // pre-split kernels: the FP16 split of t y-hat (high and low parts of
+    // each coordinate pair) and each pair's observation pattern
+    uint32_t ysh[PSN];
+    uint32_t ysl[PSN];
+    uint32_t mpat[PSN];
     T yhat[LPA];
     T sqw[LPA];
     T vk[LPA];
@@ -419,7 +429,7 @@ __device__ __attribute__((noinline)) void gram64_chol(const T *v, int lp, int l,
     wave_sync();
 }
 
-template <typename T, int LP, int NC, int PPW, int KM, bool GRAM, bool MG>
+template <typename T, int LP, int NC, int PPW, int KM, bool GRAM, bool MG, bool PS>
 __global__ __launch_bounds__(64 * waves_per_block<MG>())
 __attribute__((amdgpu_waves_per_eu((MG && PPW == 2 && LP <= 64 && KM <= 8) ? 4 : 1)))
 void k_omp_scale(ScaleArgs a)
@@ -427,6 +437,8 @@ void k_omp_scale(ScaleArgs a)
     constexpr int W = waves_per_block<MG>();
     static_assert(!MG || (sizeof(T) == 4 && NC == 1 && (PPW == 1 || PPW == 2) && !GRAM && LP >= 16 && LP <= 128),
                   "matrix-core Gram: FP32, one slot, one or two patches per wavefront");
+    static_assert(!PS || MG, "pre-split candidates feed the matrix-core Gram");
+    constexpr int PSN = PS ? LP / 2 : 1;
     constexpr int G = 64 / PPW;
     constexpr int LPA = GRAM ? LP_GRAM : LP;
     constexpr int VL = (GRAM || MG) ? 1 : LP;   // per-slot vector registers
@@ -437,9 +449,9 @@ void k_omp_scale(ScaleArgs a)
     constexpr bool G01T = MG && PPW == 1;       // (0,1) block also in LDS, column-major
     constexpr bool F16G = MG;                   // Gram from a split into FP16 products
     constexpr int G01S = 36;                    // its column stride (16-byte rows, banks spread)
-    __shared__ GroupLds<T, LPA, KM> lds[W * PPW];
+    __shared__ GroupLds<T, LPA, KM, PSN> lds[W * PPW];
     __shared__ __attribute__((aligned(16))) float g01_lds[G01T ? W : 1][G01T ? 32 * G01S : 1];
-    __shared__ double lds64[W][KX * KX + 4 * KX];
+    __shared__ __attribute__((aligned(16))) double lds64[W][KX * KX + 4 * KX];
     extern __shared__ double dyn_lds[];     // block-fold staging (fold_lds_bytes)
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -451,7 +463,7 @@ void k_omp_scale(ScaleArgs a)
     const int64_t b = wave_first + gi;
     const bool valid = b < a.b;
     const int64_t bb = valid ? b : wave_first;   // a row that exists, for loads
-    GroupLds<T, LPA, KM> &w = lds[wv * PPW + gi];
+    GroupLds<T, LPA, KM, PSN> &w = lds[wv * PPW + gi];
     const T *y = (const T *)a.y + bb * (int64_t)a.y_stride;
     const int lp = GRAM ? a.lp : LP;
 
@@ -499,7 +511,10 @@ void k_omp_scale(ScaleArgs a)
                     const int pi = __shfl(pvv, (PPW == 2 ? p * 32 : 0) + pj, 64);
                     at = pi * a.q + (ci - pj * a.q);
                 }
-                msrc[p] = (const T *)a.v + (int64_t)(livep[p] ? at : 0) * LP + hh * LH;
+                // pre-split rows hold, per 8 coordinates, the four high-part
+                // pairs then the four low-part pairs: LP 32-bit words per atom,
+                // read exactly like the FP32 rows (bits only)
+                msrc[p] = (const T *)(PS ? a.vsplit : a.v) + (int64_t)(livep[p] ? at : 0) * LP + hh * LH;
                 if constexpr (MCH == LH) {
 #pragma unroll
                     for (int j = 0; j < LH; j += 4) {
@@ -648,6 +663,38 @@ void k_omp_scale(ScaleArgs a)
         }
     }
 
+    // Pre-split kernels: the measurement is split like the candidates, after
+    // scaling by a power of two t (per patch) that brings its largest entry to
+    // at most 2^14; correlations then come out scaled by t (and by the plan's
+    // split scale s), which changes no comparison (t and s are powers of two).
+    T ysc = T(1);
+    if constexpr (PS) {
+        wave_sync();
+        T ym = T(0);
+#pragma unroll
+        for (int pi = gl; pi < LP / 2; pi += G) {
+            const float2 yv = *reinterpret_cast<const float2 *>(&w.yhat[2 * pi]);
+            ym = fmaxf(ym, fmaxf(fabsf(yv.x), fabsf(yv.y)));
+        }
+        // bit patterns of non-negative floats order like the floats
+        const T ymax = __int_as_float(group_max<G>(__float_as_int(ym)));
+        int ex = 0;
+        (void)frexpf(ymax, &ex);             // ymax = m 2^ex, m in [0.5, 1)
+        ex = ex < -40 ? -40 : (ex > 40 ? 40 : ex);
+        ysc = ymax > T(0) ? ldexpf(1.f, 14 - ex) : T(1);
+#pragma unroll
+        for (int pi = gl; pi < LP / 2; pi += G) {
+            const float2 yv = *reinterpret_cast<const float2 *>(&w.yhat[2 * pi]);
+            const float2 sq = *reinterpret_cast<const float2 *>(&w.sqw[2 * pi]);
+            const float2v xp = {yv.x * ysc, yv.y * ysc};
+            const half2v hp = __builtin_convertvector(xp, half2v);
+            const half2v lo = split_lo(xp, hp);
+            w.ysh[pi] = __builtin_bit_cast(uint32_t, hp);
+            w.ysl[pi] = __builtin_bit_cast(uint32_t, lo);
+            w.mpat[pi] = (sq.x != T(0) ? 0x0000FFFFu : 0u) | (sq.y != T(0) ? 0xFFFF0000u : 0u);
+        }
+    }
+
     int K = 0;
     if (valid) {
         K = kreq < nc ? kreq : nc;
@@ -664,6 +711,10 @@ void k_omp_scale(ScaleArgs a)
     }
 
     // ---- per-candidate state --------------------------------------------
+    // The published u row starts at zero: a pick writes only the entries
+    // filled so far, and a group that has stopped keeps reading entries no
+    // pick wrote (times zero, which must not meet stale bits).
+    if (gl < KM) w.uk[gl] = T(0);
     wave_sync();
 #pragma unroll
     for (int s = 0; s < NC; ++s)
@@ -684,6 +735,7 @@ void k_omp_scale(ScaleArgs a)
         // and 2 hold the products of candidate blocks (0,0), (0,1), (1,1)
         // (rows from the first block named, columns from the second).
         T hs[2] = {T(0), T(0)}, es[2] = {T(0), T(0)};
+        T hs2[2] = {T(0), T(0)};   // pre-split: the two cross terms of the correlations
 #pragma unroll
         for (int p = 0; p < NGM; ++p)
 #pragma unroll
@@ -709,8 +761,8 @@ void k_omp_scale(ScaleArgs a)
                 if (c0 + MCH < LH) load_chunk(c0 + MCH, vn);
             }
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                const GroupLds<T, LPA, KM> &wp = lds[wv * PPW + (PPW == 2 ? p : 0)];
+            for (int p = 0; p < 2 && !PS; ++p) {
+                const GroupLds<T, LPA, KM, PSN> &wp = lds[wv * PPW + (PPW == 2 ? p : 0)];
 #pragma unroll
                 for (int j = 0; j < MCH; ++j) {
                     const T sw = wp.sqw[hh * LH + c0 + j], yh = wp.yhat[hh * LH + c0 + j];
@@ -724,7 +776,70 @@ void k_omp_scale(ScaleArgs a)
                     es[p] += x * x;
                 }
             }
-            if constexpr (F16G && PPW == 1) {
+            if constexpr (PS) {
+                // Pre-split candidates (plan time: s x = h + l, both FP16):
+                // an unobserved coordinate clears its halves with the pair's
+                // pattern (exact: the mask only selects), the correlations
+                // with t y-hat = yh + yl come from packed FP16 dot products
+                // with FP32 accumulation (h yh + h yl + l yh; l yl is below
+                // FP32 rounding), and the Gram matrix from the same three
+                // split products on the matrix cores as below.
+                typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+                for (int c = 0; c < MCH; c += 8) {
+                    half8 hv[2], lv[2];
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        const GroupLds<T, LPA, KM, PSN> &wp = lds[wv * PPW + (PPW == 2 ? p : 0)];
+                        const int pi = (hh * LH + c0 + c) / 2;
+                        u32x4 pat = *reinterpret_cast<const u32x4 *>(&wp.mpat[pi]);
+                        const u32x4 yh = *reinterpret_cast<const u32x4 *>(&wp.ysh[pi]);
+                        const u32x4 yl = *reinterpret_cast<const u32x4 *>(&wp.ysl[pi]);
+                        if constexpr (PPW == 1) {
+                            const uint32_t keep = livep[p] ? 0xFFFFFFFFu : 0u;   // dead slots read as zero
+                            pat &= keep;
+                        }
+                        // (vector elements are copied to scalars before a bit cast:
+                        // a bit cast of an element reference reads element 0)
+                        uint32_t mh[4], ml[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const uint32_t pe = pat[e], yhe = yh[e], yle = yl[e];
+                            mh[e] = __float_as_uint(vm[p][c + e]) & pe;
+                            ml[e] = __float_as_uint(vm[p][c + 4 + e]) & pe;
+                            const half2v h2 = __builtin_bit_cast(half2v, mh[e]);
+                            const half2v l2 = __builtin_bit_cast(half2v, ml[e]);
+                            const half2v y2h = __builtin_bit_cast(half2v, yhe);
+                            const half2v y2l = __builtin_bit_cast(half2v, yle);
+                            hs[p] = __builtin_amdgcn_fdot2(h2, y2h, hs[p], false);
+                            hs2[p] = __builtin_amdgcn_fdot2(h2, y2l, hs2[p], false);
+                            hs2[p] = __builtin_amdgcn_fdot2(l2, y2h, hs2[p], false);
+                        }
+                        const u32x4 mhv = {mh[0], mh[1], mh[2], mh[3]};
+                        const u32x4 mlv = {ml[0], ml[1], ml[2], ml[3]};
+                        hv[p] = __builtin_bit_cast(half8, mhv);
+                        lv[p] = __builtin_bit_cast(half8, mlv);
+                    }
+                    if constexpr (PPW == 1) {
+                        gm[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[0], hv[0], gm[0], 0, 0, 0);
+                        gm[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[0], lv[0], gm[0], 0, 0, 0);
+                        gm[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(lv[0], hv[0], gm[0], 0, 0, 0);
+                        gm[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[0], hv[1], gm[1], 0, 0, 0);
+                        gm[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[0], lv[1], gm[1], 0, 0, 0);
+                        gm[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(lv[0], hv[1], gm[1], 0, 0, 0);
+                        gm[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[1], hv[1], gm[2], 0, 0, 0);
+                        gm[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[1], lv[1], gm[2], 0, 0, 0);
+                        gm[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(lv[1], hv[1], gm[2], 0, 0, 0);
+                    } else {
+#pragma unroll
+                        for (int p = 0; p < 2; ++p) {
+                            gm[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[p], hv[p], gm[p], 0, 0, 0);
+                            gm[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hv[p], lv[p], gm[p], 0, 0, 0);
+                            gm[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(lv[p], hv[p], gm[p], 0, 0, 0);
+                        }
+                    }
+                }
+            } else if constexpr (F16G && PPW == 1) {
                 // One patch: blocks (0,0), (0,1), (1,1) from the same split
                 // (see the two-patch case below), three products each.
 #pragma unroll
@@ -796,26 +911,56 @@ void k_omp_scale(ScaleArgs a)
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             T lo, hi;
-            swap_pair<32>(hs[p], lo, hi);
+            swap_pair<32>(PS ? hs[p] + hs2[p] : hs[p], lo, hi);
             hf[p] = lo + hi;
-            swap_pair<32>(es[p], lo, hi);
-            ef[p] = lo + hi;
+            if constexpr (!PS) {
+                swap_pair<32>(es[p], lo, hi);
+                ef[p] = lo + hi;
+            }
         }
-        // a lane's own candidate is in slot lane / 32 (patch or block); the
-        // split Gram's scaling comes off exactly (powers of two)
-        const float gi1 = F16G ? 1.f / a.gsplit : 1.f, gi2 = gi1 * gi1;   // exact
-        h[0] = (hh ? hf[1] : hf[0]) * gi1;
-        ee[0] = (hh ? ef[1] : ef[0]) * gi2;
+        // a lane's own candidate is in slot lane / 32 (patch or block).  The
+        // iterations run on the split's scaled values: Gram entries and
+        // squared norms times s^2, correlations times s t (s = the plan's
+        // split scale, t = the measurement's; both powers of two, 1 without
+        // the split), so no comparison changes; the coefficients come out
+        // times t / s and are scaled back once.
+        h[0] = hh ? hf[1] : hf[0];
+        if constexpr (!PS) ee[0] = hh ? ef[1] : ef[0];
         // keep the Gram entries in ordinary VGPRs, where a row can be picked
         // by a wavefront-uniform register index
 #pragma unroll
         for (int p = 0; p < NGM; ++p)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                float t = F16G ? gm[p][r] * gi2 : gm[p][r];
+                float t = gm[p][r];
                 asm volatile("" : "+v"(t));
                 gm[p][r] = t;
             }
+        if constexpr (PS) {
+            // squared norms: the Gram diagonal.  Entry (c, c) of a block lives
+            // in lane c + 32 ((c / 4) % 2), register 4 (c / 8) + c % 4; the
+            // lanes that hold one write their column to LDS, every lane reads
+            // its candidate's entry back (one block at a time).
+            float *dump = reinterpret_cast<float *>(lds64[wv]);
+            const int cc = lane & 31;
+            const bool holds = ((cc >> 2) & 1) == hh;
+            float dg = 0.f;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int bq = PPW == 2 ? q : 2 * q;
+                if (holds) {
+#pragma unroll
+                    for (int r = 0; r < 16; r += 4)
+                        *reinterpret_cast<float4 *>(dump + cc * 16 + r) =
+                            make_float4(gm[bq][r], gm[bq][r + 1], gm[bq][r + 2], gm[bq][r + 3]);
+                }
+                wave_sync();
+                const float dv = dump[cc * 16 + 4 * (cc >> 3) + (cc & 3)];
+                dg = hh == q ? dv : dg;
+                wave_sync();
+            }
+            ee[0] = dg;
+        }
         if constexpr (G01T) {
             // block (0,1) column-major: lane (c, half) writes its rows of
             // column c, four contiguous rows per 16-byte store
@@ -882,6 +1027,10 @@ void k_omp_scale(ScaleArgs a)
     constexpr bool KEEP = sizeof(T) == 4 && !GRAM && G * RU >= LP;
     __shared__ T keep_lds[KEEP ? W : 1][KEEP ? RU * KM : 1][64];
 
+    // split scale of the matrix-core Gram (1 otherwise): pivots computed
+    // from the stored vectors in FP64 are multiplied by it
+    const T gs = F16G ? (T)a.gsplit : T(1);
+
     // ---- OMP iterations (Algorithm 1), unrolled so u and x stay in VGPRs
     T x[KM];          // column gl of L^{-1}
 #pragma unroll
@@ -892,7 +1041,8 @@ void k_omp_scale(ScaleArgs a)
     bool active = K > 0;
     int nsel = 0;
     T trg = 0;        // trace of the support's Gram matrix
-    T lmax = 0, lmin = 0;
+    // largest and smallest squared pivot (diagonal of L) accepted so far
+    T p2max = T(0), p2min = sizeof(T) == 4 ? T(3.0e38f) : T(1.0e300);
 #pragma unroll
     for (int n = 0; n < KM; ++n) {
         if (n >= kwave) break;
@@ -900,33 +1050,67 @@ void k_omp_scale(ScaleArgs a)
         // proxy: |<a_i, r>| / ||a_i||, lowest atom index on ties
         T best = T(-1);
         int bidx = INT_MAX;
-#pragma unroll
-        for (int s = 0; s < NC; ++s) {
-            const T sc = live[s] ? fabs(c[s]) * nu[s] : T(-1);
-            const bool up = (sc > best) | ((sc == best) & (atom[s] < bidx));
-            best = up ? sc : best;
-            bidx = up ? atom[s] : bidx;
-        }
-        best = act ? best : T(-1);
-        bidx = act ? bidx : INT_MAX;
-        group_argmax<G>(best, bidx);
-        act = act && best >= T(0);          // candidates exhausted otherwise
-        // the owning lane publishes its vector, its u row and its scalars
         bool selected = false;
+        unsigned long long own = 0;   // lanes that own their group's pick (matrix-core Gram)
+        if constexpr (MG) {
+            // One candidate per lane: the largest score's bit pattern over the
+            // group; the lane that holds it is the pick.  Only when several
+            // lanes of a group hold exactly that score (an exact tie) is the
+            // lowest atom index among them searched.
+            const T sc0 = (act && live[0]) ? fabs(c[0]) * nu[0] : T(-1);
+            const int sb = __float_as_int(sc0);
+            const int mb = group_max<G>(sb);
+            best = __int_as_float(mb);
+            const bool tie = (sb == mb) & (mb >= 0);
+            own = __ballot(tie);
+            bool multi = false;
 #pragma unroll
-        for (int s = 0; s < NC; ++s) {
-            const bool sel = act && live[s] && atom[s] == bidx;
-            selected = selected || sel;
-            if (sel) {
-                if constexpr (!GRAM && !MG) {
+            for (int g = 0; g < PPW; ++g)
+                multi = multi || __popcll(G == 64 ? own : ((own >> (g * G)) & 0xFFFFFFFFull)) > 1;
+            selected = tie;
+            if (multi) {
+                const int mi = group_min<G>(tie ? atom[0] : INT_MAX);
+                selected = tie && atom[0] == mi;
+                own = __ballot(selected);
+            }
+            act = act && best >= T(0);      // candidates exhausted otherwise
+            if (selected) {
 #pragma unroll
-                    for (int j = 0; j < LP; ++j) w.vk[j] = v[s][j];
+                for (int m = 0; m < KM; ++m)
+                    if (m < n) w.uk[m] = u[0][m];   // entries past n are zero and never read
+                w.sc[0] = c[0];
+                w.sc[1] = e[0];
+                w.sc[2] = e0[0];
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < NC; ++s) {
+                const T sc = live[s] ? fabs(c[s]) * nu[s] : T(-1);
+                const bool up = (sc > best) | ((sc == best) & (atom[s] < bidx));
+                best = up ? sc : best;
+                bidx = up ? atom[s] : bidx;
+            }
+            best = act ? best : T(-1);
+            bidx = act ? bidx : INT_MAX;
+            group_argmax<G>(best, bidx);
+            act = act && best >= T(0);      // candidates exhausted otherwise
+            // the owning lane publishes its vector, its u row and its scalars
+#pragma unroll
+            for (int s = 0; s < NC; ++s) {
+                const bool sel = act && live[s] && atom[s] == bidx;
+                selected = selected || sel;
+                if (sel) {
+                    if constexpr (!GRAM) {
+#pragma unroll
+                        for (int j = 0; j < LP; ++j) w.vk[j] = v[s][j];
+                    }
+#pragma unroll
+                    for (int m = 0; m < KM; ++m)
+                        if (KM > 8 || m < n) w.uk[m] = u[s][m];
+                    w.sc[0] = c[s];
+                    w.sc[1] = e[s];
+                    w.sc[2] = e0[s];
                 }
-#pragma unroll
-                for (int m = 0; m < KM; ++m) w.uk[m] = u[s][m];
-                w.sc[0] = c[s];
-                w.sc[1] = e[s];
-                w.sc[2] = e0[s];
             }
         }
         wave_sync();
@@ -937,8 +1121,8 @@ void k_omp_scale(ScaleArgs a)
         bool need64 = false;
         if constexpr (sizeof(T) == 4) {
             // the pivot's own condition estimate: ratio of squared diagonals of L
-            const T hi = n == 0 ? ek : (lmax * lmax > ek ? lmax * lmax : ek);
-            const T lo = n == 0 ? ek : (lmin * lmin < ek ? lmin * lmin : ek);
+            const T hi = p2max > ek ? p2max : ek;
+            const T lo = p2min < ek ? p2min : ek;
             need64 = act && (!(lo > T(0)) || hi > T(1e6) * lo);
         }
         if (act && !need64) {
@@ -952,8 +1136,8 @@ void k_omp_scale(ScaleArgs a)
 #pragma unroll
                 for (int g = 0; g < PPW; ++g) {
                     if ((m64 >> (g * G)) & 1ull) {
-                        GroupLds<T, LPA, KM> &wg = lds[wv * PPW + g];
-                        if (lane == g * G) wg.sup[n] = bidx;
+                        GroupLds<T, LPA, KM, PSN> &wg = lds[wv * PPW + g];
+                        if (MG ? (selected && gi == g) : (lane == g * G)) wg.sup[n] = MG ? atom[0] : bidx;
                         wave_sync();
                         double *g64 = lds64[wv];
                         double *h64 = g64 + KX * KX;
@@ -963,7 +1147,7 @@ void k_omp_scale(ScaleArgs a)
                         if (gi == g) {
                             const double piv = pv[n], gkk = gd[n];
                             if (!(piv > 1e-10 * gkk)) act = false;  // dependent in FP64 as well
-                            else lnn = (T)sqrt(piv);
+                            else lnn = (T)sqrt(piv) * gs;
                         }
                         wave_sync();
                     }
@@ -986,7 +1170,6 @@ void k_omp_scale(ScaleArgs a)
             // the selected candidate's slot in each patch, then its row of the
             // Gram matrix (symmetric): row k, column gl lives in lane
             // gl + 32 ((k / 4) % 2), register 4 (k / 8) + k % 4
-            const unsigned long long own = __ballot(selected);
             const unsigned o0 = (unsigned)own, o1 = (unsigned)(own >> 32);
             const int k0 = o0 ? __builtin_ctz(o0) : 0;
             const int k1 = o1 ? __builtin_ctz(o1) : 0;
@@ -1006,7 +1189,6 @@ void k_omp_scale(ScaleArgs a)
             // from its partner, which reads block (bk, 1 - partner half).
             // Block (1,0) is not kept: its row kr is column kr of block
             // (0,1), read from LDS.
-            const unsigned long long own = __ballot(selected);
             const int k = own ? __builtin_ctzll(own) : 0;
             const int bk = k >> 5, kr = k & 31;
             const int rk = 4 * (kr >> 3) + (kr & 3);
@@ -1068,7 +1250,7 @@ void k_omp_scale(ScaleArgs a)
             u[s][n] = un;
             c[s] -= un * zn;
             e[s] -= un * un;
-            live[s] = live[s] & (atom[s] != kb);
+            live[s] = MG ? (live[s] & !(selected & act)) : (live[s] & (atom[s] != kb));
         }
         // column gl of L^{-1}: new entry of the appended row
         T xp[4] = {T(0), T(0), T(0), T(0)};   // x is zero past n as well
@@ -1081,12 +1263,11 @@ void k_omp_scale(ScaleArgs a)
         x[n] = xd * inv;
         al += x[n] * zn;
         col2 += x[n] * x[n];
-        if (act & (gl == 0)) w.sup[n] = bidx;
+        if (MG ? (act & selected) : (act & (gl == 0))) w.sup[n] = MG ? atom[0] : bidx;
         trg += act ? e0k : T(0);
-        const T lv = act ? lnn : (n == 0 ? T(1) : lmax);
-        lmax = n == 0 ? lv : (lv > lmax ? lv : lmax);
-        const T lw = act ? lnn : (n == 0 ? T(1) : lmin);
-        lmin = n == 0 ? lw : (lw < lmin ? lw : lmin);
+        const T l2 = lnn * lnn;
+        p2max = act ? (l2 > p2max ? l2 : p2max) : p2max;
+        p2min = act ? (l2 < p2min ? l2 : p2min) : p2min;
         nsel = act ? n + 1 : nsel;
         // one patch per wavefront: iterations are strictly sequential, and
         // keeping the scheduler within one bounds the registers in use
@@ -1102,20 +1283,30 @@ void k_omp_scale(ScaleArgs a)
             for (int i = gl; i < a.sup_count; i += G) sup_out[i] = i < nsel ? w.sup[i] : -1;
         return;
     }
-    // coefficients: lane j of the group holds alpha_j
+    // coefficients: lane j of the group holds alpha_j (back from the
+    // split's scaled units: both factors are powers of two)
+    al *= gs / ysc;
     if (gl < nsel) w.alpha[gl] = al;
     // x-hat reuses the refinement's vectors when they are D_high's atoms
     // themselves (finest-scale coordinates that are the signal's samples)
     const bool xkeep = KEEP && a.xhat && a.fold == kFold && a.blk_ident && a.n == a.l;
+    bool kept = false;   // the refinement left the support's vectors in LDS
     if constexpr (sizeof(T) == 4) {
-        // One step of mixed-precision refinement.  The FP32 normal equations
-        // leave an error of about kappa(G) 2^-24; the residual of the normal
+        // Condition estimate of the support's Gram matrix G:
+        // tr(G) tr(G^{-1}) / n lies between kappa(G) / n and n kappa(G).
+        const T trinv = group_sum<G>(col2);
+        const double est = nsel > 1 ? (double)trg * (double)trinv / nsel : 1.0;
+        // One step of mixed-precision refinement where the FP32 solution can
+        // miss the coefficient tolerance.  The FP32 normal equations leave an
+        // error of about kappa(G) 2^-24; the residual of the normal
         // equations, r = A_Omega^T (y-hat - A_Omega alpha), is formed in FP64
         // from the stored vectors, and the correction G^{-1} r = L^{-T} L^{-1} r
         // goes through the FP32 factor (lane j holds column j of L^{-1}),
         // which leaves an error of about (kappa(G) 2^-24)^2.
+        const bool refine = est > kRefineEst;
         wave_sync();
-        {
+        if (__ballot(refine)) {
+            kept = true;
             double part[KM];
             T alv[KM];
             int sid[KM];
@@ -1178,21 +1369,19 @@ void k_omp_scale(ScaleArgs a)
                 const T wm = group_sum<G>(x[m] * rme);
                 dl += x[m] * wm;
             }
-            al += dl;
+            al += dl * (gs * gs);   // x holds L^{-1} of the scaled Gram
         }
         if (gl < nsel) w.alpha[gl] = al;
         // FP64 back-substitution when even the refined FP32 solution would miss
-        // the coefficient tolerance (1e-5 relative): tr(G) tr(G^{-1}) / n
-        // estimates kappa(G) within a factor n.
-        const T trinv = group_sum<G>(col2);
-        const bool ill = nsel > 1 && (double)trg * (double)trinv / nsel > 1e4;
+        // the coefficient tolerance (1e-5 relative)
+        const bool ill = est > kBackSubEst;
         const unsigned long long mi = __ballot(ill);
         wave_sync();
         if (mi) {
 #pragma unroll
             for (int g = 0; g < PPW; ++g) {
                 if ((mi >> (g * G)) & 1ull) {
-                    GroupLds<T, LPA, KM> &wg = lds[wv * PPW + g];
+                    GroupLds<T, LPA, KM, PSN> &wg = lds[wv * PPW + g];
                     const int ng = __builtin_amdgcn_readlane(nsel, g * G);
                     double *g64 = lds64[wv];
                     double *h64 = g64 + KX * KX;
@@ -1225,7 +1414,7 @@ void k_omp_scale(ScaleArgs a)
             alx[i] = in ? w.alpha[i] : T(0);
         }
         if constexpr (KEEP) {
-            if (xkeep) {
+            if (xkeep && kept) {
                 // the lanes past l wrote nothing and store nothing
 #pragma unroll
                 for (int u = 0; u < RU; ++u) {
@@ -1271,7 +1460,7 @@ inline size_t fold_lds_bytes(const ScaleArgs &a, size_t elem, int ppw, int w)
     return elem * (size_t)(w * ppw * 2 * a.n) + sizeof(int) * (size_t)(w * (a.l + 1 + a.n));
 }
 
-template <typename T, int LP, int NC, int PPW, int KM, bool GRAM, bool MG = false>
+template <typename T, int LP, int NC, int PPW, int KM, bool GRAM, bool MG = false, bool PS = false>
 cspd_status launch_one(const ScaleArgs &a, hipStream_t st)
 {
     constexpr int W = waves_per_block<MG>();
@@ -1279,16 +1468,27 @@ cspd_status launch_one(const ScaleArgs &a, hipStream_t st)
     const unsigned grid = (unsigned)((waves + W - 1) / W);
     char label[112];
     const char *mode = GRAM ? "gram" : (MG ? "mfma" : "vec");
+    const char *ps = PS ? ",ps" : "";   // candidates split at plan time
     if (a.first && a.last)
-        snprintf(label, sizeof(label), "omp_scale<%s,%s,lp%d,nc%d,ppw%d,k%d>:full", sizeof(T) == 8 ? "f64" : "f32",
-                 mode, GRAM ? a.lp : LP, NC, PPW, KM);
+        snprintf(label, sizeof(label), "omp_scale<%s,%s,lp%d,nc%d,ppw%d,k%d%s>:full", sizeof(T) == 8 ? "f64" : "f32",
+                 mode, GRAM ? a.lp : LP, NC, PPW, KM, ps);
     else
-        snprintf(label, sizeof(label), "omp_scale<%s,%s,lp%d,nc%d,ppw%d,k%d>:s%d", sizeof(T) == 8 ? "f64" : "f32",
-                 mode, GRAM ? a.lp : LP, NC, PPW, KM, a.scale);
-    launch_timed(label, k_omp_scale<T, LP, NC, PPW, KM, GRAM, MG>, dim3(grid), dim3(64 * W),
+        snprintf(label, sizeof(label), "omp_scale<%s,%s,lp%d,nc%d,ppw%d,k%d%s>:s%d", sizeof(T) == 8 ? "f64" : "f32",
+                 mode, GRAM ? a.lp : LP, NC, PPW, KM, ps, a.scale);
+    launch_timed(label, k_omp_scale<T, LP, NC, PPW, KM, GRAM, MG, PS>, dim3(grid), dim3(64 * W),
                  (uint32_t)fold_lds_bytes(a, sizeof(T), PPW, W), st, a);
     CSPD_HIP_CHECK(hipGetLastError());
     return CSPD_OK;
+}
+
+// Matrix-core Gram kernel: on the plan's pre-split candidates when the scale
+// has them (weights 0 or 1: shared dense operator, or single-sample blocks),
+// else splitting the weighted candidates in the kernel.
+template <int LP, int PPW, int KM>
+cspd_status launch_mg(const ScaleArgs &a, hipStream_t st)
+{
+    if (a.vsplit) return launch_one<float, LP, 1, PPW, KM, false, true, true>(a, st);
+    return launch_one<float, LP, 1, PPW, KM, false, true, false>(a, st);
 }
 
 }  // namespace scale_impl

@@ -72,6 +72,31 @@ __global__ void k_cast_rows_lo(const double *__restrict__ src, int t_atoms, int 
     dst[idx] = h;
 }
 
+// Two-term FP16 split of s v (s a power of two), for the matrix-core Gram:
+// h = fp16(s v) (nearest), l = fp16(s v - h) (s v - h is exact in FP32).
+// Row layout (lp 32-bit words per atom): per 8 coordinates, the four pairs of
+// high parts, then the four pairs of low parts.
+__global__ void k_split_rows(const float *__restrict__ v, int t_atoms, int lp, float s,
+                             uint32_t *__restrict__ out)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)t_atoms * lp) return;
+    const int t = (int)(idx / lp);
+    const int w = (int)(idx % lp);
+    const int k = w & 7;
+    const int j = (w & ~7) + 2 * (k & 3);   // first coordinate of the pair
+    const float *row = v + (int64_t)t * lp;
+    uint32_t word = 0;
+    for (int e = 0; e < 2; ++e) {
+        const float x = row[j + e] * s;
+        const _Float16 h = (_Float16)x;
+        const _Float16 part = k < 4 ? h : (_Float16)(x - (float)h);
+        const uint32_t bits = __builtin_bit_cast(uint16_t, part);
+        word |= bits << (16 * e);
+    }
+    out[idx] = word;
+}
+
 template <typename T>
 __global__ void k_norms(const double *__restrict__ w64, int t_atoms, int l, T *__restrict__ nu2)
 {
@@ -266,6 +291,17 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
             ? finish_scale<double>(sc, (const double *)a64.p, wsrc, norms, gram, 0, st, p->bytes)
             : finish_scale<float>(sc, (const double *)a64.p, wsrc, norms, gram, lo, st, p->bytes);
         if (rc != CSPD_OK) return rc;
+        // candidates whose per-patch weights are 0 or 1 (a shared dense
+        // operator, or coarse samples that are single fine samples) are split
+        // for the matrix-core Gram once here instead of in every patch
+        if (p->dtype == CSPD_F32 && sc.lp >= 16 && sc.lp <= 128 && (dense || sc.blk_ident)) {
+            const size_t sb = sizeof(uint32_t) * (size_t)sc.t * sc.lp;
+            CSPD_HIP_CHECK(hipMalloc(&sc.v_split, sb));
+            p->bytes += (int64_t)sb;
+            k_split_rows<<<blocks_for((int64_t)sc.t * sc.lp, 256), 256, 0, st>>>(
+                (const float *)sc.v, sc.t, sc.lp, sc.gsplit, (uint32_t *)sc.v_split);
+            CSPD_HIP_CHECK(hipGetLastError());
+        }
         if (s == S - 1) {
             // D_high in signal coordinates, atom-contiguous, for x-hat
             size_t eb = p->dtype == CSPD_F64 ? sizeof(double) : sizeof(float);
