@@ -45,20 +45,175 @@ def scale_flops(m: int, t_c: int, k: int, norms: bool) -> int:
 
 def kernel_flops(w, k_scales):
     """FLOPs per patch of each per-scale kernel of the cross-scale call and of
-    the full-OMP call, keyed by the kernel role used in the profile labels."""
+    the full-OMP call, keyed by the kernel role used in the profile labels.
+    With a per-patch finest sparsity (w.k_fine) the finest scale's figure is
+    the mean over the batch."""
     S = w.n_scales
     mask = w.phi_kind == "mask"
     out = {}
     kprev = None
+    kf = None if w.k_fine is None else np.asarray(w.k_fine)
     for s in range(S):
         m = w.m if w.phi_kind == "dense" else w.dims[s]
         t_c = w.atoms[s] if s == 0 else min(w.atoms[s], (w.atoms[s] // w.atoms[s - 1]) * kprev)
-        k = min(k_scales[s], t_c)
-        out[f"s{s}"] = scale_flops(m, t_c, k, mask)
+        if s == S - 1 and kf is not None:
+            vals, counts = np.unique(np.minimum(kf, t_c), return_counts=True)
+            out[f"s{s}"] = float(sum(c * scale_flops(m, t_c, int(v), mask) for v, c in zip(vals, counts))
+                                 / counts.sum())
+            k = int(vals.max())
+        else:
+            k = min(k_scales[s], t_c)
+            out[f"s{s}"] = scale_flops(m, t_c, k, mask)
         kprev = k
     m = w.m if w.phi_kind == "dense" else w.dims[-1]
-    out["full"] = scale_flops(m, w.atoms[-1], min(k_scales[-1], w.atoms[-1]), mask)
+    if kf is not None:
+        vals, counts = np.unique(np.minimum(kf, w.atoms[-1]), return_counts=True)
+        out["full"] = float(sum(c * scale_flops(m, w.atoms[-1], int(v), mask) for v, c in zip(vals, counts))
+                            / counts.sum())
+    else:
+        out["full"] = scale_flops(m, w.atoms[-1], min(k_scales[-1], w.atoms[-1]), mask)
     return out
+
+
+def bound_of(label: str) -> str:
+    """Which roofline bounds a kernel, from its SQ counters: the full-search
+    kernel and the batched correlation GEMM keep the matrix cores busy; the
+    per-patch kernels (per-scale and first-scale) issue VALU on most cycles
+    with the matrix cores under a quarter busy, so their bound is the vector
+    ALU (priced against the FP32 vector peak)."""
+    return "mfma" if label.startswith(("omp_full", "proxy_gemm")) else "alu"
+
+
+def equal_psnr_phase(cspd, w, plan, timed):
+    """The paper's time-accuracy method: full OMP at several K and zero-tree
+    OMP over a (K_low, K_fine) grid on the same patches; for every full point
+    the fastest zero-tree point whose PSNR is at least the full point's minus
+    0.1 dB."""
+    import torch
+    B = w.batch
+    dev = torch.device("cuda", 0)
+    tdt = torch.float64 if w.dtype == "f64" else torch.float32
+    ndt = np.float64 if w.dtype == "f64" else np.float32
+    y = torch.from_numpy(np.ascontiguousarray(w.y.astype(ndt))).to(dev)
+    mask = None if w.mask is None else torch.from_numpy(w.mask).to(dev)
+    sup = torch.empty((B, plan.k_max), dtype=torch.int32, device=dev)
+    coef = torch.empty((B, plan.k_max), dtype=tdt, device=dev)
+    ku = torch.empty((B,), dtype=torch.int32, device=dev)
+    xh = torch.empty((B, w.n), dtype=tdt, device=dev)
+    stream = torch.cuda.current_stream()
+    q = w.atoms[-1] // w.atoms[-2]
+    full_pts = []
+    for kf_ in (2, 3, 4, 5, 6, 8):
+        if kf_ > plan.k_max:
+            continue
+
+        def step_f(k=kf_):
+            cspd.cspd_omp_full(plan, y, mask, None, k, support=sup, coef=coef, k_used=ku, xhat=xh,
+                               stream=stream)
+        t_f, _ = timed(step_f, 3, 1)
+        full_pts.append({"k": kf_, "psnr_db": psnr_db(w.x, xh.double().cpu().numpy()),
+                         "patches_per_s": B / t_f})
+    cross_pts = []
+    for k_low in (2, 3, 4, 6, 8):
+        for k_fine in (3, 4, 5, 6, 8, 10, 12):
+            if k_fine > min(q * k_low, plan.k_max) or q * k_low > 128:
+                continue
+            kk = [k_low, k_fine]
+
+            def step_k(kk=kk):
+                cspd.cspd_omp_cross_scale(plan, y, mask, kk[:-1], None, kk[-1], support=sup, coef=coef,
+                                          k_used=ku, xhat=xh, stream=stream)
+            try:
+                t_k, _ = timed(step_k, 5, 1)
+            except cspd.CspdError:
+                continue
+            cross_pts.append({"k_low": k_low, "k_fine": k_fine,
+                              "psnr_db": psnr_db(w.x, xh.double().cpu().numpy()),
+                              "patches_per_s": B / t_k})
+    pairs = []
+    for fp in full_pts:
+        ok = [c for c in cross_pts if c["psnr_db"] >= fp["psnr_db"] - 0.1]
+        best = max(ok, key=lambda c: c["patches_per_s"]) if ok else None
+        pairs.append({"full": fp, "cross": best,
+                      "speedup": None if best is None else best["patches_per_s"] / fp["patches_per_s"]})
+    matched = [p for p in pairs if p["cross"] is not None]
+    head = max(matched, key=lambda p: p["full"]["psnr_db"]) if matched else None
+    best_full = max(full_pts, key=lambda p: p["psnr_db"]) if full_pts else None
+    best_cross = max(cross_pts, key=lambda p: p["psnr_db"]) if cross_pts else None
+    equal = {"child_detail": w.meta.get("child_detail"), "pairs": pairs,
+             "best_matched_full_k": None if head is None else head["full"]["k"],
+             "speedup_at_best_matched": None if head is None else head["speedup"],
+             "best_psnr_db_full": None if best_full is None else best_full["psnr_db"],
+             "best_psnr_db_cross": None if best_cross is None else best_cross["psnr_db"],
+             "full_sweep": full_pts, "cross_sweep": cross_pts}
+    for p in pairs:
+        print(f"[bench] detail {w.meta.get('child_detail')}: full K={p['full']['k']} psnr "
+              f"{p['full']['psnr_db']:.2f} dB {p['full']['patches_per_s']:.3e}/s -> cross {p['cross']} "
+              f"speedup {p['speedup']}", file=sys.stderr, flush=True)
+    return equal
+
+
+def workloads_phase(cspd, names=("c1", "c3", "c4"), steps: int = 10, warmup: int = 2):
+    """The other configurations at their full sizes, same timing as the
+    headline (inputs resident, one cross-scale call per step, per-kernel
+    durations from the dispatches' own timestamps)."""
+    import torch
+    import synth
+    res = {}
+    for name in names:
+        w = synth.make(name)
+        B = w.batch
+        ks = list(w.k_scales)
+        plan = cspd.plan_from_workload(w)
+        tdt = torch.float64 if w.dtype == "f64" else torch.float32
+        ndt = np.float64 if w.dtype == "f64" else np.float32
+        dev = torch.device("cuda", 0)
+        y = torch.from_numpy(np.ascontiguousarray(w.y.astype(ndt))).to(dev)
+        mask = None if w.mask is None else torch.from_numpy(w.mask).to(dev)
+        kf = None if w.k_fine is None else torch.from_numpy(w.k_fine.astype(np.int32)).to(dev)
+        sup = torch.empty((B, plan.k_max), dtype=torch.int32, device=dev)
+        coef = torch.empty((B, plan.k_max), dtype=tdt, device=dev)
+        ku = torch.empty((B,), dtype=torch.int32, device=dev)
+        xh = torch.empty((B, w.n), dtype=tdt, device=dev)
+        stream = torch.cuda.current_stream()
+
+        def step():
+            cspd.cspd_omp_cross_scale(plan, y, mask, ks[:-1], kf, ks[-1], support=sup, coef=coef,
+                                      k_used=ku, xhat=xh, stream=stream)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        cspd.cspd_profile_reset()
+        cspd.cspd_profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        cspd.cspd_profile_enable(False)
+        prof = cspd.cspd_profile_read()
+        flops = kernel_flops(w, ks)
+        label, (launches, tot_ms) = max(prof.items(), key=lambda kv: kv[1][1])
+        role = label.split(":")[-1]
+        avg_ms = tot_ms / max(launches, 1)
+        per_patch = flops.get(role)
+        achieved = per_patch * B / (avg_ms * 1e-3) / 1e12 if per_patch else None
+        peak = PEAK_FP32_VECTOR_TFLOPS if w.dtype == "f32" else PEAK_FP64_VECTOR_TFLOPS
+        res[name] = {
+            "workload": f"{name}: {B} patches, dims {w.dims}, atoms {w.atoms}, K {ks}"
+                        + (" (finest K per patch)" if w.k_fine is not None else "")
+                        + f", phi {w.phi_kind}, {w.dtype}",
+            "patches_per_s": B / t, "ms_per_call": t * 1e3, "dtype": w.dtype,
+            "roofline": {"bound": bound_of(label), "achieved": achieved, "peak": peak,
+                         "unit": "TFLOP/s", "frac": None if achieved is None else achieved / peak,
+                         "traffic": None, "kernel": label, "kernel_ms": avg_ms, "flops_per_patch": per_patch},
+            "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in prof.items()},
+        }
+        print(f"[bench] {name}: {B / t / 1e6:.1f} M patches/s, {t * 1e3:.3f} ms/call, dominant {label} "
+              f"{avg_ms:.3f} ms", file=sys.stderr, flush=True)
+        del y, mask, kf, sup, coef, ku, xh, plan
+        torch.cuda.synchronize()
+    return res
 
 
 COPY_PROBE_FLOATS = 64 << 20   # 256 MiB read and written by the calibration pass
@@ -601,6 +756,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-pipeline", action="store_true")
     ap.add_argument("--no-learning", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the other configurations (FP64 denoising, 3-scale, video)")
     ap.add_argument("--serve-jobs", type=int, default=2000, help="Poisson arrivals per offered load")
     ap.add_argument("--serve-slots", type=int, default=4, help="server launches in flight")
     ap.add_argument("--serve-ring", type=int, default=8, help="client output sets (jobs outstanding)")
@@ -692,7 +849,7 @@ def main():
     traffic = load_traffic(args.workload, role, 1)
     peak = PEAK_FP32_VECTOR_TFLOPS if w.dtype == "f32" else PEAK_FP64_VECTOR_TFLOPS
     roofline = {
-        "bound": "mfma" if "mfma" in label else "alu",
+        "bound": bound_of(label),
         "achieved": achieved,
         "peak": peak,
         "unit": "TFLOP/s",
@@ -726,51 +883,14 @@ def main():
     # full OMP at several K, cross-scale at several (K_low, K_fine); for every
     # full operating point the cheapest cross-scale point within 0.1 dB.
     equal = None
+    equal_d1 = None
     if full is not None and not args.no_sweep and w.n_scales == 2:
-        q = w.atoms[-1] // w.atoms[-2]
-        full_pts = []
-        for kf_ in (2, 3, 4, 5, 6, 8):
-            if kf_ > plan.k_max:
-                continue
-
-            def step_f(k=kf_):
-                cspd.cspd_omp_full(plan, y, mask, None, k, support=sup, coef=coef, k_used=ku, xhat=xh,
-                                   stream=stream)
-            t_f, _ = timed(step_f, 3, 1)
-            full_pts.append({"k": kf_, "psnr_db": psnr_db(w.x, xh.double().cpu().numpy()),
-                             "patches_per_s": B / t_f})
-        cross_pts = []
-        for k_low in (2, 3, 4, 6, 8):
-            for k_fine in (3, 4, 5, 6, 8, 10, 12):
-                if k_fine > min(q * k_low, plan.k_max) or q * k_low > 128:
-                    continue
-                kk = [k_low, k_fine]
-
-                def step_k(kk=kk):
-                    cspd.cspd_omp_cross_scale(plan, y, mask, kk[:-1], None, kk[-1], support=sup, coef=coef,
-                                              k_used=ku, xhat=xh, stream=stream)
-                try:
-                    t_k, _ = timed(step_k, 5, 1)
-                except cspd.CspdError:
-                    continue
-                cross_pts.append({"k_low": k_low, "k_fine": k_fine,
-                                  "psnr_db": psnr_db(w.x, xh.double().cpu().numpy()),
-                                  "patches_per_s": B / t_k})
-        pairs = []
-        for fp in full_pts:
-            ok = [c for c in cross_pts if c["psnr_db"] >= fp["psnr_db"] - 0.1]
-            best = max(ok, key=lambda c: c["patches_per_s"]) if ok else None
-            pairs.append({"full": fp, "cross": best,
-                          "speedup": None if best is None else best["patches_per_s"] / fp["patches_per_s"]})
-        matched = [p for p in pairs if p["cross"] is not None]
-        head = max(matched, key=lambda p: p["full"]["psnr_db"]) if matched else None
-        equal = {"pairs": pairs, "best_matched_full_k": None if head is None else head["full"]["k"],
-                 "speedup_at_best_matched": None if head is None else head["speedup"],
-                 "full_sweep": full_pts, "cross_sweep": cross_pts}
-        for p in pairs:
-            print(f"[bench] full K={p['full']['k']} psnr {p['full']['psnr_db']:.2f} dB "
-                  f"{p['full']['patches_per_s']:.3e}/s -> cross {p['cross']} speedup {p['speedup']}",
-                  file=sys.stderr, flush=True)
+        equal = equal_psnr_phase(cspd, w, plan, timed)
+        if args.workload == "c2":
+            # the same sweep on the survey's model dictionaries (child detail 1)
+            import synth as _s
+            w1 = _s.make("c2", detail=1.0)
+            equal_d1 = equal_psnr_phase(cspd, w1, cspd.plan_from_workload(w1), timed)
 
     # ---- serving: Poisson arrivals of jobs of three shapes
     serving = None
@@ -809,7 +929,12 @@ def main():
         precision = precision_phase(cspd)
         print(f"[bench] precision: {json.dumps(precision)}", file=sys.stderr, flush=True)
 
+    workloads = None
+    if not args.no_workloads and args.workload == "c2":
+        workloads = workloads_phase(cspd)
+
     cpu = None
+    cpu1 = None
     if not args.no_cpu_baseline:
         import synth as _s
         import oracle
@@ -832,6 +957,20 @@ def main():
                          f"in {t1 - t0:.2f} s wall"}
         print(f"[bench] oracle: {n} patches x {reps} in {t1 - t0:.2f} s on {threads} threads",
               file=sys.stderr, flush=True)
+        # the same oracle on one thread, over a smaller prefix (about 5 s)
+        n1 = min(4096, n)
+        sub1 = _s.subset(w, np.arange(n1))
+        reps1 = 0
+        t0 = time.perf_counter()
+        while True:
+            oracle.omp_cross_scale(sub1, n_threads=1)
+            reps1 += 1
+            if time.perf_counter() - t0 >= 5.0 or reps1 >= 200:
+                break
+        t1 = time.perf_counter()
+        cpu1 = {"value": n1 * reps1 / (t1 - t0), "unit": "patches/s", "cores": 1, "kind": "oracle",
+                "sample": f"first {n1} patches of the workload, zero-tree OMP, FP64, solved {reps1} times "
+                          f"in {t1 - t0:.2f} s wall on one thread"}
 
     line = {
         "metric": "patches/sec cross-scale vs full OMP at equal PSNR; p50/p99 job latency",
@@ -851,9 +990,12 @@ def main():
                    "patches": B, "parallelism": "none (1 GPU)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_1thread": cpu1,
+        "workloads": workloads,
         "full_omp": full,
         "quality": quality,
         "equal_psnr": equal,
+        "equal_psnr_child_detail_1": equal_d1,
         "serving": serving,
         "precision": precision,
         "graphs": graphs,

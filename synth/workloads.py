@@ -194,7 +194,7 @@ def synthesize(rng_coef, rng_noise, dict_f, support, phi_kind, phi, mask, sigma)
 
 
 def make(name: str, batch: Optional[int] = None, seed: Optional[int] = None,
-         dict_kind: str = "model") -> Workload:
+         dict_kind: str = "model", detail: float = CHILD_DETAIL) -> Workload:
     """Build one of the named workloads.
 
     c1: 2-scale FP64 denoising, 1024 patches, 8x8 -> 4x4, Dc 16x64, Df 64x256, Q 4.
@@ -206,6 +206,9 @@ def make(name: str, batch: Optional[int] = None, seed: Optional[int] = None,
         coded-exposure Phi 64x512, per-patch K ~ U{4..16}, K_low 4.
     c5a/b/c: serving shapes (64-d / 512-d video / 400-d light field) with
         Gaussian Phi at 25 % measurement rate, K_fine ~ U{6..16}, K_low 4.
+
+    ``detail`` scales the block-mean-free detail that model-consistent
+    children add to their upsampled parent (CHILD_DETAIL by default).
     """
     name = name.lower()
     seed = SEEDS[name] if seed is None else seed
@@ -260,7 +263,7 @@ def make(name: str, batch: Optional[int] = None, seed: Optional[int] = None,
     dicts = [gaussian_dict(r_dict, atoms[0], dims[0])]
     for s in range(1, s_count):
         if dict_kind == "model":
-            dicts.append(child_dict(r_dict, dicts[s - 1], up_maps[s - 1], q[s - 1]))
+            dicts.append(child_dict(r_dict, dicts[s - 1], up_maps[s - 1], q[s - 1], detail=detail))
         elif dict_kind == "indep":
             dicts.append(gaussian_dict(r_dict, atoms[s], dims[s]))
         else:
@@ -285,7 +288,7 @@ def make(name: str, batch: Optional[int] = None, seed: Optional[int] = None,
     return Workload(name=name, seed=seed, dims=dims, atoms=atoms, dicts=dicts, up_maps=up_maps,
                     phi_kind=phi_kind, m=m, phi=phi, x=x, y=y, mask=mask, k_scales=ks,
                     k_fine=k_fine, sigma=sigma, true_support=support, dtype=dtype,
-                    meta={"dict_kind": dict_kind})
+                    meta={"dict_kind": dict_kind, "child_detail": detail})
 
 
 def custom(dims, atoms, batch, seed, phi_kind="identity", m=None, k_scales=None, sigma=0.0,
