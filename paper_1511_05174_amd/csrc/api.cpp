@@ -102,8 +102,11 @@ cspd_status validate_desc(const cspd_plan_desc *d)
     if (d->k_max > kMaxK) return set_error(CSPD_E_UNSUPPORTED, "k_max %d above the supported %d", d->k_max, kMaxK);
     for (int s = 0; s < S; ++s) {
         const int l = d->phi_kind == CSPD_PHI_DENSE ? d->m : d->dim[s];
-        if (l > 256) return set_error(CSPD_E_UNSUPPORTED, "scale %d: vector length %d above 256", s, l);
+        const int cap = d->dtype == CSPD_F32 ? kMaxLongLen : kMaxShortLen;
+        if (l > cap) return set_error(CSPD_E_UNSUPPORTED, "scale %d: vector length %d above %d", s, l, cap);
     }
+    if (d->dim[S - 1] > kMaxLongLen)
+        return set_error(CSPD_E_UNSUPPORTED, "signal dimension %d above %d", d->dim[S - 1], kMaxLongLen);
     if (d->device < 0) return set_error(CSPD_E_INVALID, "device %d", d->device);
     return CSPD_OK;
 }
@@ -171,6 +174,7 @@ struct CrossCall {
     int ksum = 0;
     int cand[CSPD_MAX_SCALES] = {};
     char gram[CSPD_MAX_SCALES] = {};
+    char lng[CSPD_MAX_SCALES] = {};   // the scale runs on the long-vector kernel
 };
 
 cspd_status prepare_cross(const cspd_plan_s *p, int64_t B, const void *y, const uint8_t *mask,
@@ -194,7 +198,15 @@ cspd_status prepare_cross(const cspd_plan_s *p, int64_t B, const void *y, const 
     for (int s = 0; s < p->s; ++s) {
         const int kprev = s == 0 ? 0 : k_scale[s - 1];
         c.cand[s] = max_candidates(p, s, s == 0, kprev);
-        if (!scale_vec_fits(p->sc[s].lp, c.cand[s], p->dtype == CSPD_F64)) {
+        const bool short_ok = scale_vec_fits(p->sc[s].lp, c.cand[s], p->dtype == CSPD_F64) ||
+                              (s == 0 && p->sc[s].gram);
+        if (p->sc[s].lp > kMaxShortLen || !short_ok) {
+            ScaleArgs la = base_args(p, s, B, y, mask);
+            if (p->dtype != CSPD_F32 || !long_fits(la, c.cand[s]))
+                return set_error(CSPD_E_UNSUPPORTED, "scale %d: no long-vector kernel for %d candidates of length %d",
+                                 s, c.cand[s], p->sc[s].l);
+            c.lng[s] = 1;
+        } else if (!scale_vec_fits(p->sc[s].lp, c.cand[s], p->dtype == CSPD_F64)) {
             if (s == 0 && p->sc[s].gram) c.gram[s] = 1;
             else return set_error(CSPD_E_UNSUPPORTED, "scale %d: no kernel for %d candidates of length %d",
                                   s, c.cand[s], p->sc[s].l);
@@ -275,6 +287,7 @@ cspd_status launch_cross_scale(const cspd_plan_s *p, int s, const ScaleArgs &a0,
                                hipStream_t st)
 {
     ScaleArgs a = a0;
+    if (c.lng[s]) return launch_long(p->dtype, a, c.cand[s], st);
     if (s == 0 && first_gemm_path(p)) {
         a.hpre = hpre;   // workspace for the GEMM variant
         a.nu2 = p->sc[0].nu2;
@@ -458,11 +471,22 @@ cspd_status cspd_omp_full(cspd_plan_t p, int64_t B, const void *y, const uint8_t
     a.xhat = xhat;
     const int cand = sc.t;
     cspd_status rc;
+    if (sc.lp > kMaxShortLen) {
+        rc = p->dtype == CSPD_F32 && long_fits(a, cand) ? launch_long(p->dtype, a, cand, st) : CSPD_E_UNSUPPORTED;
+        if (rc == CSPD_E_UNSUPPORTED && !has_error())
+            return set_error(rc, "no long-vector full search for T = %d (at most %d), length %d", sc.t, kMaxLongCand,
+                             sc.l);
+        return rc;
+    }
     const bool fits = scale_vec_fits(sc.lp, cand, p->dtype == CSPD_F64);
     // a reduced-precision proxy runs on the full-search kernel
     const bool lowp = p->corr_mode != CSPD_CORR_NATIVE && sc.v_lo != nullptr;
     if ((fits || sc.gram) && !lowp) rc = launch_scale(p->dtype, a, cand, !fits, st);
     else rc = launch_full_mfma(p, B, y, mask, k, k_uniform, support, coef, k_used, xhat, st);
+    if (rc == CSPD_E_UNSUPPORTED && p->dtype == CSPD_F32 && long_fits(a, cand)) {
+        clear_error();
+        rc = launch_long(p->dtype, a, cand, st);
+    }
     if (rc == CSPD_E_UNSUPPORTED && !has_error())
         return set_error(rc, "no full-search kernel for T = %d, length %d", sc.t, sc.l);
     return rc;

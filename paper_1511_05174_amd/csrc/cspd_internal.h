@@ -16,6 +16,11 @@ namespace cspd {
 constexpr int kMaxK = 16;
 // Per-patch Gram tables are precomputed for shared operators up to this size.
 constexpr int kMaxGramAtoms = 1024;
+// Candidate vectors longer than kMaxShortLen coordinates (up to kMaxLongLen)
+// run on the long-vector kernel, which scores up to kMaxLongCand candidates.
+constexpr int kMaxShortLen = 256;
+constexpr int kMaxLongLen = 2048;
+constexpr int kMaxLongCand = 1024;
 // Wavefronts per workgroup of the per-patch kernels (the matrix-core Gram
 // kernels use one; see waves_per_block).
 constexpr int kWavesPerBlock = 4;
@@ -174,6 +179,10 @@ int64_t cross_workspace_per_patch(const cspd_plan_s *p);
 // operator on the matrix cores, and whether a scale qualifies.
 bool proxy_gemm_fits(int dtype, const ScaleArgs &a);
 cspd_status launch_proxy_gemm(int dtype, const ScaleArgs &a, float *h, hipStream_t stream);
+// Long-vector kernel (one workgroup per patch, FP64 least squares): whether
+// it can run a scale with this many candidates, and its launch.
+bool long_fits(const ScaleArgs &a, int max_cand);
+cspd_status launch_long(int dtype, const ScaleArgs &a, int max_cand, hipStream_t stream);
 // Whether the first-scale matrix-core kernel has an instance for this scale.
 bool first_mfma_fits(int dtype, const ScaleArgs &a);
 cspd_status launch_first_mfma(int dtype, const ScaleArgs &a, hipStream_t stream);

@@ -1,0 +1,311 @@
+// Per-patch OMP over long candidate vectors (more than 256 coordinates, up
+// to 2048): the paper's 24x24 RGB image patches, 8x8x32 video patches and
+// 4x4x8x8 light-field patches (Section V), at any scale of the cross-scale
+// model (Algorithm 2) or over every atom (Algorithm 1).
+//
+// One workgroup of 256 threads owns one patch and runs Algorithm 1 in the
+// scale's coordinates, with the same operator folding as the short-vector
+// kernels (identity and mask operators: candidates are D_s columns weighted
+// per patch by the square root of the observed samples in each block; a
+// shared dense operator: the plan's A_s = Phi U D_s):
+//   proxy    every live candidate's |<a_i, r>| / ||a_i|| (FP32 dot products
+//            over the coordinates, one wavefront per candidate at a time);
+//   argmax   largest score, lowest atom index on exact ties;
+//   merge    the new atom's Gram column against the support, its correlation
+//            with y and its squared norm as FP64 sums of products of the
+//            stored values, then the Cholesky row appended in FP64; an atom
+//            whose pivot is at most 1e-10 of its squared norm is dependent
+//            and ends the patch's selection;
+//   project  L L^T alpha = A_Omega^T y by two FP64 triangular solves;
+//   residue  r = y - A_Omega alpha, summed in FP64 and kept in FP32.
+// The least squares are thus FP64 on the stored (rounded) vectors, as in the
+// FP64 oracle; only the proxy is FP32.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdio>
+
+#include "cspd_internal.h"
+
+namespace cspd {
+namespace long_impl {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int KX = kMaxK;
+
+template <typename T>
+struct Shared {
+    T yhat[kMaxLongLen];     // measurement in the scale's coordinates
+    T sqw[kMaxLongLen];      // per-coordinate weight (square root of observed samples)
+    T rw[kMaxLongLen];       // weighted residual sqw * r
+    T tmp[kMaxLongLen];      // staging of the fine samples' indicators (block folds)
+    int cand[kMaxLongCand];  // atom of each candidate slot; -1 once chosen or unusable
+    T inv_nu[kMaxLongCand];  // reciprocal weighted norm of each candidate
+    double L[KX * KX];       // Cholesky factor of the support's Gram matrix (row-major)
+    double z[KX];
+    double alpha[KX];
+    int sup[KX];
+    double red[kWaves][KX + 2];
+    T wbest[kWaves];
+    int wslot[kWaves];
+    int count;
+    int pick;                // candidate slot picked this iteration, -1 to stop
+};
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
+{
+    __shared__ Shared<T> sh;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int64_t b = blockIdx.x;
+    if (b >= a.b) return;
+    const T *y = (const T *)a.y + b * (int64_t)a.y_stride;
+    const T *v = (const T *)a.v;
+    const int lp = a.lp, l = a.l;
+    const bool fold = a.fold == kFold;
+    const uint8_t *mrow = (fold && a.mask) ? a.mask + b * (int64_t)a.n : nullptr;
+
+    // ---- measurement in the scale's coordinates and its weights ------------
+    if (tid == 0) sh.count = 0;
+    if (!fold) {
+        for (int t = tid; t < lp; t += kThreads) {
+            sh.yhat[t] = t < l ? y[t] : T(0);
+            sh.sqw[t] = t < l ? T(1) : T(0);
+        }
+    } else if (a.blk_ident) {
+        for (int t = tid; t < lp; t += kThreads) {
+            const bool obs = t < l && (mrow ? mrow[t] != 0 : true);
+            sh.yhat[t] = obs ? y[t] : T(0);
+            sh.sqw[t] = obs ? T(1) : T(0);
+        }
+    } else {
+        // blocks of several fine samples: stage the observed samples, then
+        // each coordinate folds its block (sum / sqrt(count), weight sqrt(count))
+        for (int j = tid; j < a.n; j += kThreads) {
+            const bool obs = mrow ? mrow[j] != 0 : true;
+            sh.rw[j] = obs ? y[j] : T(0);
+            sh.tmp[j] = obs ? T(1) : T(0);
+        }
+        __syncthreads();
+        for (int t = tid; t < lp; t += kThreads) {
+            T cnt = 0, acc = 0;
+            if (t < l) {
+                for (int jj = a.blk_off[t]; jj < a.blk_off[t + 1]; ++jj) {
+                    const int j = a.blk_idx[jj];
+                    cnt += sh.tmp[j];
+                    acc += sh.rw[j];
+                }
+            }
+            const T sq = sqrt(cnt);
+            sh.yhat[t] = cnt > T(0) ? acc / sq : T(0);
+            sh.sqw[t] = sq;
+        }
+    }
+    __syncthreads();
+    {
+        int c = 0;
+        for (int t = tid; t < lp; t += kThreads) c += sh.sqw[t] > T(0);
+        atomicAdd(&sh.count, c);
+    }
+    // ---- candidates ------------------------------------------------------
+    int nc = 0;
+    if (a.first) {
+        nc = a.t;
+        for (int i = tid; i < nc; i += kThreads) sh.cand[i] = i;
+    } else {
+        const int kp = a.prev_kused[b];
+        nc = kp * a.q;
+        for (int i = tid; i < nc; i += kThreads) {
+            const int pj = i / a.q;
+            const int parent = a.prev_sup[b * (int64_t)a.prev_stride + pj];
+            sh.cand[i] = parent * a.q + (i - pj * a.q);
+        }
+    }
+    for (int t = tid; t < lp; t += kThreads) sh.rw[t] = sh.sqw[t] * sh.yhat[t];
+    __syncthreads();
+    const int rank_bound = fold ? sh.count : a.m_dense;
+    const int kreq = a.kvec ? a.kvec[b] : a.kuni;
+    int K = kreq < nc ? kreq : nc;
+    K = K < a.sup_count ? K : a.sup_count;
+    K = K < KX ? K : KX;
+    K = K > 0 ? K : 0;
+
+    // ---- weighted norms of the candidates (one wavefront per candidate) ---
+    for (int i = wv; i < nc; i += kWaves) {
+        const T *vi = v + (int64_t)sh.cand[i] * lp;
+        T s = 0;
+        for (int t = lane; t < lp; t += 64) {
+            const T x = vi[t] * sh.sqw[t];
+            s += x * x;
+        }
+        s = wave_sum(s);
+        if (lane == 0) sh.inv_nu[i] = s > T(0) ? T(1) / sqrt(s) : T(-1);
+    }
+    __syncthreads();
+    for (int i = tid; i < nc; i += kThreads)
+        if (!(sh.inv_nu[i] > T(0))) sh.cand[i] = -1;   // a zero effective column is never picked
+    __syncthreads();
+
+    // ---- iterations (Algorithm 1) ------------------------------------------
+    int n = 0;
+    for (int it = 0; it < K; ++it) {
+        // proxy and argmax: each wavefront keeps its best (score, slot)
+        T best = T(-1);
+        int bslot = -1;
+        for (int i = wv; i < nc; i += kWaves) {
+            const int at = sh.cand[i];
+            if (at < 0) continue;   // wavefront-uniform
+            const T *vi = v + (int64_t)at * lp;
+            T s = 0;
+            for (int t = lane; t < lp; t += 64) s += vi[t] * sh.rw[t];
+            s = wave_sum(s);
+            const T sc = fabs(s) * sh.inv_nu[i];
+            const bool up = bslot < 0 || sc > best || (sc == best && at < sh.cand[bslot]);
+            best = up ? sc : best;
+            bslot = up ? i : bslot;
+        }
+        if (lane == 0) {
+            sh.wbest[wv] = best;
+            sh.wslot[wv] = bslot;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int ps = -1;
+            T pb = T(-1);
+            for (int w = 0; w < kWaves; ++w) {
+                const int s = sh.wslot[w];
+                if (s < 0) continue;
+                const T sc = sh.wbest[w];
+                if (ps < 0 || sc > pb || (sc == pb && sh.cand[s] < sh.cand[ps])) {
+                    pb = sc;
+                    ps = s;
+                }
+            }
+            sh.pick = n < rank_bound ? ps : -1;   // candidates exhausted, or the support spans the space
+        }
+        __syncthreads();
+        const int ps = sh.pick;
+        if (ps < 0) break;
+        const int k = sh.cand[ps];
+        // Gram column against the support, correlation with y, squared norm:
+        // FP64 sums of the stored values' products
+        double part[KX + 2];
+#pragma unroll
+        for (int j = 0; j < KX + 2; ++j) part[j] = 0.0;
+        const T *vk = v + (int64_t)k * lp;
+        for (int t = tid; t < l; t += kThreads) {
+            const double w = (double)sh.sqw[t];
+            const double xk = (double)vk[t] * w;
+#pragma unroll
+            for (int j = 0; j < KX; ++j)
+                if (j < n) part[j] += xk * ((double)v[(int64_t)sh.sup[j] * lp + t] * w);
+            part[KX] += xk * (double)sh.yhat[t];
+            part[KX + 1] += xk * xk;
+        }
+#pragma unroll
+        for (int j = 0; j < KX + 2; ++j) {
+            if (j < n || j >= KX) {
+                const double s = wave_sum(part[j]);
+                if (lane == 0) sh.red[wv][j] = s;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double g[KX];
+            for (int j = 0; j < n; ++j) g[j] = sh.red[0][j] + sh.red[1][j] + sh.red[2][j] + sh.red[3][j];
+            const double hk = sh.red[0][KX] + sh.red[1][KX] + sh.red[2][KX] + sh.red[3][KX];
+            const double ek = sh.red[0][KX + 1] + sh.red[1][KX + 1] + sh.red[2][KX + 1] + sh.red[3][KX + 1];
+            // w = L^{-1} g; pivot ek - ||w||^2
+            double d = ek;
+            for (int i = 0; i < n; ++i) {
+                double s = g[i];
+                for (int j = 0; j < i; ++j) s -= sh.L[i * KX + j] * sh.L[n * KX + j];
+                const double wi = s / sh.L[i * KX + i];
+                sh.L[n * KX + i] = wi;
+                d -= wi * wi;
+            }
+            if (!(d > 1e-10 * ek)) {
+                sh.pick = -1;                 // dependent on the support
+            } else {
+                const double lnn = sqrt(d);
+                sh.L[n * KX + n] = lnn;
+                double s = hk;
+                for (int j = 0; j < n; ++j) s -= sh.L[n * KX + j] * sh.z[j];
+                sh.z[n] = s / lnn;
+                // L^T alpha = z
+                for (int i = n; i >= 0; --i) {
+                    double u = sh.z[i];
+                    for (int j = i + 1; j <= n; ++j) u -= sh.L[j * KX + i] * sh.alpha[j];
+                    sh.alpha[i] = u / sh.L[i * KX + i];
+                }
+                sh.sup[n] = k;
+                sh.cand[ps] = -1;
+            }
+        }
+        __syncthreads();
+        if (sh.pick < 0) break;
+        ++n;
+        // residue (weighted): sqw * (y - A_Omega alpha), summed in FP64
+        for (int t = tid; t < lp; t += kThreads) {
+            const double w = (double)sh.sqw[t];
+            double s = 0.0;
+            for (int j = 0; j < n; ++j) s += sh.alpha[j] * (double)v[(int64_t)sh.sup[j] * lp + t];
+            sh.rw[t] = (T)(w * ((double)sh.yhat[t] - w * s));
+        }
+        __syncthreads();
+    }
+
+    // ---- outputs -----------------------------------------------------------
+    if (tid == 0) a.kused_out[b] = n;
+    int *sup_out = a.sup_out + b * (int64_t)a.sup_stride;
+    for (int i = tid; i < a.sup_count; i += kThreads) sup_out[i] = i < n ? sh.sup[i] : -1;
+    if (!a.last) return;
+    T *coef = (T *)a.coef_out + b * (int64_t)a.sup_stride;
+    for (int i = tid; i < a.sup_count; i += kThreads) coef[i] = i < n ? (T)sh.alpha[i] : T(0);
+    if (a.xhat) {
+        const T *dh = (const T *)a.d_high;
+        T *xh = (T *)a.xhat + b * (int64_t)a.n;
+        for (int j = tid; j < a.n; j += kThreads) {
+            double s = 0.0;
+            for (int i = 0; i < n; ++i) s += sh.alpha[i] * (double)dh[(int64_t)sh.sup[i] * a.n + j];
+            xh[j] = (T)s;
+        }
+    }
+}
+
+}  // namespace long_impl
+
+bool long_fits(const ScaleArgs &a, int max_cand)
+{
+    return a.lp > 0 && a.lp <= kMaxLongLen && a.l <= kMaxLongLen && a.n <= kMaxLongLen && max_cand <= kMaxLongCand;
+}
+
+cspd_status launch_long(int dtype, const ScaleArgs &a, int max_cand, hipStream_t st)
+{
+    using namespace long_impl;
+    if (a.b <= 0) return CSPD_OK;
+    if (!long_fits(a, max_cand)) return CSPD_E_UNSUPPORTED;
+    char label[96];
+    if (a.first && a.last)
+        snprintf(label, sizeof(label), "omp_long<f32,lp%d>:full", a.lp);
+    else
+        snprintf(label, sizeof(label), "omp_long<f32,lp%d>:s%d", a.lp, a.scale);
+    if (dtype != CSPD_F32) return CSPD_E_UNSUPPORTED;
+    const dim3 grid((unsigned)a.b), block(kThreads);
+    launch_timed(label, k_omp_long<float>, grid, block, 0, st, a);
+    CSPD_HIP_CHECK(hipGetLastError());
+    return CSPD_OK;
+}
+
+}  // namespace cspd

@@ -285,7 +285,7 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
         sc.gsplit = std::ldexp(1.0f, ex);
         const double *wsrc = dense ? (const double *)a64.p : (const double *)w64.p;
         const bool norms = !mask;
-        const bool gram = !mask && T <= kMaxGramAtoms && (s == 0 || s == S - 1);
+        const bool gram = !mask && T <= kMaxGramAtoms && (s == 0 || s == S - 1) && sc.lp <= kMaxShortLen;
         const int lo = (s == S - 1 && p->dtype == CSPD_F32) ? p->corr_mode : 0;
         cspd_status rc = p->dtype == CSPD_F64
             ? finish_scale<double>(sc, (const double *)a64.p, wsrc, norms, gram, 0, st, p->bytes)
