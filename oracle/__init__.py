@@ -38,6 +38,7 @@ class _Model(C.Structure):
         ("phi_kind", C.c_int32),
         ("m", C.c_int32),
         ("phi", C.c_void_p),
+        ("n_phases", C.c_int32),
     ]
 
 
@@ -60,7 +61,7 @@ def load(path: str = _LIB):
     lib.oracle_omp.restype = C.c_int
     lib.oracle_omp.argtypes = [C.POINTER(_Model), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
-                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
     lib.oracle_max_threads.restype = C.c_int
     _lib_cache[path] = lib
     return lib
@@ -76,7 +77,7 @@ def _ptr(a):
 
 def omp(dims, atoms, dicts, up_maps, phi_kind, m, phi, y, mask, k_scales, k_fine=None,
         full=False, forced=None, kstride=None, with_trace=False, n_threads=0,
-        lib_path: str = _LIB):
+        phase=None, lib_path: str = _LIB):
     """Run the oracle on a batch.
 
     dims/atoms/dicts/up_maps describe the scales (coarse -> fine); dicts[s] is
@@ -105,8 +106,12 @@ def omp(dims, atoms, dicts, up_maps, phi_kind, m, phi, y, mask, k_scales, k_fine
             md.up_map[s] = u.ctypes.data
     md.phi_kind = PHI_KINDS[phi_kind]
     md.m = int(m)
+    md.n_phases = 1
     if phi is not None:
         p = np.ascontiguousarray(phi, dtype=np.float64)
+        if p.ndim == 3:                 # one dense operator per phase
+            md.n_phases = p.shape[0]
+            assert p.shape[1:] == (m, dims[-1])
         keep.append(p)
         md.phi = p.ctypes.data
     y = np.ascontiguousarray(y, dtype=np.float64)
@@ -128,9 +133,13 @@ def omp(dims, atoms, dicts, up_maps, phi_kind, m, phi, y, mask, k_scales, k_fine
     ku = np.zeros((B, S), dtype=np.int32)
     xh = np.zeros((B, dims[-1]), dtype=np.float64)
     tr = np.zeros((B, S, kstride, 4), dtype=np.float64) if with_trace else None
+    ph = None
+    if phase is not None:
+        ph = np.ascontiguousarray(phase, dtype=np.int32)
+        assert ph.shape == (B,)
     rc = lib.oracle_omp(C.byref(md), B, _ptr(y), _ptr(mask), _ptr(ks), _ptr(kf), int(bool(full)),
                         _ptr(fz), kstride, _ptr(sup), _ptr(cf), _ptr(ku), _ptr(xh), _ptr(tr),
-                        int(n_threads))
+                        int(n_threads), _ptr(ph))
     if rc != 0:
         raise ValueError("oracle rejected the shapes")
     out = {"supports": sup, "coefs": cf, "k_used": ku, "xhat": xh,
@@ -141,6 +150,7 @@ def omp(dims, atoms, dicts, up_maps, phi_kind, m, phi, y, mask, k_scales, k_fine
 
 
 def _from_workload(w, **kw):
+    kw.setdefault("phase", getattr(w, "phase", None))
     return dict(dims=w.dims, atoms=w.atoms, dicts=w.dicts, up_maps=w.up_maps,
                 phi_kind=w.phi_kind, m=w.m, phi=w.phi, y=w.y, mask=w.mask,
                 k_scales=w.k_scales, k_fine=w.k_fine, **kw)

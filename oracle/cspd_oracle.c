@@ -59,7 +59,8 @@ typedef struct {
     const int32_t *up_map[OR_MAX_SCALES]; /* s < S-1: length N_{s+1}, values in [0, N_s) */
     int32_t phi_kind;
     int32_t m;                         /* rows of Phi (= N for identity / mask) */
-    const double *phi;                 /* row-major M x N for OR_PHI_DENSE */
+    const double *phi;                 /* row-major M x N for OR_PHI_DENSE, n_phases of them */
+    int32_t n_phases;                  /* dense operators to choose from per patch (0 or 1: one) */
 } oracle_model;
 
 /* ---------------------------------------------------------------------- */
@@ -203,7 +204,7 @@ static void omp_restricted(const double *A, int M, const int *cand, int nc,
 /* Effective dictionary at scale s for one patch: column t is
  * Phi applied to the upsampled atom u_j = D_s[map_s(j), t]. */
 static void effective_dict(const oracle_model *md, int s, const int64_t *map_s,
-                           const uint8_t *mask, double *A)
+                           const uint8_t *mask, const double *phi, double *A)
 {
     const int N = md->dim[md->n_scales - 1];
     const int Ns = md->dim[s];
@@ -216,7 +217,7 @@ static void effective_dict(const oracle_model *md, int s, const int64_t *map_s,
         if (md->phi_kind == OR_PHI_DENSE) {
             for (int i = 0; i < M; ++i) {
                 double acc = 0.0;
-                for (int j = 0; j < N; ++j) acc += md->phi[(size_t)i * N + j] * d[map_s[j]];
+                for (int j = 0; j < N; ++j) acc += phi[(size_t)i * N + j] * d[map_s[j]];
                 a[i] = acc;
             }
         } else {
@@ -248,12 +249,15 @@ static void compose_maps(const oracle_model *md, int64_t **maps)
  *   supports : B x S x kstride out (-1 padded), coefs: B x S x kstride out,
  *   k_used   : B x S out, xhat: B x N out (may be NULL),
  *   trace    : B x S x kstride x 4 out (may be NULL).
+ *   phase    : B (dense operators, n_phases > 1): which operator each
+ *              patch is measured with; NULL means operator 0.
  * Returns 0, or -1 on a shape error.
  */
 int oracle_omp(const oracle_model *md, int64_t B, const double *y, const uint8_t *mask,
                const int32_t *k_scale, const int32_t *k_fine, int32_t full,
                const int32_t *forced, int32_t kstride, int32_t *supports, double *coefs,
-               int32_t *k_used, double *xhat, double *trace, int32_t n_threads)
+               int32_t *k_used, double *xhat, double *trace, int32_t n_threads,
+               const int32_t *phase)
 {
     const int S = md->n_scales;
     if (S < 1 || S > OR_MAX_SCALES) return -1;
@@ -262,6 +266,10 @@ int oracle_omp(const oracle_model *md, int64_t B, const double *y, const uint8_t
     for (int s = 1; s < S; ++s)
         if (md->atoms[s] % md->atoms[s - 1] != 0) return -1;
     if (md->phi_kind != OR_PHI_DENSE && M != N) return -1;
+    const int P = md->n_phases > 1 ? md->n_phases : 1;
+    if (P > 1 && md->phi_kind != OR_PHI_DENSE) return -1;
+    if (phase)
+        for (int64_t b = 0; b < B; ++b) if (phase[b] < 0 || phase[b] >= P) return -1;
     int Tmax = 0, Kmax = 0;
     for (int s = 0; s < S; ++s) if (md->atoms[s] > Tmax) Tmax = md->atoms[s];
     for (int s = 0; s < S; ++s) if (k_scale[s] > Kmax) Kmax = k_scale[s];
@@ -273,12 +281,16 @@ int oracle_omp(const oracle_model *md, int64_t B, const double *y, const uint8_t
     for (int s = 0; s < S; ++s) maps[s] = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
     compose_maps(md, maps);
 
-    /* Shared effective dictionaries when they do not depend on the patch. */
+    /* Shared effective dictionaries when they do not depend on the patch
+     * (one per operator when there are several). */
     double *shared[OR_MAX_SCALES] = {0};
     if (md->phi_kind != OR_PHI_MASK) {
         for (int s = 0; s < S; ++s) {
-            shared[s] = (double *)malloc(sizeof(double) * (size_t)M * md->atoms[s]);
-            effective_dict(md, s, maps[s], NULL, shared[s]);
+            const size_t one = (size_t)M * md->atoms[s];
+            shared[s] = (double *)malloc(sizeof(double) * one * P);
+            for (int p = 0; p < P; ++p)
+                effective_dict(md, s, maps[s], NULL, md->phi ? md->phi + (size_t)p * M * N : NULL,
+                               shared[s] + one * p);
         }
     }
 
@@ -313,10 +325,10 @@ int oracle_omp(const oracle_model *md, int64_t B, const double *y, const uint8_t
             for (int s = s0; s < S; ++s) {
                 const double *A;
                 if (md->phi_kind == OR_PHI_MASK) {
-                    effective_dict(md, s, maps[s], mb, Aown);
+                    effective_dict(md, s, maps[s], mb, NULL, Aown);
                     A = Aown;
                 } else {
-                    A = shared[s];
+                    A = shared[s] + (size_t)M * md->atoms[s] * (size_t)(phase ? phase[b] : 0);
                 }
                 int nc = 0;
                 if (s == s0) {

@@ -536,7 +536,46 @@ def pin_three_scales(lib, trials=20, seed=22):
         np.testing.assert_allclose(out["xhat"][0], xh, rtol=1e-10, atol=1e-12)
 
 
-ALL_PINS = [pin_golden, pin_bruteforce_greedy, pin_bruteforce_cross_scale, pin_exact_recovery,
+# --------------------------------------------------------------------------
+# Per-patch operators chosen from a set (location-dependent measurements).
+# --------------------------------------------------------------------------
+def pin_phases(lib, seed=25):
+    """A batch measured with several dense operators, each patch with its
+    own: the phased run equals, patch for patch and bit for bit, a plain run
+    of each phase's patches with that phase's single operator; and operators
+    diag(m_p) give exactly the per-patch mask run with masks m_p."""
+    import synth
+    rng = np.random.default_rng(seed)
+    w = synth.custom([16, 64], [32, 256], batch=90, seed=seed, k_scales=[3, 6], sigma=0.02,
+                     phi_kind="dense", m=40)
+    P = 3
+    phis = np.stack([w.phi] + [rng.standard_normal(w.phi.shape) / np.sqrt(40) for _ in range(P - 1)])
+    ph = rng.integers(0, P, size=w.batch).astype(np.int32)
+    y = w.y
+    out = oracle.omp(w.dims, w.atoms, w.dicts, w.up_maps, "dense", w.m, phis, y, None, w.k_scales,
+                     phase=ph, lib_path=lib)
+    for p in range(P):
+        idx = np.where(ph == p)[0]
+        ref = oracle.omp(w.dims, w.atoms, w.dicts, w.up_maps, "dense", w.m, phis[p], y[idx], None,
+                         w.k_scales, lib_path=lib)
+        for key in ("supports", "coefs", "k_used", "xhat"):
+            assert np.array_equal(out[key][idx], ref[key]), (p, key)
+    # diag(mask) operators = the mask path
+    masks = rng.integers(0, 2, size=(P, 64)).astype(np.uint8)
+    dphi = np.stack([np.diag(m.astype(np.float64)) for m in masks])
+    x = w.x
+    ph2 = rng.integers(0, P, size=w.batch).astype(np.int32)
+    yd = x * masks[ph2]
+    outd = oracle.omp(w.dims, w.atoms, w.dicts, w.up_maps, "dense", 64, dphi, yd, None, w.k_scales,
+                      phase=ph2, lib_path=lib)
+    outm = oracle.omp(w.dims, w.atoms, w.dicts, w.up_maps, "mask", 64, None, yd, masks[ph2], w.k_scales,
+                      lib_path=lib)
+    for key in ("supports", "k_used"):
+        assert np.array_equal(outd[key], outm[key]), key
+    assert np.allclose(outd["coefs"], outm["coefs"], rtol=0, atol=1e-12 * np.abs(outm["coefs"]).max())
+
+
+ALL_PINS = [pin_phases, pin_golden, pin_bruteforce_greedy, pin_bruteforce_cross_scale, pin_exact_recovery,
             pin_exact_recovery_cross_scale, pin_orthonormal, pin_invariants, pin_reductions,
             pin_identity_fold, pin_operators, pin_stopping, pin_forced, pin_golden_forced,
              pin_trace_bruteforce, pin_three_scales]

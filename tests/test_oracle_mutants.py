@@ -20,7 +20,10 @@ MUTANTS = [
     ("residue_sign", "s -= asub[(size_t)j * M + i] * beta[j];", "s += asub[(size_t)j * M + i] * beta[j];"),
     ("interleaved_children", "cand[nc++] = sorted[i] * Q + q;", "cand[nc++] = q * md->atoms[s - 1] + sorted[i];"),
     ("back_substitution_transposed", "s -= w[(size_t)k * m + j] * beta[k];", "s -= w[(size_t)j * m + k] * beta[k];"),
-    ("phi_transposed", "acc += md->phi[(size_t)i * N + j] * d[map_s[j]];", "acc += md->phi[(size_t)j * M + i] * d[map_s[j]];"),
+    ("phi_transposed", "acc += phi[(size_t)i * N + j] * d[map_s[j]];", "acc += phi[(size_t)j * M + i] * d[map_s[j]];"),
+    ("phase_ignored", "(size_t)(phase ? phase[b] : 0);", "(size_t)(phase ? 0 : 0);"),
+    ("phase_shifted", "effective_dict(md, s, maps[s], NULL, md->phi ? md->phi + (size_t)p * M * N : NULL,",
+     "effective_dict(md, s, maps[s], NULL, md->phi ? md->phi + (size_t)((p + 1) % P) * M * N : NULL,"),
     ("reselect_chosen", "if (chosen[c] || nu[c] == 0.0) continue;", "if (nu[c] == 0.0) continue;"),
     ("mask_ignored", "a[j] = (md->phi_kind == OR_PHI_MASK && !mask[j]) ? 0.0 : u;", "a[j] = u;"),
     ("no_dependence_stop", "if (rlast * rlast <= OR_DEP_TOL * nu[pick] * nu[pick]) break;", "if (0) break;"),
