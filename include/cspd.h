@@ -97,6 +97,12 @@ enum { CSPD_CORR_NATIVE = 0, CSPD_CORR_BF16_RESCORE = 1, CSPD_CORR_F16_RESCORE =
  *   k_max      largest sparsity any call will ask for at any scale; the
  *              row stride of the support / coef outputs.
  *   device     HIP device ordinal the plan lives on.
+ *   n_phases   CSPD_PHI_DENSE only: number of dense operators (0 or 1: one).
+ *              With P > 1, phi holds P row-major M x N operators back to back
+ *              and every patch is measured with one of them, chosen per call
+ *              (cspd_omp_cross_scale_phased): location-dependent measurement
+ *              such as a coded-exposure shutter pattern whose tile differs
+ *              with the patch position (Section V, videos).  1 <= P <= 4096.
  */
 typedef struct cspd_plan_desc {
     int32_t n_scales;
@@ -112,6 +118,7 @@ typedef struct cspd_plan_desc {
     int32_t rescore_m;
     int32_t k_max;
     int32_t device;
+    int32_t n_phases;
 } cspd_plan_desc;
 
 typedef struct cspd_plan_s *cspd_plan_t;
@@ -171,6 +178,24 @@ cspd_status cspd_omp_cross_scale(cspd_plan_t plan, int64_t B, const void *y, con
                                  int32_t k_fine_uniform, int32_t *support, void *coef,
                                  int32_t *k_used, void *xhat, int32_t *support_coarse,
                                  void *hip_stream);
+
+/*
+ * Zero-tree OMP (or, for S = 1, full OMP) with a per-patch operator chosen
+ * from the plan's n_phases dense operators (Section III-C's y = Phi x + e
+ * with Phi depending on the patch's position, e.g. a coded-exposure pattern
+ * that is not the same over every patch).
+ *   phase      device int32[B]: the operator of each patch, in [0, n_phases);
+ *              a patch whose phase is outside that range is not solved
+ *              (k_used 0, support -1, coefficients and x-hat 0).
+ *   other arguments as for cspd_omp_cross_scale.
+ * Plans with one operator accept phase = NULL (every patch uses it).
+ * Errors: as for cspd_omp_cross_scale; E_INVALID for a NULL phase on a plan
+ * with several operators.
+ */
+cspd_status cspd_omp_cross_scale_phased(cspd_plan_t plan, int64_t B, const int32_t *phase, const void *y,
+                                        const uint8_t *mask, const int32_t *k_scale, const int32_t *k_fine,
+                                        int32_t k_fine_uniform, int32_t *support, void *coef, int32_t *k_used,
+                                        void *xhat, int32_t *support_coarse, void *hip_stream);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph

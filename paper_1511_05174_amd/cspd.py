@@ -55,6 +55,7 @@ class PlanDesc(C.Structure):
         ("rescore_m", C.c_int32),
         ("k_max", C.c_int32),
         ("device", C.c_int32),
+        ("n_phases", C.c_int32),
     ]
 
 
@@ -106,6 +107,9 @@ SIGNATURES = {
     "cspd_omp_cross_scale": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cspd_omp_cross_scale_phased": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                                C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "cspd_omp_cross_scale_noalloc": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                                  C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                                  C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -206,7 +210,8 @@ def cspd_plan(dims: Sequence[int], atoms: Sequence[int], dicts, up_maps, phi_kin
               k_max: int = 16, device: int = 0) -> Plan:
     """Build a resident plan.  dicts[s] is a (T_s, N_s) float64 array (the
     column-major N_s x T_s dictionary); up_maps[s] an int32 array of length
-    N_{s+1}; phi a (M, N) float64 array for the dense operator."""
+    N_{s+1}; phi a (M, N) float64 array for the dense operator, or (P, M, N)
+    for P operators chosen per patch (cspd_omp_cross_scale_phased)."""
     lib = load()
     S = len(dims)
     d = PlanDesc()
@@ -224,8 +229,11 @@ def cspd_plan(dims: Sequence[int], atoms: Sequence[int], dicts, up_maps, phi_kin
             d.up_map[s] = u.ctypes.data
     d.phi_kind = PHI[phi_kind]
     d.m = int(m)
+    d.n_phases = 1
     if phi is not None:
         p = np.ascontiguousarray(phi, dtype=np.float64)
+        if p.ndim == 3:                  # one operator per phase
+            d.n_phases = p.shape[0]
         keep.append(p)
         d.phi = p.ctypes.data
     d.dtype = DTYPES[dtype]
@@ -321,6 +329,20 @@ def cspd_omp_cross_scale(plan: Plan, y, mask=None, k_scale: Sequence[int] = (), 
     _check(load().cspd_omp_cross_scale(plan.handle, B, _ptr(y), _ptr(mask), ks, _ptr(k_fine),
                                        int(k_fine_uniform), _ptr(support), _ptr(coef), _ptr(k_used),
                                        _ptr(xhat), _ptr(support_coarse), _stream(stream)))
+    return support, coef, k_used, xhat
+
+
+def cspd_omp_cross_scale_phased(plan: Plan, phase, y, mask=None, k_scale: Sequence[int] = (), k_fine=None,
+                                k_fine_uniform: int = 0, support=None, coef=None, k_used=None, xhat=None,
+                                support_coarse=None, want_xhat: bool = True, stream=None):
+    """Zero-tree OMP with each patch's operator chosen by phase (device int32[B])."""
+    _check_inputs(plan, y, mask, k_fine)
+    B = y.shape[0]
+    support, coef, k_used, xhat = _outputs(plan, B, support, coef, k_used, xhat, want_xhat)
+    ks = (C.c_int32 * MAX_SCALES)(*([int(v) for v in k_scale] + [0] * (MAX_SCALES - len(k_scale))))
+    _check(load().cspd_omp_cross_scale_phased(plan.handle, B, _ptr(phase), _ptr(y), _ptr(mask), ks, _ptr(k_fine),
+                                              int(k_fine_uniform), _ptr(support), _ptr(coef), _ptr(k_used),
+                                              _ptr(xhat), _ptr(support_coarse), _stream(stream)))
     return support, coef, k_used, xhat
 
 

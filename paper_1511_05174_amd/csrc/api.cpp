@@ -108,6 +108,9 @@ cspd_status validate_desc(const cspd_plan_desc *d)
     if (d->dim[S - 1] > kMaxLongLen)
         return set_error(CSPD_E_UNSUPPORTED, "signal dimension %d above %d", d->dim[S - 1], kMaxLongLen);
     if (d->device < 0) return set_error(CSPD_E_INVALID, "device %d", d->device);
+    if (d->n_phases < 0 || d->n_phases > 4096) return set_error(CSPD_E_INVALID, "n_phases %d outside 0..4096", d->n_phases);
+    if (d->n_phases > 1 && d->phi_kind != CSPD_PHI_DENSE)
+        return set_error(CSPD_E_INVALID, "several operators (n_phases %d) need CSPD_PHI_DENSE", d->n_phases);
     return CSPD_OK;
 }
 
@@ -153,6 +156,9 @@ ScaleArgs base_args(const cspd_plan_s *p, int s, int64_t B, const void *y, const
     a.blk_ident = sc.blk_ident;
     a.gsplit = sc.gsplit;
     a.vsplit = sc.v_split;
+    a.phase = nullptr;
+    a.n_phases = p->n_phases;
+    a.phase_stride = sc.phase_stride;
     a.q = sc.q;
     a.qmagic = sc.q > 1 ? (unsigned)((((uint64_t)1 << 32) + (uint64_t)sc.q - 1) / (uint64_t)sc.q) : 0u;
     a.d_high = p->d_high;
@@ -171,6 +177,7 @@ int max_candidates(const cspd_plan_s *p, int s, bool first, int k_prev)
 
 // Validated scalars of one cross-scale call.
 struct CrossCall {
+    const int32_t *phase = nullptr;   // per-patch operator (plans with several)
     int ksum = 0;
     int cand[CSPD_MAX_SCALES] = {};
     char gram[CSPD_MAX_SCALES] = {};
@@ -293,7 +300,7 @@ cspd_status launch_cross_scale(const cspd_plan_s *p, int s, const ScaleArgs &a0,
         a.nu2 = p->sc[0].nu2;
     }
     KernelChoice tc;
-    {
+    if (p->n_phases == 1) {
         std::lock_guard<std::mutex> lk(p->mu);
         tc = p->tuned[s][k_bucket(a)];
     }
@@ -311,7 +318,8 @@ cspd_status launch_cross_scale(const cspd_plan_s *p, int s, const ScaleArgs &a0,
         return launch_choice(p->dtype, a, gg, st);
     }
     a.hpre = nullptr;
-    cspd_status rc = s == 0 ? launch_first_mfma(p->dtype, a, st) : CSPD_E_UNSUPPORTED;
+    // the first-scale matrix-core kernel keeps one shared dictionary
+    cspd_status rc = s == 0 && p->n_phases == 1 ? launch_first_mfma(p->dtype, a, st) : CSPD_E_UNSUPPORTED;
     if (rc == CSPD_E_UNSUPPORTED) rc = launch_scale(p->dtype, a, c.cand[s], c.gram[s], st);
     return rc;
 }
@@ -328,8 +336,9 @@ cspd_status run_cross(const cspd_plan_s *p, int64_t B, const void *y, const uint
     float *hpre = (float *)((char *)work + hpre_offset(p, B, c.ksum, support_coarse != nullptr));
     cspd_status rc = CSPD_OK;
     for (int s = 0; s < p->s && rc == CSPD_OK; ++s) {
-        const ScaleArgs a = cross_scale_args(p, s, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef,
+        ScaleArgs a = cross_scale_args(p, s, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef,
                                              k_used, xhat, coarse, kused_c, c.ksum);
+        a.phase = c.phase;
         rc = launch_cross_scale(p, s, a, c, hpre, st);
     }
     return rc;
@@ -353,6 +362,8 @@ cspd_status cross_scale_on(cspd_plan_s *p, int64_t B, const void *y, const uint8
                            hipStream_t st)
 {
     clear_error();
+    if (p->n_phases > 1 && B > 0)
+        return set_error(CSPD_E_INVALID, "plan has %d operators: only cspd_omp_cross_scale_phased runs it", p->n_phases);
     if (p->s == 1) return cspd_omp_full(p, B, y, mask, k_fine, k_fine_uniform, support, coef, k_used, xhat, st);
     CrossCall c;
     cspd_status rc = prepare_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, c);
@@ -413,6 +424,7 @@ cspd_status cspd_plan(const cspd_plan_desc *d, cspd_plan_t *out)
     p->corr_mode = d->corr_mode;
     p->rescore_m = d->rescore_m ? d->rescore_m : 16;
     p->k_max = d->k_max;
+    p->n_phases = d->n_phases > 1 ? d->n_phases : 1;
     p->device = d->device;
     hipStream_t st;
     if (hipStreamCreate(&st) != hipSuccess) {
@@ -440,12 +452,17 @@ void cspd_plan_destroy(cspd_plan_t p)
 
 int64_t cspd_plan_device_bytes(cspd_plan_t p) { return p ? p->bytes : 0; }
 
-cspd_status cspd_omp_full(cspd_plan_t p, int64_t B, const void *y, const uint8_t *mask,
-                          const int32_t *k, int32_t k_uniform, int32_t *support, void *coef,
-                          int32_t *k_used, void *xhat, void *hip_stream)
+}  // extern "C"
+
+namespace cspd {
+namespace {
+
+// Algorithm 1 over the finest dictionary; `phase` picks each patch's operator
+// on plans with several (null: operator 0).
+cspd_status full_on(cspd_plan_s *p, int64_t B, const int32_t *phase, const void *y, const uint8_t *mask,
+                    const int32_t *k, int32_t k_uniform, int32_t *support, void *coef, int32_t *k_used, void *xhat,
+                    hipStream_t st)
 {
-    clear_error();
-    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
     if (B < 0) return set_error(CSPD_E_INVALID, "B = %lld", (long long)B);
     if (!k && (k_uniform < 0 || k_uniform > p->k_max))
         return set_error(CSPD_E_SHAPE, "k_uniform %d outside [0, k_max = %d]", k_uniform, p->k_max);
@@ -454,10 +471,10 @@ cspd_status cspd_omp_full(cspd_plan_t p, int64_t B, const void *y, const uint8_t
     if (p->phi_kind == CSPD_PHI_MASK && !mask) return set_error(CSPD_E_INVALID, "mask plan needs a mask");
     DeviceGuard g(p->device);
     if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
-    hipStream_t st = (hipStream_t)hip_stream;
     const int s = p->s - 1;
     const ScalePlan &sc = p->sc[s];
     ScaleArgs a = base_args(p, s, B, y, mask);
+    a.phase = phase;
     a.first = 1;
     a.scale = s;
     a.kvec = k;
@@ -479,10 +496,12 @@ cspd_status cspd_omp_full(cspd_plan_t p, int64_t B, const void *y, const uint8_t
         return rc;
     }
     const bool fits = scale_vec_fits(sc.lp, cand, p->dtype == CSPD_F64);
-    // a reduced-precision proxy runs on the full-search kernel
+    // a reduced-precision proxy runs on the full-search kernel, which keeps
+    // one shared dictionary (not with several operators)
     const bool lowp = p->corr_mode != CSPD_CORR_NATIVE && sc.v_lo != nullptr;
     if ((fits || sc.gram) && !lowp) rc = launch_scale(p->dtype, a, cand, !fits, st);
-    else rc = launch_full_mfma(p, B, y, mask, k, k_uniform, support, coef, k_used, xhat, st);
+    else if (p->n_phases == 1) rc = launch_full_mfma(p, B, y, mask, k, k_uniform, support, coef, k_used, xhat, st);
+    else rc = CSPD_E_UNSUPPORTED;
     if (rc == CSPD_E_UNSUPPORTED && p->dtype == CSPD_F32 && long_fits(a, cand)) {
         clear_error();
         rc = launch_long(p->dtype, a, cand, st);
@@ -490,6 +509,58 @@ cspd_status cspd_omp_full(cspd_plan_t p, int64_t B, const void *y, const uint8_t
     if (rc == CSPD_E_UNSUPPORTED && !has_error())
         return set_error(rc, "no full-search kernel for T = %d, length %d", sc.t, sc.l);
     return rc;
+}
+
+// Zero-tree OMP on a stream-ordered temporary workspace.
+cspd_status cross_impl(cspd_plan_s *p, int64_t B, const int32_t *phase, const void *y, const uint8_t *mask,
+                       const int32_t *k_scale, const int32_t *k_fine, int32_t k_fine_uniform, int32_t *support,
+                       void *coef, int32_t *k_used, void *xhat, int32_t *support_coarse, hipStream_t st)
+{
+    if (p->s == 1) return full_on(p, B, phase, y, mask, k_fine, k_fine_uniform, support, coef, k_used, xhat, st);
+    CrossCall c;
+    cspd_status rc = prepare_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, c);
+    if (rc != CSPD_OK || B == 0) return rc;
+    c.phase = phase;
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
+    // coarse supports: the caller's buffer, or a stream-ordered temporary
+    int32_t *work = nullptr;
+    const size_t wbytes = cross_workspace_bytes(p, B, c.ksum, support_coarse != nullptr);
+    if (hipMallocAsync((void **)&work, wbytes, st) != hipSuccess)
+        return set_error(CSPD_E_NOMEM, "workspace of %zu bytes", wbytes);
+    rc = run_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat, support_coarse, work,
+                   c, st);
+    (void)hipFreeAsync(work, st);
+    return rc;
+}
+
+}  // namespace
+}  // namespace cspd
+
+extern "C" {
+
+cspd_status cspd_omp_full(cspd_plan_t p, int64_t B, const void *y, const uint8_t *mask,
+                          const int32_t *k, int32_t k_uniform, int32_t *support, void *coef,
+                          int32_t *k_used, void *xhat, void *hip_stream)
+{
+    clear_error();
+    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+    if (p->n_phases > 1 && B > 0)
+        return set_error(CSPD_E_INVALID, "plan has %d operators: use cspd_omp_cross_scale_phased", p->n_phases);
+    return full_on(p, B, nullptr, y, mask, k, k_uniform, support, coef, k_used, xhat, (hipStream_t)hip_stream);
+}
+
+cspd_status cspd_omp_cross_scale_phased(cspd_plan_t p, int64_t B, const int32_t *phase, const void *y,
+                                        const uint8_t *mask, const int32_t *k_scale, const int32_t *k_fine,
+                                        int32_t k_fine_uniform, int32_t *support, void *coef, int32_t *k_used,
+                                        void *xhat, int32_t *support_coarse, void *hip_stream)
+{
+    clear_error();
+    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+    if (p->n_phases > 1 && !phase && B > 0)
+        return set_error(CSPD_E_INVALID, "plan has %d operators and phase is NULL", p->n_phases);
+    return cross_impl(p, B, phase, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat,
+                      support_coarse, (hipStream_t)hip_stream);
 }
 
 cspd_status cspd_omp_cross_scale(cspd_plan_t p, int64_t B, const void *y, const uint8_t *mask,
@@ -500,23 +571,10 @@ cspd_status cspd_omp_cross_scale(cspd_plan_t p, int64_t B, const void *y, const 
 {
     clear_error();
     if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
-    if (p->s == 1)
-        return cspd_omp_full(p, B, y, mask, k_fine, k_fine_uniform, support, coef, k_used, xhat, hip_stream);
-    CrossCall c;
-    cspd_status rc = prepare_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, c);
-    if (rc != CSPD_OK || B == 0) return rc;
-    DeviceGuard g(p->device);
-    if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
-    hipStream_t st = (hipStream_t)hip_stream;
-    // coarse supports: the caller's buffer, or a stream-ordered temporary
-    int32_t *work = nullptr;
-    const size_t wbytes = cross_workspace_bytes(p, B, c.ksum, support_coarse != nullptr);
-    if (hipMallocAsync((void **)&work, wbytes, st) != hipSuccess)
-        return set_error(CSPD_E_NOMEM, "workspace of %zu bytes", wbytes);
-    rc = run_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat,
-                   support_coarse, work, c, st);
-    (void)hipFreeAsync(work, st);
-    return rc;
+    if (p->n_phases > 1 && B > 0)
+        return set_error(CSPD_E_INVALID, "plan has %d operators: use cspd_omp_cross_scale_phased", p->n_phases);
+    return cross_impl(p, B, nullptr, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat,
+                      support_coarse, (hipStream_t)hip_stream);
 }
 
 cspd_status cspd_graph_cross_scale(cspd_plan_t p, int64_t B, const void *y, const uint8_t *mask,
@@ -530,6 +588,8 @@ cspd_status cspd_graph_cross_scale(cspd_plan_t p, int64_t B, const void *y, cons
     *out = nullptr;
     if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
     if (B <= 0) return set_error(CSPD_E_INVALID, "B = %lld (a graph needs patches)", (long long)B);
+    if (p->n_phases > 1)
+        return set_error(CSPD_E_INVALID, "plan has %d operators: only cspd_omp_cross_scale_phased runs it", p->n_phases);
     CrossCall c;
     if (p->s > 1) {
         const cspd_status rc = prepare_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef,
@@ -610,7 +670,7 @@ cspd_status cspd_autotune(cspd_plan_t p, int64_t B, const void *y, const uint8_t
     clear_error();
     if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
     if (reps < 1 || reps > 1000) return set_error(CSPD_E_INVALID, "reps %d outside 1..1000", reps);
-    if (p->s < 2 || p->dtype != CSPD_F32 || B == 0) return CSPD_OK;   // nothing to choose
+    if (p->s < 2 || p->dtype != CSPD_F32 || B == 0 || p->n_phases > 1) return CSPD_OK;   // nothing to choose
     CrossCall c;
     int32_t dummy = 0;
     cspd_status rc = prepare_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, &dummy, &dummy, &dummy, c);

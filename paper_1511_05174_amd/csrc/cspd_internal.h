@@ -70,6 +70,7 @@ struct ScalePlan {
     // weights 0 or 1): per 8 coordinates the four high-part pairs, then the
     // four low-part pairs; t x lp 32-bit words, or null
     void *v_split = nullptr;
+    int64_t phase_stride = 0; // elements of v (and words of v_split) per operator phase
 };
 
 }  // namespace cspd
@@ -97,6 +98,7 @@ struct cspd_plan_s {
     int rescore_m = 8;
     int k_max = 0;
     int device = 0;
+    int n_phases = 1;         // dense operators (per-patch choice when > 1)
     int64_t bytes = 0;
     cspd::ScalePlan sc[CSPD_MAX_SCALES];
     void *d_high = nullptr;   // T_high x N atom-contiguous (plan dtype), for x-hat
@@ -147,6 +149,12 @@ struct ScaleArgs {
     const void *nu2;            // t squared effective norms (with hpre)
     float gsplit;               // power of two: candidates times it fit FP16 (split Gram)
     const void *vsplit;         // t x lp 32-bit words: the candidates split at plan time, or null
+    // per-patch operator (plans with several dense operators): phase[b] picks
+    // the slice phase[b] * phase_stride of v (and vsplit); a phase outside
+    // [0, n_phases) leaves the patch unsolved.  Null: every patch uses slice 0.
+    const int *phase;
+    int n_phases;
+    int64_t phase_stride;
 };
 
 // Kernel variants that can run one scale (FP32): the first-scale MFMA kernel,

@@ -71,7 +71,11 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
     const int64_t b = blockIdx.x;
     if (b >= a.b) return;
     const T *y = (const T *)a.y + b * (int64_t)a.y_stride;
-    const T *v = (const T *)a.v;
+    // operator of the patch (plans with several); out of range: unsolved
+    int ph = a.phase ? a.phase[b] : 0;
+    const bool phok = ph >= 0 && ph < a.n_phases;
+    ph = phok ? ph : 0;
+    const T *v = (const T *)a.v + (int64_t)ph * a.phase_stride;
     const int lp = a.lp, l = a.l;
     const bool fold = a.fold == kFold;
     const uint8_t *mrow = (fold && a.mask) ? a.mask + b * (int64_t)a.n : nullptr;
@@ -137,6 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
     const int rank_bound = fold ? sh.count : a.m_dense;
     const int kreq = a.kvec ? a.kvec[b] : a.kuni;
     int K = kreq < nc ? kreq : nc;
+    K = phok ? K : 0;
     K = K < a.sup_count ? K : a.sup_count;
     K = K < KX ? K : KX;
     K = K > 0 ? K : 0;

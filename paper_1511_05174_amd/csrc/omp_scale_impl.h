@@ -465,6 +465,16 @@ void k_omp_scale(ScaleArgs a)
     const int64_t bb = valid ? b : wave_first;   // a row that exists, for loads
     GroupLds<T, LPA, KM, PSN> &w = lds[wv * PPW + gi];
     const T *y = (const T *)a.y + bb * (int64_t)a.y_stride;
+    // operator of the patch (plans with several): the slice of the candidate
+    // vectors it reads; a phase out of range leaves the patch unsolved
+    int ph = 0;
+    bool phok = true;
+    if (a.phase) {
+        ph = a.phase[bb];
+        phok = ph >= 0 && ph < a.n_phases;
+        ph = phok ? ph : 0;
+    }
+    const T *vph = (const T *)a.v + (int64_t)ph * a.phase_stride;
     const int lp = GRAM ? a.lp : LP;
 
     // Every load of the prologue is issued into registers before any result
@@ -514,7 +524,9 @@ void k_omp_scale(ScaleArgs a)
                 // pre-split rows hold, per 8 coordinates, the four high-part
                 // pairs then the four low-part pairs: LP 32-bit words per atom,
                 // read exactly like the FP32 rows (bits only)
-                msrc[p] = (const T *)(PS ? a.vsplit : a.v) + (int64_t)(livep[p] ? at : 0) * LP + hh * LH;
+                const int php = PPW == 2 ? __builtin_amdgcn_readlane(ph, p * 32) : ph;
+                msrc[p] = (const T *)(PS ? a.vsplit : a.v) + (int64_t)php * a.phase_stride +
+                          (int64_t)(livep[p] ? at : 0) * LP + hh * LH;
                 if constexpr (MCH == LH) {
 #pragma unroll
                     for (int j = 0; j < LH; j += 4) {
@@ -536,7 +548,7 @@ void k_omp_scale(ScaleArgs a)
                 at = pi * a.q + (ci - pj * a.q);
             }
             atom[s] = live[s] ? at : INT_MAX;
-            src[s] = (const T *)a.v + (int64_t)(live[s] ? at : 0) * (GRAM ? lp : LP);
+            src[s] = vph + (int64_t)(live[s] ? at : 0) * (GRAM ? lp : LP);
         }
         if constexpr (!GRAM && !MG) {
 #pragma unroll
@@ -696,7 +708,7 @@ void k_omp_scale(ScaleArgs a)
     }
 
     int K = 0;
-    if (valid) {
+    if (valid && phok) {
         K = kreq < nc ? kreq : nc;
         K = K < KM ? K : KM;
         K = K < a.sup_count ? K : a.sup_count;
@@ -1143,7 +1155,8 @@ void k_omp_scale(ScaleArgs a)
                         double *h64 = g64 + KX * KX;
                         double *pv = h64 + KX;
                         double *gd = pv + KX;
-                        gram64_chol<T>((const T *)a.v, a.lp, a.l, wg.sqw, wg.yhat, wg.sup, n + 1, lane, g64, h64, pv, gd, false);
+                        const T *vg = (const T *)a.v + (int64_t)__builtin_amdgcn_readlane(ph, g * G) * a.phase_stride;
+                        gram64_chol<T>(vg, a.lp, a.l, wg.sqw, wg.yhat, wg.sup, n + 1, lane, g64, h64, pv, gd, false);
                         if (gi == g) {
                             const double piv = pv[n], gkk = gd[n];
                             if (!(piv > 1e-10 * gkk)) act = false;  // dependent in FP64 as well
@@ -1317,7 +1330,7 @@ void k_omp_scale(ScaleArgs a)
                 sid[i] = in ? w.sup[i] : 0;
                 alv[i] = in ? w.alpha[i] : T(0);
             }
-            const T *vv = (const T *)a.v;
+            const T *vv = vph;
             // RU coordinates per lane at a time: all their loads are in
             // flight together (one memory round trip per RU G coordinates)
             for (int t0 = gl; t0 < a.l; t0 += G * RU) {
@@ -1387,7 +1400,8 @@ void k_omp_scale(ScaleArgs a)
                     double *h64 = g64 + KX * KX;
                     double *pv = h64 + KX;
                     double *gd = pv + KX;
-                    gram64_chol<T>((const T *)a.v, a.lp, a.l, wg.sqw, wg.yhat, wg.sup, ng, lane, g64, h64, pv, gd, true);
+                    const T *vg = (const T *)a.v + (int64_t)__builtin_amdgcn_readlane(ph, g * G) * a.phase_stride;
+                    gram64_chol<T>(vg, a.lp, a.l, wg.sqw, wg.yhat, wg.sup, ng, lane, g64, h64, pv, gd, true);
                     if (lane == g * G)
                         for (int i = 0; i < ng; ++i) wg.alpha[i] = (T)h64[i];
                     wave_sync();

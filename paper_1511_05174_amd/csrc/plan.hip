@@ -151,13 +151,15 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 template <typename T>
 cspd_status finish_scale(ScalePlan &sc, const double *a64, const double *w64, bool want_norms,
-                         bool want_gram, int want_lo, hipStream_t st, int64_t &bytes)
+                         bool want_gram, int want_lo, int phases, hipStream_t st, int64_t &bytes)
 {
     const int bs = 256;
-    size_t vbytes = sizeof(T) * (size_t)sc.t * sc.lp;
+    // one block of t rows per operator phase
+    const int rows = sc.t * phases;
+    size_t vbytes = sizeof(T) * (size_t)rows * sc.lp;
     CSPD_HIP_CHECK(hipMalloc(&sc.v, vbytes));
     bytes += vbytes;
-    k_cast_rows<T><<<blocks_for((int64_t)sc.t * sc.lp, bs), bs, 0, st>>>(a64, sc.t, sc.l, (T *)sc.v, sc.lp);
+    k_cast_rows<T><<<blocks_for((int64_t)rows * sc.lp, bs), bs, 0, st>>>(a64, rows, sc.l, (T *)sc.v, sc.lp);
     CSPD_HIP_CHECK(hipGetLastError());
     if (want_lo) {
         size_t lb = sizeof(uint16_t) * (size_t)sc.t * sc.lp;
@@ -197,6 +199,7 @@ struct DevBuf {
 cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t st)
 {
     const int S = p->s, N = p->n, M = p->m;
+    const int P = p->n_phases;
     // composed maps: finest coordinate -> scale-s coordinate
     std::vector<std::vector<int>> maps(S, std::vector<int>(N));
     for (int j = 0; j < N; ++j) maps[S - 1][j] = j;
@@ -205,8 +208,8 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
 
     DevBuf phi_d;
     if (p->phi_kind == CSPD_PHI_DENSE) {
-        CSPD_HIP_CHECK(hipMalloc(&phi_d.p, sizeof(double) * (size_t)M * N));
-        CSPD_HIP_CHECK(hipMemcpyAsync(phi_d.p, d->phi, sizeof(double) * (size_t)M * N,
+        CSPD_HIP_CHECK(hipMalloc(&phi_d.p, sizeof(double) * (size_t)P * M * N));
+        CSPD_HIP_CHECK(hipMemcpyAsync(phi_d.p, d->phi, sizeof(double) * (size_t)P * M * N,
                                       hipMemcpyHostToDevice, st));
     }
     for (int s = 0; s < S; ++s) {
@@ -219,17 +222,19 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
         const bool dense = p->phi_kind == CSPD_PHI_DENSE;
         const bool mask = p->phi_kind == CSPD_PHI_MASK;
         const int l = dense ? M : ns;
-        CSPD_HIP_CHECK(hipMalloc(&a64.p, sizeof(double) * (size_t)l * T));
+        CSPD_HIP_CHECK(hipMalloc(&a64.p, sizeof(double) * (size_t)l * T * P));
         std::vector<int> off(ns + 1, 0), idx(N);
         std::vector<double> sqw(ns, 0.0);
         if (dense) {
             CSPD_HIP_CHECK(hipMalloc(&map_d.p, sizeof(int) * (size_t)N));
             CSPD_HIP_CHECK(hipMemcpyAsync(map_d.p, maps[s].data(), sizeof(int) * (size_t)N,
                                           hipMemcpyHostToDevice, st));
-            k_eff_dense<<<blocks_for((int64_t)T * M, 256), 256, 0, st>>>(
-                (const double *)dict_d.p, ns, T, (const double *)phi_d.p, M, N,
-                (const int *)map_d.p, (double *)a64.p);
-            CSPD_HIP_CHECK(hipGetLastError());
+            for (int ph = 0; ph < P; ++ph) {
+                k_eff_dense<<<blocks_for((int64_t)T * M, 256), 256, 0, st>>>(
+                    (const double *)dict_d.p, ns, T, (const double *)phi_d.p + (size_t)ph * M * N, M, N,
+                    (const int *)map_d.p, (double *)a64.p + (size_t)ph * T * M);
+                CSPD_HIP_CHECK(hipGetLastError());
+            }
         } else {
             // block table of U for this scale (fine samples of each coarse one)
             for (int j = 0; j < N; ++j) off[maps[s][j] + 1]++;
@@ -268,7 +273,7 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
         // becomes at most 2^14, well inside FP16's range
         DevBuf amax_d;
         CSPD_HIP_CHECK(hipMalloc(&amax_d.p, sizeof(double)));
-        k_absmax<<<1, 256, 0, st>>>((const double *)a64.p, (int64_t)l * T, (double *)amax_d.p);
+        k_absmax<<<1, 256, 0, st>>>((const double *)a64.p, (int64_t)l * T * P, (double *)amax_d.p);
         CSPD_HIP_CHECK(hipGetLastError());
         double vmax = 0.0;
         CSPD_HIP_CHECK(hipMemcpyAsync(&vmax, amax_d.p, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -284,22 +289,26 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
         }
         sc.gsplit = std::ldexp(1.0f, ex);
         const double *wsrc = dense ? (const double *)a64.p : (const double *)w64.p;
-        const bool norms = !mask;
-        const bool gram = !mask && T <= kMaxGramAtoms && (s == 0 || s == S - 1) && sc.lp <= kMaxShortLen;
-        const int lo = (s == S - 1 && p->dtype == CSPD_F32) ? p->corr_mode : 0;
+        // with several operators, the tables shared by all patches (norms,
+        // Gram matrix, 16-bit copy) do not exist; the kernels that need them
+        // are not used
+        const bool norms = !mask && P == 1;
+        const bool gram = !mask && P == 1 && T <= kMaxGramAtoms && (s == 0 || s == S - 1) && sc.lp <= kMaxShortLen;
+        const int lo = (s == S - 1 && p->dtype == CSPD_F32 && P == 1) ? p->corr_mode : 0;
         cspd_status rc = p->dtype == CSPD_F64
-            ? finish_scale<double>(sc, (const double *)a64.p, wsrc, norms, gram, 0, st, p->bytes)
-            : finish_scale<float>(sc, (const double *)a64.p, wsrc, norms, gram, lo, st, p->bytes);
+            ? finish_scale<double>(sc, (const double *)a64.p, wsrc, norms, gram, 0, P, st, p->bytes)
+            : finish_scale<float>(sc, (const double *)a64.p, wsrc, norms, gram, lo, P, st, p->bytes);
         if (rc != CSPD_OK) return rc;
+        sc.phase_stride = (int64_t)T * sc.lp;
         // candidates whose per-patch weights are 0 or 1 (a shared dense
         // operator, or coarse samples that are single fine samples) are split
         // for the matrix-core Gram once here instead of in every patch
         if (p->dtype == CSPD_F32 && sc.lp >= 16 && sc.lp <= 128 && (dense || sc.blk_ident)) {
-            const size_t sb = sizeof(uint32_t) * (size_t)sc.t * sc.lp;
+            const size_t sb = sizeof(uint32_t) * (size_t)sc.t * P * sc.lp;
             CSPD_HIP_CHECK(hipMalloc(&sc.v_split, sb));
             p->bytes += (int64_t)sb;
-            k_split_rows<<<blocks_for((int64_t)sc.t * sc.lp, 256), 256, 0, st>>>(
-                (const float *)sc.v, sc.t, sc.lp, sc.gsplit, (uint32_t *)sc.v_split);
+            k_split_rows<<<blocks_for((int64_t)sc.t * P * sc.lp, 256), 256, 0, st>>>(
+                (const float *)sc.v, sc.t * P, sc.lp, sc.gsplit, (uint32_t *)sc.v_split);
             CSPD_HIP_CHECK(hipGetLastError());
         }
         if (s == S - 1) {

@@ -357,6 +357,7 @@ cspd_status cspd_serve_submit(cspd_server_t s, const cspd_job *job, uint64_t *jo
     if (job->B > 0 && (!job->y || !job->support || !job->k_used))
         return set_error(CSPD_E_INVALID, "y / support / k_used is NULL");
     if (job->B > 0 && p->phi_kind == CSPD_PHI_MASK && !job->mask) return set_error(CSPD_E_INVALID, "mask plan needs a mask");
+    if (p->n_phases > 1) return set_error(CSPD_E_INVALID, "plan has %d operators: not served", p->n_phases);
     if (!job->k_fine && (job->k_fine_uniform < 0 || job->k_fine_uniform > p->k_max))
         return set_error(CSPD_E_SHAPE, "k_fine_uniform %d outside [0, %d]", job->k_fine_uniform, p->k_max);
     if (!job->full)

@@ -29,7 +29,8 @@ from typing import List, Optional
 import numpy as np
 
 # One seed per workload, as the workloads' recipe states.
-SEEDS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5a": 51, "c5b": 52, "c5c": 53}
+SEEDS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5a": 51, "c5b": 52, "c5c": 53,
+         "c4loc": 41, "bayer": 61, "lfca": 62}
 
 
 @dataclass
@@ -52,6 +53,7 @@ class Workload:
     true_support: np.ndarray        # (B, Kmax) int32, fine indices, -1 padded
     dtype: str                      # "f64" | "f32"
     meta: dict = field(default_factory=dict)
+    phase: Optional[np.ndarray] = None   # (B,) int32: each patch's operator when phi is (P, M, N)
 
     @property
     def n_scales(self) -> int:
@@ -187,10 +189,62 @@ def synthesize(rng_coef, rng_noise, dict_f, support, phi_kind, phi, mask, sigma)
         y = x + sigma * rng_noise.standard_normal(x.shape)
     elif phi_kind == "mask":
         y = (x + sigma * rng_noise.standard_normal(x.shape)) * mask
+    elif phi.ndim == 3:
+        # one operator per phase; ``mask`` carries the patches' phases here
+        y = np.einsum("bmn,bn->bm", phi[mask], x)
+        y = y + sigma * rng_noise.standard_normal(y.shape)
     else:
         y = x @ phi.T
         y = y + sigma * rng_noise.standard_normal(y.shape)
     return x, y
+
+
+# ---- structured measurement operators (Section V's acquisition models) ----
+
+def bayer_mask(h: int, w: int) -> np.ndarray:
+    """RGGB colour-filter array over an (h, w, 3) image: red at (even, even),
+    green at (even, odd) and (odd, even), blue at (odd, odd); 1 = observed."""
+    m = np.zeros((h, w, 3), dtype=np.uint8)
+    m[0::2, 0::2, 0] = 1
+    m[0::2, 1::2, 1] = 1
+    m[1::2, 0::2, 1] = 1
+    m[1::2, 1::2, 2] = 1
+    return m
+
+
+def coded_exposure_phases(rng, frames: int, patch: int, period: int) -> np.ndarray:
+    """Location-dependent coded exposure: a per-pixel shutter code of
+    ``period`` x ``period`` pixels (Bernoulli(1/2) per pixel and frame), tiled
+    over the sensor.  A patch of patch x patch pixels starting at (y0, x0)
+    sees the tile shifted by (y0 mod period, x0 mod period); each of the
+    period^2 shifts is one operator, M = patch^2 rows over the frame-major
+    (t, y, x) patch of N = frames * patch^2 samples: the coded image sums the
+    open frames of each pixel.  Returns (period^2, patch^2, frames * patch^2)."""
+    code = rng.integers(0, 2, size=(frames, period, period)).astype(np.float64)
+    px = patch * patch
+    ops = np.zeros((period * period, px, frames * px))
+    yy, xx = np.meshgrid(np.arange(patch), np.arange(patch), indexing="ij")
+    pix = (yy * patch + xx).reshape(-1)
+    for dy in range(period):
+        for dx in range(period):
+            ph = dy * period + dx
+            c = code[:, (yy + dy) % period, (xx + dx) % period].reshape(frames, px)
+            for t in range(frames):
+                ops[ph, pix, t * px + pix] = c[t]
+    return ops
+
+
+def coded_aperture_phi(rng, shots: int, ang=(4, 4), spatial=(8, 8)) -> np.ndarray:
+    """Programmable-aperture light-field capture: each shot opens a binary
+    code over the angular samples (Bernoulli(1/2)) and every pixel records
+    the sum of its open views.  Rows (shot, y, x), columns (u, v, y, x)."""
+    na, ns = ang[0] * ang[1], spatial[0] * spatial[1]
+    codes = rng.integers(0, 2, size=(shots, na)).astype(np.float64)
+    phi = np.zeros((shots * ns, na * ns))
+    for s_ in range(shots):
+        for a in range(na):
+            phi[s_ * ns + np.arange(ns), a * ns + np.arange(ns)] = codes[s_, a]
+    return phi
 
 
 def make(name: str, batch: Optional[int] = None, seed: Optional[int] = None,
@@ -238,6 +292,26 @@ def make(name: str, batch: Optional[int] = None, seed: Optional[int] = None,
         dims, atoms, ks, sigma, phi_kind, m, dtype = [32, 512], [256, 4096], [4, 16], 0.005, "dense", 64, "f32"
         up_maps = [up0]
         k_fine = r_k.integers(4, 17, size=b).astype(np.int32)
+    elif name == "c4loc":
+        # video coded exposure whose shutter tile differs with the patch position
+        b = 32768 if batch is None else batch
+        up0, _ = box_map((8, 8, 8), (4, 2, 2))
+        dims, atoms, ks, sigma, phi_kind, m, dtype = [32, 512], [256, 4096], [4, 16], 0.005, "dense", 64, "f32"
+        up_maps = [up0]
+        k_fine = r_k.integers(4, 17, size=b).astype(np.int32)
+    elif name == "bayer":
+        # demosaicing: 24x24 RGB patches (y, x, c) over 12x12 per channel,
+        # observed through the colour-filter array at the patch's position
+        b = 4096 if batch is None else batch
+        up0, _ = box_map((24, 24, 3), (2, 2, 1))
+        dims, atoms, ks, sigma, phi_kind, m, dtype = [432, 1728], [128, 2048], [4, 8], 0.005, "mask", 1728, "f32"
+        up_maps = [up0]
+    elif name == "lfca":
+        # light field 4x4 views x 8x8 pixels through two coded-aperture shots
+        b = 16384 if batch is None else batch
+        up0, _ = box_map((4, 4, 8, 8), (2, 2, 2, 2))
+        dims, atoms, ks, sigma, phi_kind, m, dtype = [64, 1024], [128, 1024], [4, 8], 0.005, "dense", 128, "f32"
+        up_maps = [up0]
     elif name in ("c5a", "c5b", "c5c"):
         b = 4096 if batch is None else batch
         if name == "c5a":
@@ -272,7 +346,18 @@ def make(name: str, batch: Optional[int] = None, seed: Optional[int] = None,
     n = dims[-1]
     phi = None
     mask = None
-    if phi_kind == "dense":
+    phase = None
+    if name == "c4loc":
+        phi = coded_exposure_phases(r_phi, 8, 8, 4)
+        phase = r_extra.integers(0, phi.shape[0], size=b).astype(np.int32)
+    elif name == "lfca":
+        phi = coded_aperture_phi(r_phi, 2)
+    elif name == "bayer":
+        # patches cut at random positions: the CFA phase is the position's parity
+        cfa = bayer_mask(2 * 24 + 2, 2 * 24 + 2)
+        pos = r_mask.integers(0, 2, size=(b, 2))
+        mask = np.stack([cfa[py:py + 24, px:px + 24].reshape(-1) for py, px in pos]).astype(np.uint8)
+    elif phi_kind == "dense":
         if name == "c4":
             frames = r_phi.integers(0, 2, size=(8, 64)).astype(np.float64)
             phi = np.zeros((64, 512))
@@ -284,11 +369,12 @@ def make(name: str, batch: Optional[int] = None, seed: Optional[int] = None,
         mask = r_mask.integers(0, 2, size=(b, n)).astype(np.uint8)
 
     support = draw_tree_support(r_sup, b, atoms, q, ks, k_fine)
-    x, y = synthesize(r_coef, r_noise, dicts[-1], support, phi_kind, phi, mask, sigma)
+    x, y = synthesize(r_coef, r_noise, dicts[-1], support, phi_kind, phi,
+                      phase if phase is not None else mask, sigma)
     return Workload(name=name, seed=seed, dims=dims, atoms=atoms, dicts=dicts, up_maps=up_maps,
                     phi_kind=phi_kind, m=m, phi=phi, x=x, y=y, mask=mask, k_scales=ks,
                     k_fine=k_fine, sigma=sigma, true_support=support, dtype=dtype,
-                    meta={"dict_kind": dict_kind, "child_detail": detail})
+                    meta={"dict_kind": dict_kind, "child_detail": detail}, phase=phase)
 
 
 def custom(dims, atoms, batch, seed, phi_kind="identity", m=None, k_scales=None, sigma=0.0,
@@ -339,4 +425,4 @@ def subset(w: Workload, idx) -> Workload:
                     y=w.y[idx], mask=None if w.mask is None else w.mask[idx],
                     k_scales=w.k_scales, k_fine=None if w.k_fine is None else w.k_fine[idx],
                     sigma=w.sigma, true_support=w.true_support[idx], dtype=w.dtype,
-                    meta=dict(w.meta, subset=True))
+                    meta=dict(w.meta, subset=True), phase=None if w.phase is None else w.phase[idx])

@@ -106,7 +106,7 @@ def compare(w, gpu_sup, gpu_coef, gpu_kused, gpu_xhat=None, full=False, k_scales
         sub = _subset(w, active)
         res = oracle.omp(sub.dims, sub.atoms, sub.dicts, sub.up_maps, sub.phi_kind, sub.m, sub.phi,
                          sub.y, sub.mask, ks, k_fine=sub.k_fine, full=full, forced=forced[active],
-                         kstride=kstride, with_trace=True)
+                         kstride=kstride, with_trace=True, phase=getattr(sub, "phase", None))
         nxt = []
         for ii, b in enumerate(active):
             b = int(b)
