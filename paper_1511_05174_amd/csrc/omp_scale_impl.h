@@ -45,7 +45,7 @@ constexpr int KX = kMaxK;        // FP64 rare-path table size
 // Condition estimates tr(G) tr(G^{-1}) / n of the final support's Gram
 // matrix above which the coefficients take one step of mixed-precision
 // refinement, and above which they are re-solved in FP64 altogether.
-constexpr double kRefineEst = 20.0;
+constexpr double kRefineEst = 10.0;
 constexpr double kBackSubEst = 1e4;
 constexpr int LP_GRAM = 256;     // LDS row length for gram-mode kernels
 

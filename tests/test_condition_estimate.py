@@ -5,7 +5,7 @@ The kernels estimate kappa(G) of the final support's Gram matrix as
 tr(G) tr(G^-1) / n, accumulated while the support grows (tr(G) from the
 pivots' squared norms, tr(G^-1) = ||L^-1||_F^2 from the columns of L^-1).
 For symmetric positive definite G this lies between kappa(G) / n and
-n kappa(G); the kernels refine the coefficients above 20 and re-solve them in
+n kappa(G); the kernels refine the coefficients above 10 and re-solve them in
 FP64 above 1e4 (one refinement step leaves about (kappa 2^-24)^2, which
 reaches the 1e-5 tolerance near kappa ~ 5e4, hence the margin), and compute a
 pivot in FP64 when the squared pivots' range exceeds 1e6.
@@ -61,7 +61,7 @@ def test_thresholds_reach_each_stage():
         return estimate(g), g[0, 0] / piv, piv / g[1, 1]
 
     e, ratio, rel = pair(2.0 ** -3)
-    assert 20 < e < 1e4 and ratio < 1e6 and rel > 1e-5          # refinement only
+    assert 10 < e < 1e4 and ratio < 1e6 and rel > 1e-5          # refinement only
     e, ratio, rel = pair(2.0 ** -7)
     assert e > 1e4 and ratio < 1e6 and rel > 1e-5               # FP64 re-solve
     e, ratio, rel = pair(2.0 ** -11)

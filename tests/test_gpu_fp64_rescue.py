@@ -92,7 +92,7 @@ def test_fp64_rescue(delta, stage):
     est, g = estimate(w.dicts[-1][w.true_support[0]].T)
     piv = g[1, 1] - g[0, 1] ** 2 / g[0, 0]
     if stage == "refine":
-        assert 20 < est < 1e4
+        assert 10 < est < 1e4
     else:
         assert est > 1e4
     if "pivot" in stage:
