@@ -396,10 +396,12 @@ def serve_phase(cspd, jobs=2000, loads=(0.5, 0.8, 0.95), budget=4 << 30, slots=4
 
 
 def precision_phase(cspd, steps: int = 3):
-    """Reduced-precision proxy study on the three-scale workload's finest
-    scale (full OMP, 4096 atoms of length 128, K = 12, 262,144 patches): time
-    per call of the FP32 proxy and of the bf16 / fp16 proxies with FP32
-    re-scoring, and how far each result is from the FP32 path's."""
+    """Reduced-precision proxy study on the three-scale workload (262,144
+    patches): full OMP over its finest scale (4096 atoms of length 128, K =
+    12) and cross-scale OMP over all three scales, each with the FP32 proxy
+    and with bf16 / fp16 proxies plus FP32 re-scoring: time per call and how
+    far each result is from the FP32 path's.  (Errors against the FP64
+    oracle come from the parity tests, which run the oracle.)"""
     import torch
 
     import synth
@@ -438,6 +440,41 @@ def precision_phase(cspd, steps: int = 3):
             ent["xhat_rel_diff_vs_fp32_max"] = float(d.max())
             ent["speedup_vs_fp32"] = out["modes"]["native"]["ms_per_call"] / ent["ms_per_call"]
         out["modes"][mode] = ent
+        cspd.cspd_plan_destroy(plan)
+    # cross-scale OMP on the same workload: scale 0's correlations with y from
+    # the FP32 / bf16 / fp16 batched contraction, FP32 re-scoring before each
+    # first-scale pick
+    ks = w.k_scales
+    out["cross"] = {"workload": f"c3 cross-scale: {B} patches, dims {w.dims}, atoms {w.atoms}, K {ks}",
+                    "modes": {}}
+    ref = None
+    for mode in ("native", "bf16", "f16"):
+        plan = cspd.plan_from_workload(w, corr_mode=mode)
+        res = cspd.cspd_omp_cross_scale(plan, y, None, ks[:-1], None, ks[-1])
+        torch.cuda.synchronize()
+        cspd.cspd_profile_reset()
+        cspd.cspd_profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            cspd.cspd_omp_cross_scale(plan, y, None, ks[:-1], None, ks[-1], support=res[0], coef=res[1],
+                                      k_used=res[2], xhat=res[3])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cspd.cspd_profile_enable(False)
+        prof = cspd.cspd_profile_read()
+        s_np = res[0].cpu().numpy()
+        x_np = res[3].double().cpu().numpy()
+        ent = {"ms_per_call": (t1 - t0) / steps * 1e3, "patches_per_s": B * steps / (t1 - t0),
+               "kernels": {k: v[1] / max(v[0], 1) for k, v in prof.items()}}
+        if ref is None:
+            ref = (s_np, x_np)
+        else:
+            d = np.linalg.norm(x_np - ref[1], axis=1) / np.maximum(np.linalg.norm(ref[1], axis=1), 1e-30)
+            ent["same_support_as_fp32"] = float(np.mean(np.all(s_np == ref[0], axis=1)))
+            ent["xhat_rel_diff_vs_fp32_q99"] = float(np.quantile(d, 0.99))
+            ent["xhat_rel_diff_vs_fp32_max"] = float(d.max())
+            ent["speedup_vs_fp32"] = out["cross"]["modes"]["native"]["ms_per_call"] / ent["ms_per_call"]
+        out["cross"]["modes"][mode] = ent
         cspd.cspd_plan_destroy(plan)
     return out
 

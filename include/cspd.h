@@ -71,10 +71,13 @@ enum { CSPD_F64 = 0, CSPD_F32 = 1 };
 /* How the full-dictionary proxy is evaluated (not in the paper: a precision
  * option).  NATIVE computes correlations in the plan's dtype; the two
  * RESCORE modes compute them with bf16 / fp16 matrix cores and FP32
- * accumulation, keep a pool of rescore_m candidates per patch and re-score
- * those in FP32 (exact correlations and norms) before the argmax.  The pool
- * is the best reduced-precision scores of each of the 8 lanes that serve a
- * patch: one per lane for rescore_m <= 8, two for rescore_m > 8. */
+ * accumulation, and re-score in FP32 (exact correlations and norms) the
+ * rescore_m candidates of each patch with the best reduced-precision scores
+ * (an exact per-patch top-m, ties to the lower atom index) before the argmax:
+ * in full OMP at every iteration; in cross-scale OMP at the first scale,
+ * whose correlations with y come from one batched contraction (shared dense
+ * operator), the top rescore_m by current score at every iteration (a
+ * candidate re-scored once stays exact). */
 enum { CSPD_CORR_NATIVE = 0, CSPD_CORR_BF16_RESCORE = 1, CSPD_CORR_F16_RESCORE = 2 };
 
 /*
@@ -93,7 +96,7 @@ enum { CSPD_CORR_NATIVE = 0, CSPD_CORR_BF16_RESCORE = 1, CSPD_CORR_F16_RESCORE =
  *   phi        host, row-major M x N, FP64 (CSPD_PHI_DENSE only, else NULL).
  *   dtype      CSPD_F32 or CSPD_F64.
  *   corr_mode  CSPD_CORR_* (RESCORE modes need CSPD_F32).
- *   rescore_m  candidates re-scored per patch in RESCORE modes (1..16; 0 = 16).
+ *   rescore_m  candidates re-scored per patch in RESCORE modes (1..16; 0 = 8).
  *   k_max      largest sparsity any call will ask for at any scale; the
  *              row stride of the support / coef outputs.
  *   device     HIP device ordinal the plan lives on.

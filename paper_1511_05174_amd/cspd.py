@@ -247,9 +247,10 @@ def cspd_plan(dims: Sequence[int], atoms: Sequence[int], dicts, up_maps, phi_kin
 
 
 def plan_from_workload(w, dtype: Optional[str] = None, corr_mode: str = "native", k_max: int = 16,
-                       device: int = 0) -> Plan:
+                       device: int = 0, rescore_m: int = 0) -> Plan:
     return cspd_plan(w.dims, w.atoms, w.dicts, w.up_maps, w.phi_kind, w.m, w.phi,
-                     dtype=dtype or w.dtype, corr_mode=corr_mode, k_max=k_max, device=device)
+                     dtype=dtype or w.dtype, corr_mode=corr_mode, rescore_m=rescore_m, k_max=k_max,
+                     device=device)
 
 
 def cspd_plan_destroy(plan: Plan):

@@ -162,6 +162,11 @@ ScaleArgs base_args(const cspd_plan_s *p, int s, int64_t B, const void *y, const
     a.q = sc.q;
     a.qmagic = sc.q > 1 ? (unsigned)((((uint64_t)1 << 32) + (uint64_t)sc.q - 1) / (uint64_t)sc.q) : 0u;
     a.d_high = p->d_high;
+    if (s == 0 && p->s >= 2 && p->corr_mode != CSPD_CORR_NATIVE && sc.v_lo) {
+        a.vlo = sc.v_lo;
+        a.corr_lo = p->corr_mode;
+        a.hre = p->rescore_m;
+    }
     return a;
 }
 
@@ -422,7 +427,7 @@ cspd_status cspd_plan(const cspd_plan_desc *d, cspd_plan_t *out)
     p->phi_kind = d->phi_kind;
     p->dtype = d->dtype;
     p->corr_mode = d->corr_mode;
-    p->rescore_m = d->rescore_m ? d->rescore_m : 16;
+    p->rescore_m = d->rescore_m ? d->rescore_m : 8;
     p->k_max = d->k_max;
     p->n_phases = d->n_phases > 1 ? d->n_phases : 1;
     p->device = d->device;

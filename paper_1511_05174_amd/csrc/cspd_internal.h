@@ -155,6 +155,13 @@ struct ScaleArgs {
     const int *phase;
     int n_phases;
     int64_t phase_stride;
+    // reduced-precision first-scale correlations (cross-scale, dense
+    // operator): the 16-bit copy of v for the contraction, its format
+    // (CSPD_CORR_*), and how many candidates the kernel may re-score in FP32
+    // before each pick (0: the correlations are FP32 and no re-scoring runs)
+    const void *vlo;
+    int corr_lo;
+    int hre;
 };
 
 // Kernel variants that can run one scale (FP32): the first-scale MFMA kernel,

@@ -21,10 +21,20 @@
 // tiles run on bf16 or fp16 matrix cores (v_mfma_f32_32x32x16_*, FP32
 // accumulation) from the plan's 16-bit copy of A and a 16-bit copy of the
 // residual (scaled per patch to a maximum of 1, which leaves the argmax
-// unchanged and keeps fp16 clear of underflow).  Each of the eight lanes that
-// serve a patch keeps its RR best scores; those 8 RR candidates are re-scored
-// with exact FP32 correlations and norms, and the argmax is taken over the
-// re-scored values.  Everything after the pick stays FP32.
+// unchanged and keeps fp16 clear of underflow).  The patch's m best
+// reduced-precision candidates (m = rescore_m; an exact top-m under the key
+// below) are re-scored with FP32 correlations and norms, and the argmax is
+// taken over the re-scored values.  A candidate's key is one 32-bit word:
+// its score with the 11 lowest mantissa bits dropped (12 remain, finer than
+// the 16-bit products' own error) above its inverted atom index, so a larger
+// key is a better score, or an equal one at a lower index.  Each of the eight
+// lanes that serve a patch keeps its MM >= m largest keys sorted (insertion is
+// a max / min chain, run only for keys above the lane's smallest); the eight
+// lists go to LDS, where an entry's rank in the union is its position in its
+// own list plus the entries of the other lists above it, and the entries of
+// rank below m are the top m.  The eight threads of the patch then re-score
+// those m together, one dot product at a time.  Everything after the pick
+// stays FP32.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -68,6 +78,7 @@ struct FullArgs {
     float *xhat;
     const float *d_high;       // T x n
     const uint16_t *v_lo;      // t x lp, bf16 or fp16 copy of v (reduced-precision proxy)
+    int rescore_m;             // candidates re-scored in FP32 per patch (1..16)
 };
 
 __device__ __forceinline__ void sync() { __syncthreads(); }
@@ -142,7 +153,7 @@ __device__ __forceinline__ void argmax8(float &s, int &i)
     argmax_dpp<0x141>(s, i);
 }
 
-template <int LP, int KM, bool MASK, int CM, int RR>
+template <int LP, int KM, bool MASK, int CM, int MM>
 __global__ __launch_bounds__(64 * NW) void k_omp_full(FullArgs a)
 {
     constexpr int HL = LP / 2;            // coordinates per operand half
@@ -161,7 +172,12 @@ __global__ __launch_bounds__(64 * NW) void k_omp_full(FullArgs a)
     __shared__ float s_al[P][KM];
     __shared__ int s_sup[P][KM];
     __shared__ int s_n[P], s_kk[P], s_live[P];
-    __shared__ int s_cand[CM != CM_NATIVE ? P : 1][CM != CM_NATIVE ? NW * 2 * RR : 1];
+    // reduced-precision pools: 8 sorted lists of MM (score, atom) per patch,
+    // and the patch's top m in rank order (-1: fewer valid candidates)
+    constexpr bool RP = CM != CM_NATIVE;
+    __shared__ unsigned s_pk[RP ? P : 1][RP ? NW * 2 : 1][RP ? MM : 1];
+    __shared__ int s_top[RP ? P : 1][RP ? MM : 1];
+    const int mtop = RP ? (a.rescore_m < MM ? (a.rescore_m > 0 ? a.rescore_m : 1) : MM) : 1;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -231,8 +247,12 @@ __global__ __launch_bounds__(64 * NW) void k_omp_full(FullArgs a)
         }
         float bs = -1.f;
         int bi = INT_MAX;
-        float bs2 = -1.f;          // second best of this lane (RR == 2)
-        int bi2 = INT_MAX;
+        unsigned lk[RP ? MM : 1];   // this lane's largest keys, sorted (0: empty)
+#pragma unroll
+        for (int q = 0; q < (RP ? MM : 1); ++q) lk[q] = 0u;
+        if constexpr (RP) {
+            for (int i = tid; i < P * MM; i += 64 * NW) s_top[i / MM][i % MM] = -1;
+        }
         const bool plive = s_live[pp] != 0;
         unsigned rlo[CM != CM_NATIVE ? HL / 8 : 1][4];
         if constexpr (CM != CM_NATIVE) {
@@ -291,47 +311,83 @@ __global__ __launch_bounds__(64 * NW) void k_omp_full(FullArgs a)
                 float sc = fabsf(acc[r]) * inv;
                 const bool ok = plive & (atom < a.t) & (inv > 0.f) & (((selw >> row) & 1u) == 0u);
                 sc = ok ? sc : -1.f;
-                if constexpr (RR == 2) {
-                    const bool up1 = sc > bs, up2 = sc > bs2;
-                    bs2 = up1 ? bs : (up2 ? sc : bs2);
-                    bi2 = up1 ? bi : (up2 ? atom : bi2);
+                if constexpr (RP) {
+                    // key: score bits >> 11 (plus one, so 0 means none) over
+                    // the inverted atom index (atoms < 4096)
+                    const unsigned key = sc >= 0.f ? ((((__float_as_uint(sc) >> 11) + 1u) << 12) | (4095u - (unsigned)atom))
+                                                   : 0u;
+                    if (key > lk[MM - 1]) {
+                        unsigned x = key;
+#pragma unroll
+                        for (int q = 0; q < MM; ++q) {
+                            const unsigned hi = x > lk[q] ? x : lk[q];
+                            x = x > lk[q] ? lk[q] : x;
+                            lk[q] = hi;
+                        }
+                    }
+                } else if (sc > bs) {
+                    bs = sc;
+                    bi = atom;
                 }
-                if (sc > bs) { bs = sc; bi = atom; }
             }
         }
-        if constexpr (CM != CM_NATIVE) {
-            // every lane's pool to LDS, then FP32 re-scoring by the update threads
-            int *cd = s_cand[pp] + (wave * 2 + h) * RR;
-            cd[0] = bs >= 0.f ? bi : -1;
-            if constexpr (RR == 2) cd[1] = bs2 >= 0.f ? bi2 : -1;
+        if constexpr (RP) {
+            // the eight sorted pools of each patch to LDS
+#pragma unroll
+            for (int q = 0; q < MM; ++q) s_pk[pp][wave * 2 + h][q] = lk[q];
             sync();
             {
+                // rank of each own entry in the union; the top m by rank
+                const int upp = tid / TPP, uss = tid % TPP;
+                for (int q = 0; q < mtop; ++q) {
+                    const unsigned ek = s_pk[upp][uss][q];
+                    if (ek == 0u) break;
+                    int rank = q;
+                    for (int j = 0; j < NW * 2 && rank < mtop; ++j) {
+                        if (j == uss) continue;
+                        for (int r = 0; r < MM && s_pk[upp][j][r] > ek; ++r) ++rank;
+                    }
+                    if (rank < mtop) s_top[upp][rank] = 4095 - (int)(ek & 4095u);
+                }
+            }
+            sync();
+            {
+                // FP32 re-score of the top m by the patch's eight threads
                 const int upp = tid / TPP, uss = tid % TPP;
                 float best = -1.f;
                 int bidx = INT_MAX;
+                for (int j = 0; j < mtop; ++j) {
+                    const int atom = s_top[upp][j];
+                    if (atom < 0) break;
+                    const float *ar = a.v + (int64_t)atom * a.lp + uss * CP;
+                    float c = 0.f, nn = 0.f;
+                    float vv[CP];
+                    if constexpr (CP % 4 == 0) {
 #pragma unroll
-                for (int j = 0; j < RR; ++j) {
-                    const int atom = s_cand[upp][uss * RR + j];
-                    if (atom >= 0) {
-                        const float *ar = a.v + (int64_t)atom * a.lp;
-                        float c = 0.f, nn = 0.f;
-                        for (int q = 0; q < LP; q += 4) {
+                        for (int q = 0; q < CP; q += 4) {
                             const float4 v4 = *reinterpret_cast<const float4 *>(ar + q);
-                            const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                c += vv[e] * s_r[upp][q + e];
-                                if constexpr (MASK) nn += vv[e] * vv[e] * s_m[upp][q + e];
-                            }
+                            vv[q] = v4.x; vv[q + 1] = v4.y; vv[q + 2] = v4.z; vv[q + 3] = v4.w;
                         }
-                        float inv;
-                        if constexpr (MASK) inv = nn > 0.f ? 1.f / sqrtf(nn) : -1.f;
-                        else inv = a.inv_nu[atom];
-                        const float sc = inv > 0.f ? fabsf(c) * inv : -1.f;
-                        if (beats(sc, atom, best, bidx)) { best = sc; bidx = atom; }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < CP; ++q) vv[q] = ar[q];
                     }
+#pragma unroll
+                    for (int q = 0; q < CP; ++q) {
+                        c += vv[q] * s_r[upp][uss * CP + q];
+                        if constexpr (MASK) nn += vv[q] * vv[q] * mk[q];
+                    }
+                    c = sum8(c);
+                    float inv;
+                    if constexpr (MASK) {
+                        nn = sum8(nn);
+                        inv = nn > 0.f ? 1.f / sqrtf(nn) : -1.f;
+                    } else {
+                        inv = a.inv_nu[atom];
+                    }
+                    const float sc = inv > 0.f ? fabsf(c) * inv : -1.f;
+                    if (beats(sc, atom, best, bidx)) { best = sc; bidx = atom; }
                 }
-                argmax8(best, bidx);
                 if (uss == 0) {
                     const bool go = s_live[upp] && best >= 0.f && s_n[upp] < s_kk[upp];
                     s_k[upp] = go ? bidx : -1;
@@ -477,23 +533,23 @@ __global__ __launch_bounds__(64 * NW) void k_omp_full(FullArgs a)
     }
 }
 
-template <int LP, int KM, bool MASK, int CM, int RR>
+template <int LP, int KM, bool MASK, int CM, int MM>
 cspd_status launch(const FullArgs &a, hipStream_t st)
 {
     const unsigned grid = (unsigned)((a.b + P - 1) / P);
     char label[96];
     const char *ty = CM == CM_BF16 ? "bf16" : (CM == CM_F16 ? "f16" : "f32");
     snprintf(label, sizeof(label), "omp_full_mfma<%s,lp%d,k%d%s,m%d>:full", ty, LP, KM, MASK ? ",mask" : "",
-             CM == CM_NATIVE ? 0 : 8 * RR);
-    launch_timed(label, k_omp_full<LP, KM, MASK, CM, RR>, dim3(grid), dim3(64 * NW), 0u, st, a);
+             CM == CM_NATIVE ? 0 : MM);
+    launch_timed(label, k_omp_full<LP, KM, MASK, CM, MM>, dim3(grid), dim3(64 * NW), 0u, st, a);
     CSPD_HIP_CHECK(hipGetLastError());
     return CSPD_OK;
 }
 
-template <int LP, int KM, int CM, int RR>
+template <int LP, int KM, int CM, int MM>
 cspd_status by_mask(const FullArgs &a, bool mask, hipStream_t st)
 {
-    return mask ? launch<LP, KM, true, CM, RR>(a, st) : launch<LP, KM, false, CM, RR>(a, st);
+    return mask ? launch<LP, KM, true, CM, MM>(a, st) : launch<LP, KM, false, CM, MM>(a, st);
 }
 
 template <int LP, int KM>
@@ -501,9 +557,9 @@ cspd_status by_mode(const FullArgs &a, bool mask, int corr, int rr, hipStream_t 
 {
     if constexpr (LP >= 16) {
         if (corr == CSPD_CORR_BF16_RESCORE)
-            return rr == 1 ? by_mask<LP, KM, CM_BF16, 1>(a, mask, st) : by_mask<LP, KM, CM_BF16, 2>(a, mask, st);
+            return rr <= 8 ? by_mask<LP, KM, CM_BF16, 8>(a, mask, st) : by_mask<LP, KM, CM_BF16, 16>(a, mask, st);
         if (corr == CSPD_CORR_F16_RESCORE)
-            return rr == 1 ? by_mask<LP, KM, CM_F16, 1>(a, mask, st) : by_mask<LP, KM, CM_F16, 2>(a, mask, st);
+            return rr <= 8 ? by_mask<LP, KM, CM_F16, 8>(a, mask, st) : by_mask<LP, KM, CM_F16, 16>(a, mask, st);
     }
     return by_mask<LP, KM, CM_NATIVE, 1>(a, mask, st);
 }
@@ -558,7 +614,8 @@ cspd_status launch_full_mfma(const cspd_plan_s *p, int64_t b, const void *y, con
     const int kmax = kvec ? p->k_max : kuni;
     const bool m = a.mask != nullptr;
     const int corr = sc.v_lo ? p->corr_mode : CSPD_CORR_NATIVE;
-    const int rr = p->rescore_m <= 8 ? 1 : 2;   // candidates kept per lane (8 lanes per patch)
+    const int rr = p->rescore_m;    // top m re-scored per patch (pool lists of 8 or 16 per lane)
+    a.rescore_m = rr;
     switch (sc.lp) {
         case 16: return by_k<16>(a, kmax, m, corr, rr, stream);
         case 32: return by_k<32>(a, kmax, m, corr, rr, stream);

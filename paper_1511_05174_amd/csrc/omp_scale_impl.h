@@ -355,7 +355,7 @@ struct alignas(16) GroupLds {
     uint32_t ysh[PSN];
     uint32_t ysl[PSN];
     uint32_t mpat[PSN];
-    T yhat[LPA];
+    alignas(16) T yhat[LPA];
     T sqw[LPA];
     T vk[LPA];
     T uk[KM];
@@ -1055,6 +1055,10 @@ void k_omp_scale(ScaleArgs a)
     T trg = 0;        // trace of the support's Gram matrix
     // largest and smallest squared pivot (diagonal of L) accepted so far
     T p2max = T(0), p2min = sizeof(T) == 4 ? T(3.0e38f) : T(1.0e300);
+    // reduced-precision correlations with y (first scale): slots whose
+    // correlation has been re-scored in FP32
+    const bool rescore = GRAM && sizeof(T) == 4 && a.hre > 0 && a.hpre != nullptr;
+    unsigned exm = 0u;
 #pragma unroll
     for (int n = 0; n < KM; ++n) {
         if (n >= kwave) break;
@@ -1095,9 +1099,78 @@ void k_omp_scale(ScaleArgs a)
                 w.sc[2] = e0[0];
             }
         } else {
+            if constexpr (GRAM && sizeof(T) == 4) {
+                if (rescore) {
+                    // The a.hre candidates with the best current scores are
+                    // selected, and those whose correlation is still the
+                    // reduced-precision one are re-scored in FP32, all lanes
+                    // at once (<a_i, y> from the stored vector; a re-scored
+                    // slot stays exact).  The pick is the best exactly scored
+                    // candidate: the selected ones and any re-scored before.
+                    // Selection key: the score with its 11 lowest mantissa
+                    // bits dropped, over the inverted atom index (a larger key
+                    // is a better score, or an equal one at a lower index);
+                    // the a.hre-th largest key of the group is found bit by
+                    // bit from the top with ballot counts.
+                    unsigned key[NC];
+#pragma unroll
+                    for (int s = 0; s < NC; ++s) {
+                        const T sc = fabs(c[s]) * nu[s];
+                        key[s] = (act && live[s] && sc >= T(0))
+                                     ? ((((__float_as_uint(sc) >> 11) + 1u) << 12) | (4095u - (unsigned)atom[s]))
+                                     : 0u;
+                    }
+                    unsigned thr = 0u;
+                    for (int bit = 31; bit >= 0; --bit) {
+                        const unsigned cand = thr | (1u << bit);
+                        int cnt = 0;
+#pragma unroll
+                        for (int s = 0; s < NC; ++s) cnt += group_count<G>(key[s] >= cand, lane);
+                        thr = cnt >= a.hre ? cand : thr;
+                    }
+                    unsigned todo = 0u;
+#pragma unroll
+                    for (int s = 0; s < NC; ++s)
+                        if (key[s] != 0u && key[s] >= thr && !((exm >> s) & 1u)) todo |= 1u << s;
+                    if (__ballot(todo != 0u)) {
+                        static_assert(G == 64, "Gram-table kernels hold one patch per wavefront");
+                        // The wavefront re-scores the selected candidates
+                        // together, one at a time: lane l takes coordinates
+                        // l, l + 64, ... (the shared dense operator has unit
+                        // weights), and the sum goes to every lane.
+                        constexpr int NR = LP_GRAM / 64;
+                        T yl[NR];
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) {
+                            const int j = lane + 64 * r;
+                            yl[r] = j < lp ? w.yhat[j] : T(0);
+                        }
+#pragma unroll
+                        for (int s = 0; s < NC; ++s) {
+                            unsigned long long ms = __ballot((todo >> s) & 1u);
+                            while (ms) {
+                                const int ln = __builtin_ctzll(ms);
+                                ms &= ms - 1ull;
+                                const int at = __builtin_amdgcn_readlane(atom[s], ln);
+                                const T *row = vph + (int64_t)at * lp;
+                                T part = T(0);
+#pragma unroll
+                                for (int r = 0; r < NR; ++r) {
+                                    const int j = lane + 64 * r;
+                                    if (j < lp) part += row[j] * yl[r];
+                                }
+                                const T hx = group_sum<64>(part);
+                                if (lane == ln) c[s] += hx - ((const T *)a.hpre)[bb * (int64_t)a.t + at];
+                            }
+                        }
+                        exm |= todo;
+                    }
+                }
+            }
 #pragma unroll
             for (int s = 0; s < NC; ++s) {
-                const T sc = live[s] ? fabs(c[s]) * nu[s] : T(-1);
+                const bool ok = live[s] && (!rescore || ((exm >> s) & 1u));
+                const T sc = ok ? fabs(c[s]) * nu[s] : T(-1);
                 const bool up = (sc > best) | ((sc == best) & (atom[s] < bidx));
                 best = up ? sc : best;
                 bidx = up ? atom[s] : bidx;

@@ -294,7 +294,11 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
         // are not used
         const bool norms = !mask && P == 1;
         const bool gram = !mask && P == 1 && T <= kMaxGramAtoms && (s == 0 || s == S - 1) && sc.lp <= kMaxShortLen;
-        const int lo = (s == S - 1 && p->dtype == CSPD_F32 && P == 1) ? p->corr_mode : 0;
+        // 16-bit copies for the reduced-precision proxy: full search at the
+        // finest scale, and the first scale's batched contraction under a
+        // shared dense operator
+        const bool lo_scale = s == S - 1 || (s == 0 && dense && S >= 2);
+        const int lo = (lo_scale && p->dtype == CSPD_F32 && P == 1) ? p->corr_mode : 0;
         cspd_status rc = p->dtype == CSPD_F64
             ? finish_scale<double>(sc, (const double *)a64.p, wsrc, norms, gram, 0, P, st, p->bytes)
             : finish_scale<float>(sc, (const double *)a64.p, wsrc, norms, gram, lo, P, st, p->bytes);

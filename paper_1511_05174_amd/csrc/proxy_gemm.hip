@@ -16,6 +16,14 @@
 // LH) of its patch and its atom).  The accumulator leaves lane l with atom
 // l % 32 of patches 8 (r / 4) + 4 (l / 32) + r % 4, so each store instruction
 // writes two 128-byte row segments of H.
+//
+// Reduced-precision variant (a precision option, not in the paper): the same
+// tiles on the bf16 / fp16 matrix cores (v_mfma_f32_32x32x16_*, FP32
+// accumulation) from the plan's 16-bit copy of A_0 and a 16-bit copy of each
+// patch scaled by a power of two to a largest entry in [0.5, 1) (the scale is
+// undone exactly on the accumulators).  Lane half h supplies coordinates
+// h LH + 8 g + [0, 8) at step g on both operands.  The per-patch OMP then
+// re-scores its candidates in FP32 before each pick.
 #include <hip/hip_runtime.h>
 
 #include "cspd_internal.h"
@@ -74,11 +82,115 @@ void k_proxy_gemm(const float *__restrict__ y, int y_stride, int m, int64_t nb, 
     }
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <int LP, bool BF16>
+__global__ __launch_bounds__(64 * W)
+void k_proxy_gemm_lo(const float *__restrict__ y, int y_stride, int m, int64_t nb,
+                     const uint16_t *__restrict__ vlo, int lp, int t, float *__restrict__ h)
+{
+    constexpr int LH = LP / 2;
+    constexpr int NG = LH / 8;
+    static_assert(NG >= 1 && LH % 8 == 0, "8 coordinates per lane and step");
+    typedef float acc_t __attribute__((ext_vector_type(16)));
+    const int lane = threadIdx.x & 63;
+    const int hh = lane >> 5;
+    const int col = lane & 31;
+    const int64_t p0 = ((int64_t)blockIdx.x * W + (threadIdx.x >> 6)) * 32;
+    if (p0 >= nb) return;   // the whole wavefront leaves together
+    const int64_t prow = p0 + col < nb ? p0 + col : nb - 1;
+    const float *yr = y + prow * (int64_t)y_stride;
+    float ya[LH];
+    float mx = 0.f;
+#pragma unroll
+    for (int j = 0; j < LH; ++j) {
+        const int c = hh * LH + j;
+        const float val = yr[c < m ? c : 0];
+        ya[j] = c < m ? val : 0.f;
+        mx = fmaxf(mx, fabsf(ya[j]));
+    }
+    {
+        // lanes l and l + 32 hold the two halves of the same patch
+        auto rs = __builtin_amdgcn_permlane32_swap(__float_as_int(mx), __float_as_int(mx), false, false);
+        mx = fmaxf(__int_as_float(rs[0]), __int_as_float(rs[1]));
+    }
+    int ex = 0;
+    (void)frexpf(mx, &ex);                   // mx = f 2^ex, f in [0.5, 1)
+    ex = ex < -100 ? -100 : (ex > 100 ? 100 : ex);
+    const float sc = mx > 0.f ? ldexpf(1.f, -ex) : 1.f;
+    const float inv = mx > 0.f ? ldexpf(1.f, ex) : 1.f;
+    unsigned yl[NG][4];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float f0 = ya[8 * g + 2 * i] * sc, f1 = ya[8 * g + 2 * i + 1] * sc;
+            unsigned lo, hi;
+            if constexpr (BF16) {
+                unsigned u0 = __float_as_uint(f0), u1 = __float_as_uint(f1);
+                u0 += 0x7fffu + ((u0 >> 16) & 1u);   // round to nearest even
+                u1 += 0x7fffu + ((u1 >> 16) & 1u);
+                lo = u0 >> 16;
+                hi = u1 >> 16;
+            } else {
+                const _Float16 a0 = (_Float16)f0, a1 = (_Float16)f1;
+                lo = *reinterpret_cast<const unsigned short *>(&a0);
+                hi = *reinterpret_cast<const unsigned short *>(&a1);
+            }
+            yl[g][i] = lo | (hi << 16);
+        }
+    }
+    // inverse scale of the patch row each accumulator entry belongs to
+    float rinv[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) rinv[r] = __shfl(inv, 8 * (r >> 2) + 4 * hh + (r & 3), 64);
+    for (int a0 = 0; a0 < t; a0 += 32) {
+        const int at = a0 + col < t ? a0 + col : t - 1;
+        const uint16_t *vr = vlo + (int64_t)at * lp + hh * LH;
+        acc_t acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(vr + 8 * g);
+            const unsigned xb[4] = {q.x, q.y, q.z, q.w};
+            if constexpr (BF16) {
+                bf16x8 xa, xv;
+                __builtin_memcpy(&xa, yl[g], 16);
+                __builtin_memcpy(&xv, xb, 16);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, xv, acc, 0, 0, 0);
+            } else {
+                f16x8 xa, xv;
+                __builtin_memcpy(&xa, yl[g], 16);
+                __builtin_memcpy(&xv, xb, 16);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa, xv, acc, 0, 0, 0);
+            }
+        }
+        if (a0 + col < t) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t p = p0 + 8 * (r >> 2) + 4 * hh + (r & 3);
+                if (p < nb) h[p * t + a0 + col] = acc[r] * rinv[r];
+            }
+        }
+    }
+}
+
 template <int LP>
 cspd_status launch(const ScaleArgs &a, float *h, hipStream_t st)
 {
     const int64_t waves = (a.b + 31) / 32;
     const unsigned grid = (unsigned)((waves + W - 1) / W);
+    if (a.hre > 0 && a.vlo) {
+        if (a.corr_lo == CSPD_CORR_BF16_RESCORE)
+            launch_timed("proxy_gemm<bf16>:s0", k_proxy_gemm_lo<LP, true>, dim3(grid), dim3(64 * W), 0u, st,
+                         (const float *)a.y, a.y_stride, a.m_dense, a.b, (const uint16_t *)a.vlo, a.lp, a.t, h);
+        else
+            launch_timed("proxy_gemm<f16>:s0", k_proxy_gemm_lo<LP, false>, dim3(grid), dim3(64 * W), 0u, st,
+                         (const float *)a.y, a.y_stride, a.m_dense, a.b, (const uint16_t *)a.vlo, a.lp, a.t, h);
+        return hipGetLastError() == hipSuccess ? CSPD_OK : CSPD_E_DEVICE;
+    }
     launch_timed("proxy_gemm<f32>:s0", k_proxy_gemm<LP>, dim3(grid), dim3(64 * W), 0u, st, (const float *)a.y,
                  a.y_stride, a.m_dense, a.b, (const float *)a.v, a.lp, a.t, h);
     return hipGetLastError() == hipSuccess ? CSPD_OK : CSPD_E_DEVICE;

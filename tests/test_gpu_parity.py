@@ -316,20 +316,3 @@ def test_first_scale_duplicate_atoms():
         assert not ({0, 1} <= s) and not ({4, 5} <= s)
 
 
-# --------------------------- reduced-precision proxy with FP32 re-scoring
-@pytest.mark.parametrize("mode", ["bf16", "f16"])
-def test_c3_full_reduced_precision(mode):
-    """Full OMP over 4096 atoms of length 128 (the three-scale workload's
-    finest scale) with a bf16 / fp16 proxy: after FP32 re-scoring of the
-    16-candidate pool the picks match the FP64 oracle's (near-tie rule), the
-    coefficients stay within the FP32 tolerance and every reconstruction
-    within 1e-3 of the oracle's."""
-    w = synth.make("c3", batch=1024)
-    plan = cspd.plan_from_workload(w, corr_mode=mode)
-    out = G.run_full(plan, w)
-    wo = G.with_y(w, out["y64"])
-    sup = parity.gpu_scales(w, out["support"], out["k_used"])
-    rep = parity.compare(wo, sup, out["coef"], out["k_used"], out["xhat"], full=True, tie_tol=1e-6)
-    _say(f"[full c3 {mode} B={w.batch}] {rep.summary()}")
-    rep.check(1e-5, 1e-3, max_mismatch=2)
-    assert rep.xhat_rel_max_mismatched <= 1e-3
