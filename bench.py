@@ -273,7 +273,8 @@ def serve_phase(cspd, jobs=2000, loads=(0.5, 0.8, 0.95), budget=4 << 30, slots=4
     a ring of `ring` job-sized sets, so at most `ring` jobs are outstanding;
     the client waits for the oldest when all are taken); latency = finish -
     submit as the server records it (queueing, admission, PCIe both ways,
-    kernels)."""
+    kernels).  The same burst is also run on device-resident jobs (inputs in
+    HBM, outputs written in place) for the capacity without PCIe."""
     import torch
 
     import synth
@@ -344,11 +345,52 @@ def serve_phase(cspd, jobs=2000, loads=(0.5, 0.8, 0.95), budget=4 << 30, slots=4
         submit(srv, d, i, held, rows)
     collect(srv, held, rows, True)
     cap = float(d["size"].sum()) / (time.perf_counter() - t0)
+    # the same burst with device-resident jobs: inputs already in HBM, outputs
+    # written in place (no PCIe); a ring of `ring` device output sets
+    dev = torch.device("cuda", 0)
+    dev_y = {nm: torch.from_numpy(shapes[nm][2]).to(dev) for nm in SERVE_SHAPES}
+    dev_sets = [{"support": torch.empty(bmax * kmax, dtype=torch.int32, device=dev),
+                 "k_used": torch.empty(bmax, dtype=torch.int32, device=dev),
+                 "coef": torch.empty(bmax * kmax, dtype=torch.float32, device=dev),
+                 "xhat": torch.empty(bmax * nmax, dtype=torch.float32, device=dev)} for _ in range(ring)]
+    dheld = []
+
+    def dev_submit(i):
+        name = SERVE_SHAPES[int(d["shape"][i])]
+        w, plan, _ = shapes[name]
+        n, a = int(d["size"][i]), int(d["start"][i])
+        if not dev_sets:
+            jid, bufs = dheld.pop(0)
+            cspd.cspd_serve_poll(srv, jid, -1)
+            dev_sets.append(bufs)
+        bufs = dev_sets.pop()
+        jid = cspd.cspd_serve_submit_device(
+            srv, plan, dev_y[name][a:a + n], None, None, int(d["k"][i]), w.k_scales[:-1],
+            support=bufs["support"][:n * plan.k_max].view(n, plan.k_max), coef=bufs["coef"][:n * plan.k_max].view(
+                n, plan.k_max), k_used=bufs["k_used"][:n], xhat=bufs["xhat"][:n * plan.n].view(n, plan.n))
+        dheld.append((jid, bufs))
+
+    for i in range(min(6, burst)):      # warm-up of the in-place path
+        dev_submit(i)
+    while dheld:
+        jid, bufs = dheld.pop(0)
+        cspd.cspd_serve_poll(srv, jid, -1)
+        dev_sets.append(bufs)
+    t0 = time.perf_counter()
+    for i in range(burst):
+        dev_submit(i)
+    while dheld:
+        jid, bufs = dheld.pop(0)
+        cspd.cspd_serve_poll(srv, jid, -1)
+        dev_sets.append(bufs)
+    cap_dev = float(d["size"].sum()) / (time.perf_counter() - t0)
+    del dev_y, dev_sets
     mean_size = (bmax + 1 - 1024) / np.log((bmax + 1) / 1024.0)
     out = {"shapes": {n: f"{shapes[n][0].dims} atoms {shapes[n][0].atoms} M {shapes[n][0].m}"
                       for n in SERVE_SHAPES},
            "job_patches": f"log-uniform integer in [1024, {bmax}]", "k_fine": "uniform 6..16 per job",
-           "capacity_patches_per_s": cap, "capacity_burst_jobs": burst, "slots": slots,
+           "capacity_patches_per_s": cap, "capacity_device_buffers_patches_per_s": cap_dev,
+           "capacity_burst_jobs": burst, "slots": slots,
            "client_ring": ring,
            "hbm_budget_bytes": budget, "jobs_per_load": jobs, "loads": {}}
     for load in loads:

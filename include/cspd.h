@@ -367,9 +367,13 @@ cspd_status cspd_ksvd_update(const float *x, int64_t P, int32_t N, float *dict, 
 typedef struct cspd_server_s *cspd_server_t;
 
 /*
- * One reconstruction job.  Inputs and outputs are HOST buffers, read and
- * written by the server's copy engine; they must stay valid until
- * cspd_serve_poll has returned CSPD_OK for the job.
+ * One reconstruction job.  With on_device = 0, inputs and outputs are HOST
+ * buffers, read and written by the server's copy engine; with on_device != 0
+ * they are DEVICE buffers on the server's device, which the launches read
+ * and write in place (no copies; the job's pieces are not packed with other
+ * jobs; per-patch k_fine is then not checked on the host, the kernels clamp
+ * it to [0, k_max]).  Either way they must stay valid until cspd_serve_poll
+ * has returned CSPD_OK for the job.
  *   plan      a resident plan (jobs of several plans may be in flight).
  *   B         patches; y: B x M; mask: B x N or NULL; k_fine: int32[B] or
  *             NULL (then k_fine_uniform); k_scale: int32[S-1] (copied at
@@ -390,6 +394,7 @@ typedef struct cspd_job {
     void *coef;
     int32_t *k_used;
     void *xhat;
+    int32_t on_device;
 } cspd_job;
 
 /* Timestamps (CLOCK_MONOTONIC nanoseconds) of one finished job. */
@@ -401,19 +406,24 @@ typedef struct cspd_job_stats {
     int64_t patches;
     int32_t batched_with; /* most other jobs that shared one of its launches */
     int32_t status;      /* CSPD_OK or the error that failed the job */
+    int64_t server_resident_bytes; /* device bytes the server held when the job finished */
 } cspd_job_stats;
 
 /*
  * Create a server on `device` with an HBM budget for job buffers (bytes,
  * > 0) and at most `max_slots` (1..64) launches in flight, each on its own
  * stream.  Jobs are cut into pieces of at most 65,536 patches.  A
- * background thread admits queued pieces in arrival order when their
- * buffers fit in the budget, packs waiting pieces of the same plan and kind
- * into one launch (at most 65,536 patches), copies in, launches, copies out
- * and retires them; a job finishes with its last piece.  Each slot keeps its
- * device buffers from launch to launch (grown to its largest launch, freed
- * by cspd_serve_destroy); the budget bounds the bytes of launches in
- * flight.
+ * background thread admits queued pieces when their buffers fit in the
+ * budget, packs waiting pieces of the same plan and kind into one launch (at
+ * most 65,536 patches), copies in, launches, copies out and retires them; a
+ * job finishes with its last piece.  Pieces are admitted in arrival order,
+ * except that pieces of small jobs (at most 8,192 patches) go first while the
+ * oldest waiting piece has waited less than 5 ms, and with three or more
+ * slots the last free slot is kept for small jobs.  Each slot keeps its device buffers from
+ * launch to launch (grown to its largest launch); the budget bounds every
+ * byte the server holds on the device: all slots' buffers, in flight or
+ * idle, and an idle slot's buffers are released when a launch would not fit
+ * otherwise.  Everything is freed by cspd_serve_destroy.
  * Errors: E_INVALID, E_DEVICE, E_NOMEM.
  */
 cspd_status cspd_serve_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slots,

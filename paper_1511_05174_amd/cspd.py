@@ -73,6 +73,7 @@ class Job(C.Structure):
         ("coef", C.c_void_p),
         ("k_used", C.c_void_p),
         ("xhat", C.c_void_p),
+        ("on_device", C.c_int32),
     ]
 
 
@@ -94,6 +95,7 @@ class JobStats(C.Structure):
         ("patches", C.c_int64),
         ("batched_with", C.c_int32),
         ("status", C.c_int32),
+        ("server_resident_bytes", C.c_int64),
     ]
 
 
@@ -589,6 +591,40 @@ def cspd_serve_submit(server: Server, plan: Plan, y: np.ndarray, mask: Optional[
     jid = C.c_uint64()
     _check(load().cspd_serve_submit(server.handle, C.byref(j), C.byref(jid)))
     server.pending[jid.value] = (bufs, plan)
+    return jid.value
+
+
+def cspd_serve_submit_device(server: Server, plan: Plan, y, mask=None, k_fine=None, k_fine_uniform: int = 0,
+                             k_scale: Sequence[int] = (), full: bool = False, support=None, coef=None,
+                             k_used=None, xhat=None, want_xhat: bool = True) -> int:
+    """Queue a job whose inputs and outputs are device tensors on the
+    server's device (run in place, no copies); returns its id.  Outputs not
+    passed are allocated here; cspd_serve_poll returns them."""
+    _check_inputs(plan, y, mask, k_fine)
+    B = y.shape[0]
+    support, coef, k_used, xhat = _outputs(plan, B, support, coef, k_used, xhat, want_xhat)
+    j = Job()
+    j.plan = plan.handle
+    j.B = B
+    j.y = y.data_ptr()
+    j.mask = None if mask is None else mask.data_ptr()
+    j.k_fine = None if k_fine is None else k_fine.data_ptr()
+    j.k_fine_uniform = int(k_fine_uniform)
+    for i, v in enumerate(k_scale):
+        j.k_scale[i] = int(v)
+    j.full = 1 if full else 0
+    j.support = support.data_ptr()
+    j.coef = None if coef is None else coef.data_ptr()
+    j.k_used = k_used.data_ptr()
+    j.xhat = None if xhat is None else xhat.data_ptr()
+    j.on_device = 1
+    # the server's streams do not wait for the caller's: finish the inputs first
+    _torch().cuda.synchronize(y.device)
+    jid = C.c_uint64()
+    _check(load().cspd_serve_submit(server.handle, C.byref(j), C.byref(jid)))
+    bufs = {"y": y, "mask": mask, "k_fine": k_fine, "support": support, "coef": coef, "k_used": k_used,
+            "xhat": xhat}
+    server.pending[jid.value] = ({k: v for k, v in bufs.items() if v is not None}, plan)
     return jid.value
 
 

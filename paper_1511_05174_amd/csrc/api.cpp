@@ -407,52 +407,58 @@ const char *cspd_version(void) { return "cspd 0.1 (gfx950)"; }
 
 cspd_status cspd_plan(const cspd_plan_desc *d, cspd_plan_t *out)
 {
-    clear_error();
-    if (!out) return set_error(CSPD_E_INVALID, "out is NULL");
-    *out = nullptr;
-    cspd_status rc = validate_desc(d);
-    if (rc != CSPD_OK) return rc;
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
-        return set_error(CSPD_E_DEVICE, "no HIP device available");
-    if (d->device >= ndev) return set_error(CSPD_E_INVALID, "device %d of %d", d->device, ndev);
-    DeviceGuard g(d->device);
-    if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", d->device);
-    noalloc_setup(d->device);
-    cspd_plan_s *p = new (std::nothrow) cspd_plan_s();
-    if (!p) return set_error(CSPD_E_NOMEM, "host allocation failed");
-    p->s = d->n_scales;
-    p->n = d->dim[d->n_scales - 1];
-    p->m = d->m;
-    p->phi_kind = d->phi_kind;
-    p->dtype = d->dtype;
-    p->corr_mode = d->corr_mode;
-    p->rescore_m = d->rescore_m ? d->rescore_m : 8;
-    p->k_max = d->k_max;
-    p->n_phases = d->n_phases > 1 ? d->n_phases : 1;
-    p->device = d->device;
-    hipStream_t st;
-    if (hipStreamCreate(&st) != hipSuccess) {
-        free_plan(p);
-        return set_error(CSPD_E_DEVICE, "hipStreamCreate failed");
-    }
-    rc = plan_effective(p, d, st);
-    (void)hipStreamSynchronize(st);
-    (void)hipStreamDestroy(st);
-    if (rc != CSPD_OK) {
-        free_plan(p);
-        return rc;
-    }
-    *out = p;
-    return CSPD_OK;
+    return guarded([&]() -> cspd_status {
+        clear_error();
+        if (!out) return set_error(CSPD_E_INVALID, "out is NULL");
+        *out = nullptr;
+        cspd_status rc = validate_desc(d);
+        if (rc != CSPD_OK) return rc;
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+            return set_error(CSPD_E_DEVICE, "no HIP device available");
+        if (d->device >= ndev) return set_error(CSPD_E_INVALID, "device %d of %d", d->device, ndev);
+        DeviceGuard g(d->device);
+        if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", d->device);
+        noalloc_setup(d->device);
+        cspd_plan_s *p = new (std::nothrow) cspd_plan_s();
+        if (!p) return set_error(CSPD_E_NOMEM, "host allocation failed");
+        p->s = d->n_scales;
+        p->n = d->dim[d->n_scales - 1];
+        p->m = d->m;
+        p->phi_kind = d->phi_kind;
+        p->dtype = d->dtype;
+        p->corr_mode = d->corr_mode;
+        p->rescore_m = d->rescore_m ? d->rescore_m : 8;
+        p->k_max = d->k_max;
+        p->n_phases = d->n_phases > 1 ? d->n_phases : 1;
+        p->device = d->device;
+        hipStream_t st;
+        if (hipStreamCreate(&st) != hipSuccess) {
+            free_plan(p);
+            return set_error(CSPD_E_DEVICE, "hipStreamCreate failed");
+        }
+        rc = plan_effective(p, d, st);
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+        if (rc != CSPD_OK) {
+            free_plan(p);
+            return rc;
+        }
+        *out = p;
+        return CSPD_OK;
+    });
 }
 
 void cspd_plan_destroy(cspd_plan_t p)
 {
-    if (!p) return;
-    DeviceGuard g(p->device);
-    (void)hipDeviceSynchronize();
-    free_plan(p);
+    try {
+        if (!p) return;
+        DeviceGuard g(p->device);
+        (void)hipDeviceSynchronize();
+        free_plan(p);
+    } catch (...) {
+        // nothing may cross the C ABI; the object is left as it is
+    }
 }
 
 int64_t cspd_plan_device_bytes(cspd_plan_t p) { return p ? p->bytes : 0; }
@@ -548,11 +554,13 @@ cspd_status cspd_omp_full(cspd_plan_t p, int64_t B, const void *y, const uint8_t
                           const int32_t *k, int32_t k_uniform, int32_t *support, void *coef,
                           int32_t *k_used, void *xhat, void *hip_stream)
 {
-    clear_error();
-    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
-    if (p->n_phases > 1 && B > 0)
-        return set_error(CSPD_E_INVALID, "plan has %d operators: use cspd_omp_cross_scale_phased", p->n_phases);
-    return full_on(p, B, nullptr, y, mask, k, k_uniform, support, coef, k_used, xhat, (hipStream_t)hip_stream);
+    return guarded([&]() -> cspd_status {
+        clear_error();
+        if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+        if (p->n_phases > 1 && B > 0)
+            return set_error(CSPD_E_INVALID, "plan has %d operators: use cspd_omp_cross_scale_phased", p->n_phases);
+        return full_on(p, B, nullptr, y, mask, k, k_uniform, support, coef, k_used, xhat, (hipStream_t)hip_stream);
+    });
 }
 
 cspd_status cspd_omp_cross_scale_phased(cspd_plan_t p, int64_t B, const int32_t *phase, const void *y,
@@ -560,12 +568,14 @@ cspd_status cspd_omp_cross_scale_phased(cspd_plan_t p, int64_t B, const int32_t 
                                         int32_t k_fine_uniform, int32_t *support, void *coef, int32_t *k_used,
                                         void *xhat, int32_t *support_coarse, void *hip_stream)
 {
-    clear_error();
-    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
-    if (p->n_phases > 1 && !phase && B > 0)
-        return set_error(CSPD_E_INVALID, "plan has %d operators and phase is NULL", p->n_phases);
-    return cross_impl(p, B, phase, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat,
-                      support_coarse, (hipStream_t)hip_stream);
+    return guarded([&]() -> cspd_status {
+        clear_error();
+        if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+        if (p->n_phases > 1 && !phase && B > 0)
+            return set_error(CSPD_E_INVALID, "plan has %d operators and phase is NULL", p->n_phases);
+        return cross_impl(p, B, phase, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat,
+                          support_coarse, (hipStream_t)hip_stream);
+    });
 }
 
 cspd_status cspd_omp_cross_scale(cspd_plan_t p, int64_t B, const void *y, const uint8_t *mask,
@@ -574,12 +584,14 @@ cspd_status cspd_omp_cross_scale(cspd_plan_t p, int64_t B, const void *y, const 
                                  int32_t *k_used, void *xhat, int32_t *support_coarse,
                                  void *hip_stream)
 {
-    clear_error();
-    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
-    if (p->n_phases > 1 && B > 0)
-        return set_error(CSPD_E_INVALID, "plan has %d operators: use cspd_omp_cross_scale_phased", p->n_phases);
-    return cross_impl(p, B, nullptr, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat,
-                      support_coarse, (hipStream_t)hip_stream);
+    return guarded([&]() -> cspd_status {
+        clear_error();
+        if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+        if (p->n_phases > 1 && B > 0)
+            return set_error(CSPD_E_INVALID, "plan has %d operators: use cspd_omp_cross_scale_phased", p->n_phases);
+        return cross_impl(p, B, nullptr, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat,
+                          support_coarse, (hipStream_t)hip_stream);
+    });
 }
 
 cspd_status cspd_graph_cross_scale(cspd_plan_t p, int64_t B, const void *y, const uint8_t *mask,
@@ -588,211 +600,225 @@ cspd_status cspd_graph_cross_scale(cspd_plan_t p, int64_t B, const void *y, cons
                                    int32_t *k_used, void *xhat, int32_t *support_coarse,
                                    cspd_graph_t *out)
 {
-    clear_error();
-    if (!out) return set_error(CSPD_E_INVALID, "out is NULL");
-    *out = nullptr;
-    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
-    if (B <= 0) return set_error(CSPD_E_INVALID, "B = %lld (a graph needs patches)", (long long)B);
-    if (p->n_phases > 1)
-        return set_error(CSPD_E_INVALID, "plan has %d operators: only cspd_omp_cross_scale_phased runs it", p->n_phases);
-    CrossCall c;
-    if (p->s > 1) {
-        const cspd_status rc = prepare_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef,
-                                             k_used, c);
-        if (rc != CSPD_OK) return rc;
-    }
-    DeviceGuard g(p->device);
-    if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
-    cspd_graph_s *gr = new (std::nothrow) cspd_graph_s();
-    if (!gr) return set_error(CSPD_E_NOMEM, "host allocation failed");
-    gr->device = p->device;
-    auto fail = [&](cspd_status code, const char *what) {
-        cspd_graph_destroy(gr);
-        return set_error(code, "%s", what);
-    };
-    const size_t wbytes = p->s > 1 ? cross_workspace_bytes(p, B, c.ksum, support_coarse != nullptr) : 0;
-    if (wbytes && hipMalloc(&gr->work, wbytes) != hipSuccess) return fail(CSPD_E_NOMEM, "graph workspace");
-    if (hipStreamCreateWithFlags(&gr->capture, hipStreamNonBlocking) != hipSuccess)
-        return fail(CSPD_E_DEVICE, "capture stream");
-    if (hipStreamBeginCapture(gr->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return fail(CSPD_E_DEVICE, "hipStreamBeginCapture failed");
-    cspd_status rc;
-    {
-        ProfileSuspend quiet;
-        if (p->s == 1)
-            rc = cspd_omp_full(p, B, y, mask, k_fine, k_fine_uniform, support, coef, k_used, xhat, gr->capture);
-        else
-            rc = run_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat,
-                           support_coarse, (int32_t *)gr->work, c, gr->capture);
-    }
-    hipGraph_t graph = nullptr;
-    const hipError_t ce = hipStreamEndCapture(gr->capture, &graph);
-    gr->graph = graph;
-    if (rc != CSPD_OK) {
-        char msg[sizeof(cspd::g_err)];
-        std::memcpy(msg, cspd::g_err, sizeof(msg));
-        cspd_graph_destroy(gr);
-        return set_error(rc, "%s", msg);
-    }
-    if (ce != hipSuccess || !graph) return fail(CSPD_E_DEVICE, "hipStreamEndCapture failed");
-    if (hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) != hipSuccess)
-        return fail(CSPD_E_DEVICE, "hipGraphInstantiate failed");
-    *out = gr;
-    return CSPD_OK;
+    return guarded([&]() -> cspd_status {
+        clear_error();
+        if (!out) return set_error(CSPD_E_INVALID, "out is NULL");
+        *out = nullptr;
+        if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+        if (B <= 0) return set_error(CSPD_E_INVALID, "B = %lld (a graph needs patches)", (long long)B);
+        if (p->n_phases > 1)
+            return set_error(CSPD_E_INVALID, "plan has %d operators: only cspd_omp_cross_scale_phased runs it", p->n_phases);
+        CrossCall c;
+        if (p->s > 1) {
+            const cspd_status rc = prepare_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef,
+                                                 k_used, c);
+            if (rc != CSPD_OK) return rc;
+        }
+        DeviceGuard g(p->device);
+        if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
+        cspd_graph_s *gr = new (std::nothrow) cspd_graph_s();
+        if (!gr) return set_error(CSPD_E_NOMEM, "host allocation failed");
+        gr->device = p->device;
+        auto fail = [&](cspd_status code, const char *what) {
+            cspd_graph_destroy(gr);
+            return set_error(code, "%s", what);
+        };
+        const size_t wbytes = p->s > 1 ? cross_workspace_bytes(p, B, c.ksum, support_coarse != nullptr) : 0;
+        if (wbytes && hipMalloc(&gr->work, wbytes) != hipSuccess) return fail(CSPD_E_NOMEM, "graph workspace");
+        if (hipStreamCreateWithFlags(&gr->capture, hipStreamNonBlocking) != hipSuccess)
+            return fail(CSPD_E_DEVICE, "capture stream");
+        if (hipStreamBeginCapture(gr->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(CSPD_E_DEVICE, "hipStreamBeginCapture failed");
+        cspd_status rc;
+        {
+            ProfileSuspend quiet;
+            if (p->s == 1)
+                rc = cspd_omp_full(p, B, y, mask, k_fine, k_fine_uniform, support, coef, k_used, xhat, gr->capture);
+            else
+                rc = run_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat,
+                               support_coarse, (int32_t *)gr->work, c, gr->capture);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t ce = hipStreamEndCapture(gr->capture, &graph);
+        gr->graph = graph;
+        if (rc != CSPD_OK) {
+            char msg[sizeof(cspd::g_err)];
+            std::memcpy(msg, cspd::g_err, sizeof(msg));
+            cspd_graph_destroy(gr);
+            return set_error(rc, "%s", msg);
+        }
+        if (ce != hipSuccess || !graph) return fail(CSPD_E_DEVICE, "hipStreamEndCapture failed");
+        if (hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+            return fail(CSPD_E_DEVICE, "hipGraphInstantiate failed");
+        *out = gr;
+        return CSPD_OK;
+    });
 }
 
 cspd_status cspd_graph_launch(cspd_graph_t gr, void *hip_stream)
 {
-    clear_error();
-    if (!gr || !gr->exec) return set_error(CSPD_E_INVALID, "graph is NULL");
-    DeviceGuard g(gr->device);
-    if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", gr->device);
-    CSPD_HIP_CHECK(hipGraphLaunch(gr->exec, (hipStream_t)hip_stream));
-    return CSPD_OK;
+    return guarded([&]() -> cspd_status {
+        clear_error();
+        if (!gr || !gr->exec) return set_error(CSPD_E_INVALID, "graph is NULL");
+        DeviceGuard g(gr->device);
+        if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", gr->device);
+        CSPD_HIP_CHECK(hipGraphLaunch(gr->exec, (hipStream_t)hip_stream));
+        return CSPD_OK;
+    });
 }
 
 void cspd_graph_destroy(cspd_graph_t gr)
 {
-    if (!gr) return;
-    DeviceGuard g(gr->device);
-    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
-    if (gr->graph) (void)hipGraphDestroy(gr->graph);
-    if (gr->capture) {
-        (void)hipStreamSynchronize(gr->capture);
-        (void)hipStreamDestroy(gr->capture);
+    try {
+        if (!gr) return;
+        DeviceGuard g(gr->device);
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        if (gr->capture) {
+            (void)hipStreamSynchronize(gr->capture);
+            (void)hipStreamDestroy(gr->capture);
+        }
+        if (gr->work) {
+            (void)hipDeviceSynchronize();   // no replay may still read the workspace
+            (void)hipFree(gr->work);
+        }
+        delete gr;
+    } catch (...) {
+        // nothing may cross the C ABI; the object is left as it is
     }
-    if (gr->work) {
-        (void)hipDeviceSynchronize();   // no replay may still read the workspace
-        (void)hipFree(gr->work);
-    }
-    delete gr;
 }
 
 cspd_status cspd_autotune(cspd_plan_t p, int64_t B, const void *y, const uint8_t *mask,
                           const int32_t *k_scale, const int32_t *k_fine, int32_t k_fine_uniform,
                           int32_t reps, void *hip_stream)
 {
-    clear_error();
-    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
-    if (reps < 1 || reps > 1000) return set_error(CSPD_E_INVALID, "reps %d outside 1..1000", reps);
-    if (p->s < 2 || p->dtype != CSPD_F32 || B == 0 || p->n_phases > 1) return CSPD_OK;   // nothing to choose
-    CrossCall c;
-    int32_t dummy = 0;
-    cspd_status rc = prepare_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, &dummy, &dummy, &dummy, c);
-    if (rc != CSPD_OK) return rc;
-    DeviceGuard g(p->device);
-    if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
-    hipStream_t st = (hipStream_t)hip_stream;
-    ProfileSuspend quiet;
-    // scratch outputs and workspace for the timing runs
-    int32_t *work = nullptr, *sup = nullptr, *ku = nullptr;
-    void *coef = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    auto cleanup = [&]() {
-        (void)hipStreamSynchronize(st);
-        if (work) (void)hipFree(work);
-        if (sup) (void)hipFree(sup);
-        if (ku) (void)hipFree(ku);
-        if (coef) (void)hipFree(coef);
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
-    };
-    const size_t wbytes = cross_workspace_bytes(p, B, c.ksum, false);
-    if (hipMalloc((void **)&work, wbytes) != hipSuccess || hipMalloc((void **)&sup, sizeof(int32_t) * B * p->k_max) != hipSuccess ||
-        hipMalloc((void **)&ku, sizeof(int32_t) * B) != hipSuccess ||
-        hipMalloc(&coef, sizeof(float) * B * p->k_max) != hipSuccess) {
-        cleanup();
-        return set_error(CSPD_E_NOMEM, "autotune scratch for %lld patches", (long long)B);
-    }
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        cleanup();
-        return set_error(CSPD_E_DEVICE, "hipEventCreate failed");
-    }
-    // one call with the current choices leaves every coarse support in place
-    rc = run_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, sup, coef, ku, nullptr, nullptr, work, c, st);
-    if (rc != CSPD_OK) { cleanup(); return rc; }
-    const int64_t nk = B * (p->s - 1);
-    for (int s = 0; s < p->s; ++s) {
-        ScaleArgs a = cross_scale_args(p, s, B, y, mask, k_scale, k_fine, k_fine_uniform, sup, coef, ku, nullptr,
-                                       work + nk, work, c.ksum);
-        if (s == 0 && first_gemm_path(p)) {
-            a.hpre = (char *)work + hpre_offset(p, B, c.ksum, false);
-            a.nu2 = p->sc[0].nu2;
+    return guarded([&]() -> cspd_status {
+        clear_error();
+        if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+        if (reps < 1 || reps > 1000) return set_error(CSPD_E_INVALID, "reps %d outside 1..1000", reps);
+        if (p->s < 2 || p->dtype != CSPD_F32 || B == 0 || p->n_phases > 1) return CSPD_OK;   // nothing to choose
+        CrossCall c;
+        int32_t dummy = 0;
+        cspd_status rc = prepare_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, &dummy, &dummy, &dummy, c);
+        if (rc != CSPD_OK) return rc;
+        DeviceGuard g(p->device);
+        if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", p->device);
+        hipStream_t st = (hipStream_t)hip_stream;
+        ProfileSuspend quiet;
+        // scratch outputs and workspace for the timing runs
+        int32_t *work = nullptr, *sup = nullptr, *ku = nullptr;
+        void *coef = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        auto cleanup = [&]() {
+            (void)hipStreamSynchronize(st);
+            if (work) (void)hipFree(work);
+            if (sup) (void)hipFree(sup);
+            if (ku) (void)hipFree(ku);
+            if (coef) (void)hipFree(coef);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        };
+        const size_t wbytes = cross_workspace_bytes(p, B, c.ksum, false);
+        if (hipMalloc((void **)&work, wbytes) != hipSuccess || hipMalloc((void **)&sup, sizeof(int32_t) * B * p->k_max) != hipSuccess ||
+            hipMalloc((void **)&ku, sizeof(int32_t) * B) != hipSuccess ||
+            hipMalloc(&coef, sizeof(float) * B * p->k_max) != hipSuccess) {
+            cleanup();
+            return set_error(CSPD_E_NOMEM, "autotune scratch for %lld patches", (long long)B);
         }
-        KernelChoice ch[24];
-        const int nch = scale_choices(p->dtype, a, c.cand[s], p->sc[s].gram != nullptr, ch, 24);
-        float best_ms = 0.f;
-        int best = -1;
-        for (int i = 0; i < nch; ++i) {
-            if (launch_choice(p->dtype, a, ch[i], st) != CSPD_OK) { clear_error(); continue; }
-            (void)hipEventRecord(e0, st);
-            bool ok = true;
-            for (int r = 0; r < reps && ok; ++r) ok = launch_choice(p->dtype, a, ch[i], st) == CSPD_OK;
-            (void)hipEventRecord(e1, st);
-            float ms = 0.f;
-            if (!ok || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                clear_error();
-                continue;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            cleanup();
+            return set_error(CSPD_E_DEVICE, "hipEventCreate failed");
+        }
+        // one call with the current choices leaves every coarse support in place
+        rc = run_cross(p, B, y, mask, k_scale, k_fine, k_fine_uniform, sup, coef, ku, nullptr, nullptr, work, c, st);
+        if (rc != CSPD_OK) { cleanup(); return rc; }
+        const int64_t nk = B * (p->s - 1);
+        for (int s = 0; s < p->s; ++s) {
+            ScaleArgs a = cross_scale_args(p, s, B, y, mask, k_scale, k_fine, k_fine_uniform, sup, coef, ku, nullptr,
+                                           work + nk, work, c.ksum);
+            if (s == 0 && first_gemm_path(p)) {
+                a.hpre = (char *)work + hpre_offset(p, B, c.ksum, false);
+                a.nu2 = p->sc[0].nu2;
             }
-            if (best < 0 || ms < best_ms) { best_ms = ms; best = i; }
+            KernelChoice ch[24];
+            const int nch = scale_choices(p->dtype, a, c.cand[s], p->sc[s].gram != nullptr, ch, 24);
+            float best_ms = 0.f;
+            int best = -1;
+            for (int i = 0; i < nch; ++i) {
+                if (launch_choice(p->dtype, a, ch[i], st) != CSPD_OK) { clear_error(); continue; }
+                (void)hipEventRecord(e0, st);
+                bool ok = true;
+                for (int r = 0; r < reps && ok; ++r) ok = launch_choice(p->dtype, a, ch[i], st) == CSPD_OK;
+                (void)hipEventRecord(e1, st);
+                float ms = 0.f;
+                if (!ok || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    clear_error();
+                    continue;
+                }
+                if (best < 0 || ms < best_ms) { best_ms = ms; best = i; }
+            }
+            if (best >= 0) {
+                ch[best].cand = c.cand[s];
+                std::lock_guard<std::mutex> lk(p->mu);
+                p->tuned[s][k_bucket(a)] = ch[best];
+            }
         }
-        if (best >= 0) {
-            ch[best].cand = c.cand[s];
-            std::lock_guard<std::mutex> lk(p->mu);
-            p->tuned[s][k_bucket(a)] = ch[best];
-        }
-    }
-    cleanup();
-    return CSPD_OK;
+        cleanup();
+        return CSPD_OK;
+    });
 }
 
 cspd_status cspd_tuned_kernel(cspd_plan_t p, int32_t scale, int32_t k_bucket_, int32_t *kind, int32_t *nc,
                               int32_t *ppw, int32_t *cand)
 {
-    clear_error();
-    if (!p || !kind || !nc || !ppw || !cand) return set_error(CSPD_E_INVALID, "NULL argument");
-    if (scale < 0 || scale >= p->s || k_bucket_ < 0 || k_bucket_ > 2)
-        return set_error(CSPD_E_INVALID, "scale %d / bucket %d out of range", scale, k_bucket_);
-    std::lock_guard<std::mutex> lk(p->mu);
-    const KernelChoice &c = p->tuned[scale][k_bucket_];
-    *kind = c.kind;
-    *nc = c.nc;
-    *ppw = c.ppw;
-    *cand = c.cand;
-    return CSPD_OK;
+    return guarded([&]() -> cspd_status {
+        clear_error();
+        if (!p || !kind || !nc || !ppw || !cand) return set_error(CSPD_E_INVALID, "NULL argument");
+        if (scale < 0 || scale >= p->s || k_bucket_ < 0 || k_bucket_ > 2)
+            return set_error(CSPD_E_INVALID, "scale %d / bucket %d out of range", scale, k_bucket_);
+        std::lock_guard<std::mutex> lk(p->mu);
+        const KernelChoice &c = p->tuned[scale][k_bucket_];
+        *kind = c.kind;
+        *nc = c.nc;
+        *ppw = c.ppw;
+        *cand = c.cand;
+        return CSPD_OK;
+    });
 }
 
 cspd_status cspd_set_tuned_kernel(cspd_plan_t p, int32_t scale, int32_t k_bucket_, int32_t kind, int32_t nc,
                                   int32_t ppw, int32_t cand)
 {
-    clear_error();
-    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
-    if (scale < 0 || scale >= p->s || k_bucket_ < 0 || k_bucket_ > 2)
-        return set_error(CSPD_E_INVALID, "scale %d / bucket %d out of range", scale, k_bucket_);
-    KernelChoice c;
-    if (kind != kChoiceAuto) {
-        if (cand < 1 || cand > p->sc[scale].t)
-            return set_error(CSPD_E_INVALID, "cand %d outside [1, T = %d]", cand, p->sc[scale].t);
-        // the variants that can run this scale at this candidate count
-        ScaleArgs a = base_args(p, scale, 1, nullptr, nullptr);
-        a.first = scale == 0;
-        a.last = scale + 1 == p->s;
-        a.kvec = nullptr;
-        a.kuni = a.sup_count = 4 << k_bucket_;   // largest K of the bucket
-        KernelChoice ch[24];
-        const int nch = scale_choices(p->dtype, a, cand, p->sc[scale].gram != nullptr, ch, 24);
-        int hit = -1;
-        for (int i = 0; i < nch && hit < 0; ++i)
-            if (ch[i].kind == kind && (kind == kChoiceFirstMfma || (ch[i].nc == nc && ch[i].ppw == ppw))) hit = i;
-        if (hit < 0)
-            return set_error(CSPD_E_UNSUPPORTED, "scale %d: no kernel kind %d (nc %d, ppw %d) for %d candidates",
-                             scale, kind, nc, ppw, cand);
-        c = ch[hit];
-        c.cand = cand;
-    }
-    std::lock_guard<std::mutex> lk(p->mu);
-    p->tuned[scale][k_bucket_] = c;
-    return CSPD_OK;
+    return guarded([&]() -> cspd_status {
+        clear_error();
+        if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+        if (scale < 0 || scale >= p->s || k_bucket_ < 0 || k_bucket_ > 2)
+            return set_error(CSPD_E_INVALID, "scale %d / bucket %d out of range", scale, k_bucket_);
+        KernelChoice c;
+        if (kind != kChoiceAuto) {
+            if (cand < 1 || cand > p->sc[scale].t)
+                return set_error(CSPD_E_INVALID, "cand %d outside [1, T = %d]", cand, p->sc[scale].t);
+            // the variants that can run this scale at this candidate count
+            ScaleArgs a = base_args(p, scale, 1, nullptr, nullptr);
+            a.first = scale == 0;
+            a.last = scale + 1 == p->s;
+            a.kvec = nullptr;
+            a.kuni = a.sup_count = 4 << k_bucket_;   // largest K of the bucket
+            KernelChoice ch[24];
+            const int nch = scale_choices(p->dtype, a, cand, p->sc[scale].gram != nullptr, ch, 24);
+            int hit = -1;
+            for (int i = 0; i < nch && hit < 0; ++i)
+                if (ch[i].kind == kind && (kind == kChoiceFirstMfma || (ch[i].nc == nc && ch[i].ppw == ppw))) hit = i;
+            if (hit < 0)
+                return set_error(CSPD_E_UNSUPPORTED, "scale %d: no kernel kind %d (nc %d, ppw %d) for %d candidates",
+                                 scale, kind, nc, ppw, cand);
+            c = ch[hit];
+            c.cand = cand;
+        }
+        std::lock_guard<std::mutex> lk(p->mu);
+        p->tuned[scale][k_bucket_] = c;
+        return CSPD_OK;
+    });
 }
 
 }  // extern "C"

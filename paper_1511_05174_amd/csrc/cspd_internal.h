@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <mutex>
 #include <string>
 
@@ -26,6 +28,23 @@ constexpr int kMaxLongCand = 1024;
 constexpr int kWavesPerBlock = 4;
 
 cspd_status set_error(cspd_status code, const char *fmt, ...);
+
+// Runs an entry point's body and turns any C++ exception into a status (and
+// the thread's error message), so that nothing thrown inside the library
+// crosses the C ABI.
+template <typename F>
+cspd_status guarded(F &&body) noexcept
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return set_error(CSPD_E_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return set_error(CSPD_E_DEVICE, "C++ exception: %s", e.what());
+    } catch (...) {
+        return set_error(CSPD_E_DEVICE, "unknown C++ exception");
+    }
+}
 void clear_error();
 bool has_error();
 // Resolves this device's address of the no-allocation entry point's static

@@ -261,74 +261,76 @@ extern "C" {
 cspd_status cspd_ksvd_update(const float *x, int64_t p, int32_t n, float *dict, int32_t t_atoms,
                              const int32_t *support, float *coef, int32_t kstride, void *hip_stream)
 {
-    clear_error();
-    if (p < 0 || n < 1 || n > NMAX || t_atoms < 1 || kstride < 1)
-        return set_error(CSPD_E_SHAPE, "P %lld, N %d (1..%d), T %d, kstride %d", (long long)p, n, NMAX, t_atoms,
-                         kstride);
-    if (p * (int64_t)kstride >= ((int64_t)1 << 31) || p * (int64_t)n >= ((int64_t)1 << 40))
-        return set_error(CSPD_E_SHAPE, "too many signals");
-    if (p == 0) return CSPD_OK;
-    if (!x || !dict || !support || !coef) return set_error(CSPD_E_INVALID, "NULL pointer");
-    hipStream_t st = (hipStream_t)hip_stream;
-    const int64_t entries = p * kstride;
-    // workspace: residual, keys / values twice, counts, offsets, sort and scan storage
-    size_t sort_bytes = 0, scan_bytes = 0;
-    int *dummy = nullptr;
-    int bits = 1;
-    while ((1 << bits) <= t_atoms) ++bits;
-    if (hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, dummy, dummy, dummy, dummy, (int)entries, 0, bits,
-                                           st) != hipSuccess ||
-        hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, dummy, dummy, t_atoms, st) != hipSuccess)
-        return set_error(CSPD_E_DEVICE, "temporary storage query failed");
-    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    const size_t o_r = 0;
-    const size_t o_k0 = o_r + al(sizeof(float) * (size_t)(p * n));
-    const size_t o_v0 = o_k0 + al(sizeof(int) * (size_t)entries);
-    const size_t o_k1 = o_v0 + al(sizeof(int) * (size_t)entries);
-    const size_t o_v1 = o_k1 + al(sizeof(int) * (size_t)entries);
-    const size_t o_cnt = o_v1 + al(sizeof(int) * (size_t)entries);
-    const size_t o_off = o_cnt + al(sizeof(int) * (size_t)t_atoms);
-    const size_t o_part = o_off + al(sizeof(int) * (size_t)t_atoms);
-    const size_t o_tab = o_part + al(sizeof(double) * (size_t)PG * NUT);
-    const size_t o_dold = o_tab + al(sizeof(int) * (size_t)NUT);
-    const size_t o_tmp = o_dold + al(sizeof(float) * (size_t)NMAX);
-    const size_t total = o_tmp + al(sort_bytes > scan_bytes ? sort_bytes : scan_bytes);
-    char *ws = nullptr;
-    if (hipMallocAsync((void **)&ws, total, st) != hipSuccess) return set_error(CSPD_E_NOMEM, "workspace");
-    float *r = (float *)(ws + o_r);
-    int *k0 = (int *)(ws + o_k0), *v0 = (int *)(ws + o_v0), *k1 = (int *)(ws + o_k1), *v1 = (int *)(ws + o_v1);
-    int *cnt = (int *)(ws + o_cnt), *off = (int *)(ws + o_off);
-    void *tmp = ws + o_tmp;
-    double *part = (double *)(ws + o_part);
-    int *tab = (int *)(ws + o_tab);
-    float *dold = (float *)(ws + o_dold);
-    cspd_status rc = CSPD_OK;
-    ProfileToken *tok = profile_begin("ksvd_update", st);
-    const int bs = 256;
-    hipLaunchKernelGGL(k_residual, dim3((unsigned)((p * n + bs - 1) / bs)), dim3(bs), 0, st, x, dict, support, coef,
-                       kstride, p, n, r);
-    // counts start at zero: a fill kernel rather than a memset (graph-safe)
-    hipLaunchKernelGGL(k_fill_zero_i32, dim3((unsigned)((t_atoms + bs - 1) / bs)), dim3(bs), 0, st, cnt, t_atoms);
-    hipLaunchKernelGGL(k_keys, dim3((unsigned)((entries + bs - 1) / bs)), dim3(bs), 0, st, support, entries,
-                       t_atoms, k0, v0, cnt);
-    size_t sb = sort_bytes, cb = scan_bytes;
-    if (hipcub::DeviceRadixSort::SortPairs(tmp, sb, k0, k1, v0, v1, (int)entries, 0, bits, st) != hipSuccess ||
-        hipcub::DeviceScan::ExclusiveSum(tmp, cb, cnt, off, t_atoms, st) != hipSuccess)
-        rc = set_error(CSPD_E_DEVICE, "sort / scan failed");
-    if (rc == CSPD_OK) {
-        hipLaunchKernelGGL(k_tri_table, dim3(1), dim3(NMAX), 0, st, n, tab);
-        for (int k = 0; k < t_atoms; ++k) {
-            hipLaunchKernelGGL(k_atom_gram, dim3(PG), dim3(BS), 0, st, k, n, kstride, off, cnt, v1, dict, coef, r,
-                               tab, part);
-            hipLaunchKernelGGL(k_atom, dim3(1), dim3(BS), 0, st, k, n, cnt, dict, dold, part, tab, 2000, 1e-12);
-            hipLaunchKernelGGL(k_atom_users, dim3(PG), dim3(BS), 0, st, k, n, kstride, off, cnt, v1, dict, dold,
-                               coef, r);
+    return guarded([&]() -> cspd_status {
+        clear_error();
+        if (p < 0 || n < 1 || n > NMAX || t_atoms < 1 || kstride < 1)
+            return set_error(CSPD_E_SHAPE, "P %lld, N %d (1..%d), T %d, kstride %d", (long long)p, n, NMAX, t_atoms,
+                             kstride);
+        if (p * (int64_t)kstride >= ((int64_t)1 << 31) || p * (int64_t)n >= ((int64_t)1 << 40))
+            return set_error(CSPD_E_SHAPE, "too many signals");
+        if (p == 0) return CSPD_OK;
+        if (!x || !dict || !support || !coef) return set_error(CSPD_E_INVALID, "NULL pointer");
+        hipStream_t st = (hipStream_t)hip_stream;
+        const int64_t entries = p * kstride;
+        // workspace: residual, keys / values twice, counts, offsets, sort and scan storage
+        size_t sort_bytes = 0, scan_bytes = 0;
+        int *dummy = nullptr;
+        int bits = 1;
+        while ((1 << bits) <= t_atoms) ++bits;
+        if (hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, dummy, dummy, dummy, dummy, (int)entries, 0, bits,
+                                               st) != hipSuccess ||
+            hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, dummy, dummy, t_atoms, st) != hipSuccess)
+            return set_error(CSPD_E_DEVICE, "temporary storage query failed");
+        auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+        const size_t o_r = 0;
+        const size_t o_k0 = o_r + al(sizeof(float) * (size_t)(p * n));
+        const size_t o_v0 = o_k0 + al(sizeof(int) * (size_t)entries);
+        const size_t o_k1 = o_v0 + al(sizeof(int) * (size_t)entries);
+        const size_t o_v1 = o_k1 + al(sizeof(int) * (size_t)entries);
+        const size_t o_cnt = o_v1 + al(sizeof(int) * (size_t)entries);
+        const size_t o_off = o_cnt + al(sizeof(int) * (size_t)t_atoms);
+        const size_t o_part = o_off + al(sizeof(int) * (size_t)t_atoms);
+        const size_t o_tab = o_part + al(sizeof(double) * (size_t)PG * NUT);
+        const size_t o_dold = o_tab + al(sizeof(int) * (size_t)NUT);
+        const size_t o_tmp = o_dold + al(sizeof(float) * (size_t)NMAX);
+        const size_t total = o_tmp + al(sort_bytes > scan_bytes ? sort_bytes : scan_bytes);
+        char *ws = nullptr;
+        if (hipMallocAsync((void **)&ws, total, st) != hipSuccess) return set_error(CSPD_E_NOMEM, "workspace");
+        float *r = (float *)(ws + o_r);
+        int *k0 = (int *)(ws + o_k0), *v0 = (int *)(ws + o_v0), *k1 = (int *)(ws + o_k1), *v1 = (int *)(ws + o_v1);
+        int *cnt = (int *)(ws + o_cnt), *off = (int *)(ws + o_off);
+        void *tmp = ws + o_tmp;
+        double *part = (double *)(ws + o_part);
+        int *tab = (int *)(ws + o_tab);
+        float *dold = (float *)(ws + o_dold);
+        cspd_status rc = CSPD_OK;
+        ProfileToken *tok = profile_begin("ksvd_update", st);
+        const int bs = 256;
+        hipLaunchKernelGGL(k_residual, dim3((unsigned)((p * n + bs - 1) / bs)), dim3(bs), 0, st, x, dict, support, coef,
+                           kstride, p, n, r);
+        // counts start at zero: a fill kernel rather than a memset (graph-safe)
+        hipLaunchKernelGGL(k_fill_zero_i32, dim3((unsigned)((t_atoms + bs - 1) / bs)), dim3(bs), 0, st, cnt, t_atoms);
+        hipLaunchKernelGGL(k_keys, dim3((unsigned)((entries + bs - 1) / bs)), dim3(bs), 0, st, support, entries,
+                           t_atoms, k0, v0, cnt);
+        size_t sb = sort_bytes, cb = scan_bytes;
+        if (hipcub::DeviceRadixSort::SortPairs(tmp, sb, k0, k1, v0, v1, (int)entries, 0, bits, st) != hipSuccess ||
+            hipcub::DeviceScan::ExclusiveSum(tmp, cb, cnt, off, t_atoms, st) != hipSuccess)
+            rc = set_error(CSPD_E_DEVICE, "sort / scan failed");
+        if (rc == CSPD_OK) {
+            hipLaunchKernelGGL(k_tri_table, dim3(1), dim3(NMAX), 0, st, n, tab);
+            for (int k = 0; k < t_atoms; ++k) {
+                hipLaunchKernelGGL(k_atom_gram, dim3(PG), dim3(BS), 0, st, k, n, kstride, off, cnt, v1, dict, coef, r,
+                                   tab, part);
+                hipLaunchKernelGGL(k_atom, dim3(1), dim3(BS), 0, st, k, n, cnt, dict, dold, part, tab, 2000, 1e-12);
+                hipLaunchKernelGGL(k_atom_users, dim3(PG), dim3(BS), 0, st, k, n, kstride, off, cnt, v1, dict, dold,
+                                   coef, r);
+            }
+            if (hipGetLastError() != hipSuccess) rc = set_error(CSPD_E_DEVICE, "atom update launch failed");
         }
-        if (hipGetLastError() != hipSuccess) rc = set_error(CSPD_E_DEVICE, "atom update launch failed");
-    }
-    profile_end(tok, st);
-    (void)hipFreeAsync(ws, st);
-    return rc;
+        profile_end(tok, st);
+        (void)hipFreeAsync(ws, st);
+        return rc;
+    });
 }
 
 }  // extern "C"

@@ -55,34 +55,36 @@ extern "C" cspd_status cspd_omp_cross_scale_noalloc(cspd_plan_t p, int64_t B, co
                                                     int32_t *k_used, void *xhat, int32_t *support_coarse,
                                                     void *hip_stream)
 {
-    clear_error();
-    if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
-    // profiling events are created per launch; this entry point records none
-    ProfileSuspend quiet;
-    // one scale: the full-dictionary kernels use no workspace
-    if (p->s == 1)
-        return cspd_omp_full(p, B, y, mask, k_fine, k_fine_uniform, support, coef, k_used, xhat, hip_stream);
-    if (B < 0) return set_error(CSPD_E_INVALID, "B = %lld", (long long)B);
-    if (!k_scale) return set_error(CSPD_E_INVALID, "k_scale is NULL");
-    for (int s = 0; s + 1 < p->s; ++s)
-        if (k_scale[s] < 0 || k_scale[s] > p->k_max)
-            return set_error(CSPD_E_SHAPE, "k_scale[%d] = %d outside [0, k_max = %d]", s, k_scale[s], p->k_max);
-    const size_t need = cross_call_workspace(p, B, k_scale, support_coarse != nullptr);
-    if (need > (size_t)CSPD_NOALLOC_SCRATCH_BYTES)
-        return set_error(CSPD_E_CAPACITY,
-                         "%lld patches need %zu bytes of workspace; the static scratch holds %zu "
-                         "(pass support_coarse, or split the batch)",
-                         (long long)B, need, (size_t)CSPD_NOALLOC_SCRATCH_BYTES);
-    if (p->device < 0 || p->device >= kMaxDevices)
-        return set_error(CSPD_E_UNSUPPORTED, "device %d: the scratch table holds %d devices", p->device, kMaxDevices);
-    void *work = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        if (!g_ptr[p->device])
-            return set_error(CSPD_E_DEVICE, "device %d: address of the static scratch unavailable (%s)", p->device,
-                             g_tried[p->device] ? hipGetErrorString(g_rc[p->device]) : "never resolved");
-        work = g_ptr[p->device];
-    }
-    return cross_scale_on(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat,
-                          support_coarse, work, (size_t)CSPD_NOALLOC_SCRATCH_BYTES, (hipStream_t)hip_stream);
+    return guarded([&]() -> cspd_status {
+        clear_error();
+        if (!p) return set_error(CSPD_E_INVALID, "plan is NULL");
+        // profiling events are created per launch; this entry point records none
+        ProfileSuspend quiet;
+        // one scale: the full-dictionary kernels use no workspace
+        if (p->s == 1)
+            return cspd_omp_full(p, B, y, mask, k_fine, k_fine_uniform, support, coef, k_used, xhat, hip_stream);
+        if (B < 0) return set_error(CSPD_E_INVALID, "B = %lld", (long long)B);
+        if (!k_scale) return set_error(CSPD_E_INVALID, "k_scale is NULL");
+        for (int s = 0; s + 1 < p->s; ++s)
+            if (k_scale[s] < 0 || k_scale[s] > p->k_max)
+                return set_error(CSPD_E_SHAPE, "k_scale[%d] = %d outside [0, k_max = %d]", s, k_scale[s], p->k_max);
+        const size_t need = cross_call_workspace(p, B, k_scale, support_coarse != nullptr);
+        if (need > (size_t)CSPD_NOALLOC_SCRATCH_BYTES)
+            return set_error(CSPD_E_CAPACITY,
+                             "%lld patches need %zu bytes of workspace; the static scratch holds %zu "
+                             "(pass support_coarse, or split the batch)",
+                             (long long)B, need, (size_t)CSPD_NOALLOC_SCRATCH_BYTES);
+        if (p->device < 0 || p->device >= kMaxDevices)
+            return set_error(CSPD_E_UNSUPPORTED, "device %d: the scratch table holds %d devices", p->device, kMaxDevices);
+        void *work = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            if (!g_ptr[p->device])
+                return set_error(CSPD_E_DEVICE, "device %d: address of the static scratch unavailable (%s)", p->device,
+                                 g_tried[p->device] ? hipGetErrorString(g_rc[p->device]) : "never resolved");
+            work = g_ptr[p->device];
+        }
+        return cross_scale_on(p, B, y, mask, k_scale, k_fine, k_fine_uniform, support, coef, k_used, xhat,
+                              support_coarse, work, (size_t)CSPD_NOALLOC_SCRATCH_BYTES, (hipStream_t)hip_stream);
+    });
 }

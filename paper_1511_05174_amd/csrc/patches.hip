@@ -173,36 +173,40 @@ int64_t cspd_patch_count(const cspd_patch_grid *grid)
 cspd_status cspd_extract_patches(const cspd_patch_grid *grid, const float *signal, const uint8_t *mask, float *y,
                                  uint8_t *patch_mask, void *hip_stream)
 {
-    clear_error();
-    Grid g{};
-    cspd_status rc = make_grid(grid, g);
-    if (rc != CSPD_OK) return rc;
-    if (!signal || !y) return set_error(CSPD_E_INVALID, "signal / y is NULL");
-    const int64_t n = g.npatch * g.pvol;
-    const int bs = 256;
-    ProfileToken *tok = profile_begin("extract_patches", (hipStream_t)hip_stream);
-    hipLaunchKernelGGL(k_extract, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, (hipStream_t)hip_stream, g,
-                       signal, mask, y, patch_mask);
-    profile_end(tok, (hipStream_t)hip_stream);
-    if (hipGetLastError() != hipSuccess) return set_error(CSPD_E_DEVICE, "extract launch failed");
-    return CSPD_OK;
+    return guarded([&]() -> cspd_status {
+        clear_error();
+        Grid g{};
+        cspd_status rc = make_grid(grid, g);
+        if (rc != CSPD_OK) return rc;
+        if (!signal || !y) return set_error(CSPD_E_INVALID, "signal / y is NULL");
+        const int64_t n = g.npatch * g.pvol;
+        const int bs = 256;
+        ProfileToken *tok = profile_begin("extract_patches", (hipStream_t)hip_stream);
+        hipLaunchKernelGGL(k_extract, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, (hipStream_t)hip_stream, g,
+                           signal, mask, y, patch_mask);
+        profile_end(tok, (hipStream_t)hip_stream);
+        if (hipGetLastError() != hipSuccess) return set_error(CSPD_E_DEVICE, "extract launch failed");
+        return CSPD_OK;
+    });
 }
 
 cspd_status cspd_aggregate_patches(const cspd_patch_grid *grid, const float *estimates, float *signal_out,
                                    void *hip_stream)
 {
-    clear_error();
-    Grid g{};
-    cspd_status rc = make_grid(grid, g);
-    if (rc != CSPD_OK) return rc;
-    if (!estimates || !signal_out) return set_error(CSPD_E_INVALID, "estimates / signal_out is NULL");
-    const int bs = 256;
-    ProfileToken *tok = profile_begin("aggregate_patches", (hipStream_t)hip_stream);
-    hipLaunchKernelGGL(k_aggregate, dim3((unsigned)((g.nsig + bs - 1) / bs)), dim3(bs), 0, (hipStream_t)hip_stream,
-                       g, estimates, signal_out);
-    profile_end(tok, (hipStream_t)hip_stream);
-    if (hipGetLastError() != hipSuccess) return set_error(CSPD_E_DEVICE, "aggregate launch failed");
-    return CSPD_OK;
+    return guarded([&]() -> cspd_status {
+        clear_error();
+        Grid g{};
+        cspd_status rc = make_grid(grid, g);
+        if (rc != CSPD_OK) return rc;
+        if (!estimates || !signal_out) return set_error(CSPD_E_INVALID, "estimates / signal_out is NULL");
+        const int bs = 256;
+        ProfileToken *tok = profile_begin("aggregate_patches", (hipStream_t)hip_stream);
+        hipLaunchKernelGGL(k_aggregate, dim3((unsigned)((g.nsig + bs - 1) / bs)), dim3(bs), 0, (hipStream_t)hip_stream,
+                           g, estimates, signal_out);
+        profile_end(tok, (hipStream_t)hip_stream);
+        if (hipGetLastError() != hipSuccess) return set_error(CSPD_E_DEVICE, "aggregate launch failed");
+        return CSPD_OK;
+    });
 }
 
 }  // extern "C"

@@ -131,31 +131,41 @@ extern "C" {
 
 cspd_status cspd_profile_enable(int32_t on)
 {
-    g_on.store(on ? 1 : 0);
-    return CSPD_OK;
+    return guarded([&]() -> cspd_status {
+        g_on.store(on ? 1 : 0);
+        return CSPD_OK;
+    });
 }
 
 int32_t cspd_profile_read(int32_t idx, char *name, int32_t name_len, int64_t *launches, double *total_ms)
 {
-    std::lock_guard<std::mutex> g(g_mu);
-    settle_locked();
-    const int32_t n = (int32_t)g_entries.size();
-    if (idx < 0 || idx >= n) return n;
-    const Entry &e = g_entries[idx];
-    if (name && name_len > 0) {
-        std::strncpy(name, e.label.c_str(), (size_t)name_len - 1);
-        name[name_len - 1] = 0;
+    try {
+        std::lock_guard<std::mutex> g(g_mu);
+        settle_locked();
+        const int32_t n = (int32_t)g_entries.size();
+        if (idx < 0 || idx >= n) return n;
+        const Entry &e = g_entries[idx];
+        if (name && name_len > 0) {
+            std::strncpy(name, e.label.c_str(), (size_t)name_len - 1);
+            name[name_len - 1] = 0;
+        }
+        if (launches) *launches = e.launches;
+        if (total_ms) *total_ms = e.total_ms;
+        return n;
+    } catch (...) {
+        return CSPD_E_DEVICE;
     }
-    if (launches) *launches = e.launches;
-    if (total_ms) *total_ms = e.total_ms;
-    return n;
 }
 
 void cspd_profile_reset(void)
 {
-    std::lock_guard<std::mutex> g(g_mu);
-    settle_locked();
-    g_entries.clear();
+    try {
+        std::lock_guard<std::mutex> g(g_mu);
+        settle_locked();
+        g_entries.clear();
+    } catch (...) {
+        // nothing may cross the C ABI; the object is left as it is
+    }
 }
 
 }  // extern "C"

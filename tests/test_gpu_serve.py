@@ -118,3 +118,85 @@ def test_large_job_cut_into_pieces():
     assert np.array_equal(out_s["support"], ref["support"][:500])
     print(f"small job shared a launch with {st_s['batched_with']} other job(s)", flush=True)
     cspd.cspd_serve_destroy(srv)
+
+
+def test_device_buffers_run_in_place():
+    """A job on device tensors (two pieces, zero-tree OMP) and one on a full
+    OMP, mixed with a host-buffer job: each equals the call alone."""
+    torch = G.torch_mod()
+    w = synth.make("c2", batch=70000)
+    plan = cspd.plan_from_workload(w)
+    y, mask, kf, _ = G.inputs(w)
+    ks = list(w.k_scales)
+    srv = cspd.cspd_serve_create(0, 1 << 30, 3)
+    jd = cspd.cspd_serve_submit_device(srv, plan, y, mask, kf, ks[-1], ks[:-1])
+    small = synth.subset(w, np.arange(0, 3000))
+    ys, ms, kfs, _ = G.inputs(small)
+    jf = cspd.cspd_serve_submit_device(srv, plan, ys, ms, kfs, ks[-1], full=True)
+    jh = _submit(srv, plan, small, ks, False)
+    out, st = cspd.cspd_serve_poll(srv, jd, -1)
+    assert st["status"] == 0 and st["patches"] == w.batch and st["batched_with"] == 0
+    ref = G.run_cross(plan, w)
+    assert np.array_equal(out["support"].cpu().numpy(), ref["support"])
+    assert np.array_equal(out["k_used"].cpu().numpy(), ref["k_used"])
+    assert np.array_equal(out["coef"].double().cpu().numpy(), ref["coef"])
+    assert np.array_equal(out["xhat"].double().cpu().numpy(), ref["xhat"])
+    outf, _ = cspd.cspd_serve_poll(srv, jf, -1)
+    reff = G.run_full(plan, small)
+    assert np.array_equal(outf["support"].cpu().numpy(), reff["support"])
+    assert np.array_equal(outf["coef"].double().cpu().numpy(), reff["coef"])
+    outh, _ = cspd.cspd_serve_poll(srv, jh, -1)
+    assert np.array_equal(outh["support"], ref["support"][:3000])
+    cspd.cspd_serve_destroy(srv)
+    torch.cuda.synchronize()
+
+
+def test_budget_bounds_resident_buffers():
+    """Slots keep their buffers between launches; the budget bounds all of
+    them (idle ones are released when a launch would not fit), and every
+    job still finishes with the result it gets alone."""
+    G.torch_mod()
+    w = synth.make("c2", batch=16384)
+    plan = cspd.plan_from_workload(w)
+    budget = 24 << 20      # about two launches of 16,384 patches
+    srv = cspd.cspd_serve_create(0, budget, 4)
+    rng = np.random.default_rng(11)
+    jobs = []
+    for i in range(24):
+        n = int(rng.integers(1024, 16385))
+        sub = synth.subset(w, np.arange(0, n))
+        jobs.append((_submit(srv, plan, sub, w.k_scales, False), n))
+    ref = G.run_cross(plan, w)
+    worst = 0
+    for jid, n in jobs:
+        out, st = cspd.cspd_serve_poll(srv, jid, -1)
+        assert st["status"] == 0
+        worst = max(worst, st["server_resident_bytes"])
+        assert np.array_equal(out["support"], ref["support"][:n])
+    print(f"largest resident bytes seen: {worst} (budget {budget})", flush=True)
+    assert 0 < worst <= budget
+    cspd.cspd_serve_destroy(srv)
+
+
+def test_small_jobs_do_not_wait_behind_large():
+    """A large job (seven pieces) then a small one on three slots: the large
+    job leaves the last free slot to small jobs, so the small one is admitted
+    at once and finishes long before the large one."""
+    G.torch_mod()
+    w = synth.make("c5a", batch=400000)
+    plan = cspd.plan_from_workload(w)
+    srv = cspd.cspd_serve_create(0, 4 << 30, 3)
+    j_big = _submit(srv, plan, w, w.k_scales, False)
+    small = synth.subset(w, np.arange(0, 500))
+    j_small = _submit(srv, plan, small, w.k_scales, False)
+    out_s, st_s = cspd.cspd_serve_poll(srv, j_small, -1)
+    out_b, st_b = cspd.cspd_serve_poll(srv, j_big, -1)
+    wait_s = (st_s["admit_ns"] - st_s["submit_ns"]) * 1e-6
+    lat_s = (st_s["finish_ns"] - st_s["submit_ns"]) * 1e-6
+    lat_b = (st_b["finish_ns"] - st_b["submit_ns"]) * 1e-6
+    print(f"small job: admitted after {wait_s:.3f} ms, done after {lat_s:.3f} ms; large job {lat_b:.3f} ms",
+          flush=True)
+    assert st_s["finish_ns"] < st_b["finish_ns"]
+    assert wait_s < 0.2 * lat_b
+    assert np.array_equal(out_s["support"], out_b["support"][:500])
+    cspd.cspd_serve_destroy(srv)
