@@ -99,7 +99,11 @@ cspd_status validate_desc(const cspd_plan_desc *d)
         return set_error(CSPD_E_INVALID, "reduced-precision proxy needs an FP32 plan");
     if (d->rescore_m < 0 || d->rescore_m > 16) return set_error(CSPD_E_INVALID, "rescore_m %d outside 0..16", d->rescore_m);
     if (d->k_max < 1) return set_error(CSPD_E_SHAPE, "k_max %d must be >= 1", d->k_max);
-    if (d->k_max > kMaxK) return set_error(CSPD_E_UNSUPPORTED, "k_max %d above the supported %d", d->k_max, kMaxK);
+    if (d->k_max > kMaxKBatch)
+        return set_error(CSPD_E_UNSUPPORTED, "k_max %d above the supported %d", d->k_max, kMaxKBatch);
+    if (d->k_max > kMaxK && (d->dtype != CSPD_F32 || d->phi_kind == CSPD_PHI_MASK || d->n_phases > 1))
+        return set_error(CSPD_E_UNSUPPORTED,
+                         "k_max %d above %d needs the FP32 full search over a shared operator", d->k_max, kMaxK);
     for (int s = 0; s < S; ++s) {
         const int l = d->phi_kind == CSPD_PHI_DENSE ? d->m : d->dim[s];
         const int cap = d->dtype == CSPD_F32 ? kMaxLongLen : kMaxShortLen;
@@ -129,6 +133,8 @@ void free_plan(cspd_plan_s *p)
         if (sc.blk_idx) (void)hipFree(sc.blk_idx);
     }
     if (p->d_high) (void)hipFree(p->d_high);
+    if (p->bat_a64) (void)hipFree(p->bat_a64);
+    if (p->bat_g) (void)hipFree(p->bat_g);
     delete p;
 }
 
@@ -195,6 +201,8 @@ cspd_status prepare_cross(const cspd_plan_s *p, int64_t B, const void *y, const 
 {
     if (B < 0) return set_error(CSPD_E_INVALID, "B = %lld", (long long)B);
     if (!k_scale) return set_error(CSPD_E_INVALID, "k_scale is NULL");
+    if (p->k_max > kMaxK && p->s > 1)
+        return set_error(CSPD_E_UNSUPPORTED, "a plan with k_max %d above %d runs full OMP only", p->k_max, kMaxK);
     c.ksum = 0;
     for (int s = 0; s + 1 < p->s; ++s) {
         if (k_scale[s] < 0 || k_scale[s] > p->k_max)
@@ -499,6 +507,12 @@ cspd_status full_on(cspd_plan_s *p, int64_t B, const int32_t *phase, const void 
     a.xhat = xhat;
     const int cand = sc.t;
     cspd_status rc;
+    // full search in coefficient coordinates: built for dictionaries (or
+    // sparsities) that no per-patch kernel holds
+    if (batch_fits(p)) return launch_batch(p, a, st);
+    if (p->k_max > kMaxK)
+        return set_error(CSPD_E_UNSUPPORTED, "k_max %d above %d needs the full-search tables (T = %d)", p->k_max,
+                         kMaxK, sc.t);
     if (sc.lp > kMaxShortLen) {
         rc = p->dtype == CSPD_F32 && long_fits(a, cand) ? launch_long(p->dtype, a, cand, st) : CSPD_E_UNSUPPORTED;
         if (rc == CSPD_E_UNSUPPORTED && !has_error())

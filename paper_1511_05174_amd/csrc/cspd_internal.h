@@ -16,6 +16,10 @@ namespace cspd {
 
 // Largest sparsity per scale the per-patch kernels keep state for.
 constexpr int kMaxK = 16;
+// full search in coefficient coordinates (Gram matrix precomputed): atoms and
+// sparsity it supports; plans with k_max above kMaxK run only this path
+constexpr int kMaxBatchAtoms = 8192;
+constexpr int kMaxKBatch = 64;
 // Per-patch Gram tables are precomputed for shared operators up to this size.
 constexpr int kMaxGramAtoms = 1024;
 // Candidate vectors longer than kMaxShortLen coordinates (up to kMaxLongLen)
@@ -121,6 +125,11 @@ struct cspd_plan_s {
     int64_t bytes = 0;
     cspd::ScalePlan sc[CSPD_MAX_SCALES];
     void *d_high = nullptr;   // T_high x N atom-contiguous (plan dtype), for x-hat
+    // full search over large dictionaries (FP32 plans, shared operator):
+    // the finest effective dictionary in FP64 (T x l, atom-contiguous) and its
+    // Gram matrix A^T A (T x T, FP32); null unless built
+    void *bat_a64 = nullptr;
+    void *bat_g = nullptr;
     // autotuned kernel per scale and sparsity bucket (K <= 4, <= 8, <= 16)
     cspd::KernelChoice tuned[CSPD_MAX_SCALES][3];
     mutable std::mutex mu;   // guards tuned
@@ -261,5 +270,14 @@ struct ProfileSuspend {
 
 // Plan-time kernels.
 cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t stream);
+
+// Plain library GEMM (rocBLAS, FP64): column-major C (m x n) = A^T B with A
+// stored k x m (leading dimension lda) and B stored k x n, on `st`.
+cspd_status gemm_tn_f64(int device, hipStream_t st, int m, int n, int k, const double *a, int lda,
+                        const double *b, int ldb, double *c, int ldc);
+// Full search in coefficient coordinates over the plan's finest scale (its
+// Gram matrix precomputed): whether the plan has the tables, and the launch.
+bool batch_fits(const cspd_plan_s *p);
+cspd_status launch_batch(const cspd_plan_s *p, const ScaleArgs &a, hipStream_t st);
 
 }  // namespace cspd

@@ -315,6 +315,26 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
                 (const float *)sc.v, sc.t * P, sc.lp, sc.gsplit, (uint32_t *)sc.v_split);
             CSPD_HIP_CHECK(hipGetLastError());
         }
+        if (s == S - 1 && p->dtype == CSPD_F32 && P == 1 && !mask && T <= kMaxBatchAtoms &&
+            (p->k_max > kMaxK || T > 4096 || (T > kMaxLongCand && sc.lp > 128))) {
+            // full search in coefficient coordinates: the effective atoms in
+            // FP64 and their Gram matrix (FP64 GEMM, stored FP32)
+            const size_t ab = sizeof(double) * (size_t)T * l;
+            CSPD_HIP_CHECK(hipMalloc(&p->bat_a64, ab));
+            p->bytes += (int64_t)ab;
+            CSPD_HIP_CHECK(hipMemcpyAsync(p->bat_a64, a64.p, ab, hipMemcpyDeviceToDevice, st));
+            DevBuf g64;
+            CSPD_HIP_CHECK(hipMalloc(&g64.p, sizeof(double) * (size_t)T * T));
+            const cspd_status grc = gemm_tn_f64(p->device, st, T, T, l, (const double *)a64.p, l,
+                                                (const double *)a64.p, l, (double *)g64.p, T);
+            if (grc != CSPD_OK) return grc;
+            CSPD_HIP_CHECK(hipMalloc(&p->bat_g, sizeof(float) * (size_t)T * T));
+            p->bytes += (int64_t)(sizeof(float) * (size_t)T * T);
+            k_cast_rows<float><<<blocks_for((int64_t)T * T, 256), 256, 0, st>>>((const double *)g64.p, T, T,
+                                                                                (float *)p->bat_g, T);
+            CSPD_HIP_CHECK(hipGetLastError());
+            CSPD_HIP_CHECK(hipStreamSynchronize(st));
+        }
         if (s == S - 1) {
             // D_high in signal coordinates, atom-contiguous, for x-hat
             size_t eb = p->dtype == CSPD_F64 ? sizeof(double) : sizeof(float);

@@ -51,7 +51,9 @@ def _desc(**over):
     (dict(m=12), cspd.E_SHAPE),                                # identity needs M = N
     (dict(phi_kind="dense", m=12, phi=None), cspd.E_INVALID),  # dense without Phi
     (dict(k_max=0), cspd.E_SHAPE),
-    (dict(k_max=64), cspd.E_UNSUPPORTED),
+    (dict(k_max=65), cspd.E_UNSUPPORTED),                     # above the full search's 64
+    (dict(k_max=32, dtype="f64"), cspd.E_UNSUPPORTED),        # K > 16: FP32 full search only
+    (dict(k_max=32, phi_kind="mask"), cspd.E_UNSUPPORTED),    # ... over a shared operator
     (dict(up_maps=[np.full(16, 7, dtype=np.int32)]), cspd.E_SHAPE),   # outside [0, N_0)
     (dict(up_maps=[np.zeros(16, dtype=np.int32)]), cspd.E_SHAPE),     # not onto
     (dict(dtype="f64", corr_mode="bf16"), cspd.E_INVALID),
