@@ -831,6 +831,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-timeacc", action="store_true", help="skip the time versus accuracy studies")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-pipeline", action="store_true")
@@ -1002,6 +1003,19 @@ def main():
         learning = learning_phase(cspd, w)
         print(f"[bench] learning: {json.dumps(learning)}", file=sys.stderr, flush=True)
 
+    # ---- time versus accuracy: single-scale dictionaries of 256..8192 atoms
+    # against zero-tree OMP on 8x8x32 video patches; the effect of Q
+    time_accuracy = q_study = None
+    if not args.no_timeacc:
+        from paper_1511_05174_amd import timeacc
+        time_accuracy = timeacc.video_time_accuracy(batch=1024, steps=2)
+        z = time_accuracy["zero_tree"]
+        print(f"[bench] time-accuracy: zero-tree {z['ms_per_call']:.3f} ms, {z['psnr_db']:.2f} dB; single-scale "
+              + ", ".join(f"T{p['atoms']}/K{p['k']}: {p['ms_per_call']:.3f} ms {p['psnr_db']:.2f} dB"
+                          for p in time_accuracy["single_scale"]), file=sys.stderr, flush=True)
+        q_study = timeacc.q_effect()
+        print(f"[bench] Q study: {json.dumps(q_study['points'])}", file=sys.stderr, flush=True)
+
     # ---- precision: bf16 / fp16 proxies with FP32 re-scoring (full OMP, 3-scale workload)
     precision = None
     if not args.no_precision:
@@ -1077,6 +1091,8 @@ def main():
         "equal_psnr_child_detail_1": equal_d1,
         "serving": serving,
         "precision": precision,
+        "time_accuracy": time_accuracy,
+        "q_effect": q_study,
         "graphs": graphs,
         "autotune": autotune,
         "pipeline": pipeline,

@@ -192,7 +192,7 @@ struct CrossCall {
     int ksum = 0;
     int cand[CSPD_MAX_SCALES] = {};
     char gram[CSPD_MAX_SCALES] = {};
-    char lng[CSPD_MAX_SCALES] = {};   // the scale runs on the long-vector kernel
+    char lng[CSPD_MAX_SCALES] = {};   // 1: the long-vector kernel; 2: coefficient coordinates
 };
 
 cspd_status prepare_cross(const cspd_plan_s *p, int64_t B, const void *y, const uint8_t *mask,
@@ -220,7 +220,10 @@ cspd_status prepare_cross(const cspd_plan_s *p, int64_t B, const void *y, const 
         c.cand[s] = max_candidates(p, s, s == 0, kprev);
         const bool short_ok = scale_vec_fits(p->sc[s].lp, c.cand[s], p->dtype == CSPD_F64) ||
                               (s == 0 && p->sc[s].gram);
-        if (p->sc[s].lp > kMaxShortLen || !short_ok) {
+        if (s == p->s - 1 && s > 0 && p->sc[s].lp > kMaxShortLen && batch_fits(p) &&
+            c.cand[s] <= kMaxBatchAtoms) {
+            c.lng[s] = 2;   // zero-tree finest scale in coefficient coordinates (Gram table)
+        } else if (p->sc[s].lp > kMaxShortLen || !short_ok) {
             ScaleArgs la = base_args(p, s, B, y, mask);
             if (p->dtype != CSPD_F32 || !long_fits(la, c.cand[s]))
                 return set_error(CSPD_E_UNSUPPORTED, "scale %d: no long-vector kernel for %d candidates of length %d",
@@ -307,6 +310,7 @@ cspd_status launch_cross_scale(const cspd_plan_s *p, int s, const ScaleArgs &a0,
                                hipStream_t st)
 {
     ScaleArgs a = a0;
+    if (c.lng[s] == 2) return launch_batch(p, a, c.cand[s], st);
     if (c.lng[s]) return launch_long(p->dtype, a, c.cand[s], st);
     if (s == 0 && first_gemm_path(p)) {
         a.hpre = hpre;   // workspace for the GEMM variant
@@ -509,7 +513,7 @@ cspd_status full_on(cspd_plan_s *p, int64_t B, const int32_t *phase, const void 
     cspd_status rc;
     // full search in coefficient coordinates: built for dictionaries (or
     // sparsities) that no per-patch kernel holds
-    if (batch_fits(p)) return launch_batch(p, a, st);
+    if (batch_fits(p)) return launch_batch(p, a, sc.t, st);
     if (p->k_max > kMaxK)
         return set_error(CSPD_E_UNSUPPORTED, "k_max %d above %d needs the full-search tables (T = %d)", p->k_max,
                          kMaxK, sc.t);

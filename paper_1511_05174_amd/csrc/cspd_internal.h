@@ -275,9 +275,11 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
 // stored k x m (leading dimension lda) and B stored k x n, on `st`.
 cspd_status gemm_tn_f64(int device, hipStream_t st, int m, int n, int k, const double *a, int lda,
                         const double *b, int ldb, double *c, int ldc);
-// Full search in coefficient coordinates over the plan's finest scale (its
-// Gram matrix precomputed): whether the plan has the tables, and the launch.
+// Search in coefficient coordinates over the plan's finest scale (its Gram
+// matrix precomputed): whether the plan has the tables, and the launch.
 bool batch_fits(const cspd_plan_s *p);
-cspd_status launch_batch(const cspd_plan_s *p, const ScaleArgs &a, hipStream_t st);
+// With a.first == 0 it runs zero-tree OMP's finest scale over the children of
+// the coarse support (at most max_cand candidates).
+cspd_status launch_batch(const cspd_plan_s *p, const ScaleArgs &a, int max_cand, hipStream_t st);
 
 }  // namespace cspd

@@ -23,7 +23,14 @@
 // ... of the proxy, held in FP64 registers (p0 and G[:, Omega] alpha); each
 // step reads the k + 1 rows of G of the support (G is symmetric, so rows
 // are columns) with coalesced loads.  The argmax takes the lowest atom index
-// on ties.  Wavefront 0 runs the triangular solves column by column, lane j
+// on ties.
+//
+// The same kernel runs the finest scale of zero-tree OMP (Algorithm 2) when
+// its vectors are long: the candidates are then the children of the coarse
+// support (candidate c is child c mod Q of the (c / Q)-th coarse atom), their
+// correlations <a_i, y> are formed in the kernel (FP64 sums of the FP32
+// vectors, one wavefront per candidate), and the proxy gathers G[Omega, i]
+// over the candidates only.  Wavefront 0 runs the triangular solves column by column, lane j
 // holding row j.  An atom whose squared pivot is at most 1e-10 of its squared
 // norm is dependent and ends the patch, as does reaching the rank of the
 // measurement space.
@@ -57,6 +64,15 @@ struct BatchArgs {
     float *xhat;           // b x n or null
     const float *dh;       // t x n atoms in signal coordinates
     int n;
+    // candidate mode (zero-tree finest scale): children of the coarse support
+    const float *y;        // b x y_stride measurements
+    int y_stride;
+    const float *v;        // t x lp effective atoms (FP32)
+    int lp;
+    const int *prev_sup;   // b x prev_stride coarse supports
+    int prev_stride;
+    const int *prev_kused; // b
+    int q;                 // children per coarse atom
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -87,38 +103,68 @@ __device__ __forceinline__ double wave_sum_d(double v)
     return v;
 }
 
-template <int TPT, int KX>
+template <int TPT, int KX, bool CAND>
 __global__ __launch_bounds__(kThreads) void k_omp_batch(BatchArgs a)
 {
     static_assert(TPT >= 1 && TPT <= 32 && KX <= 64, "atoms per thread, sparsity");
+    constexpr int NCX = CAND ? TPT * kThreads : 1;
+    __shared__ double sp0[NCX];      // candidate mode: <a_i, y> of every candidate
     __shared__ double sL[KX * KX];
     __shared__ double sz[KX], sal[KX], sg[KX + 1];
     __shared__ int ssup[KX];
     __shared__ double wbs[kWaves];
     __shared__ int wbi[kWaves];
     __shared__ int s_pick, s_go;
+    __shared__ double s_p0k;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
     const int64_t b = blockIdx.x;
     const int t = a.t;
-    const double *p0 = a.p0 + b * (int64_t)t;
+    const double *p0 = CAND ? nullptr : a.p0 + b * (int64_t)t;
 
+    // candidates: every atom, or the children of the coarse support
+    int nc = t;
+    if constexpr (CAND) {
+        const int kp = a.prev_kused[b];
+        nc = kp * a.q;
+        nc = nc < NCX ? nc : NCX;
+    }
+    auto atom_of = [&](int ci) -> int {
+        if constexpr (!CAND) return ci;
+        const int pj = ci / a.q;
+        return a.prev_sup[b * (int64_t)a.prev_stride + pj] * a.q + (ci - pj * a.q);
+    };
+    if constexpr (CAND) {
+        // <a_i, y> of each candidate: one wavefront per candidate, FP64 sums
+        const float *yr = a.y + b * (int64_t)a.y_stride;
+        for (int ci = wv; ci < nc; ci += kWaves) {
+            const float *vr = a.v + (int64_t)atom_of(ci) * a.lp;
+            double part = 0.0;
+            for (int c = lane; c < a.l; c += 64) part += (double)vr[c] * (double)yr[c];
+            part = wave_sum_d(part);
+            if (lane == 0) sp0[ci] = part;
+        }
+        __syncthreads();
+    }
     double pr[TPT], beta[TPT];
     double inv[TPT];
+    int at[TPT];
     unsigned sel = 0u;
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
-        const int i = tid + q * kThreads;
-        pr[q] = i < t ? p0[i] : 0.0;
+        const int ci = tid + q * kThreads;
+        const bool live = ci < nc;
+        at[q] = live ? atom_of(ci) : INT_MAX;
+        pr[q] = live ? (CAND ? sp0[ci] : p0[ci]) : 0.0;
         beta[q] = 0.0;
-        const double gii = i < t ? (double)a.g[(int64_t)i * t + i] : 0.0;
+        const double gii = live ? (double)a.g[(int64_t)at[q] * t + at[q]] : 0.0;
         inv[q] = gii > 0.0 ? 1.0 / sqrt(gii) : -1.0;   // an effective column of zero is never picked
     }
     int K = a.kvec ? a.kvec[b] : a.kuni;
     K = K < a.kcap ? K : a.kcap;
     K = K < KX ? K : KX;
-    K = K < t ? K : t;
+    K = K < nc ? K : nc;
     K = K > 0 ? K : 0;
 
     int nsel = 0;
@@ -128,10 +174,9 @@ __global__ __launch_bounds__(kThreads) void k_omp_batch(BatchArgs a)
         int bi = INT_MAX;
 #pragma unroll
         for (int q = 0; q < TPT; ++q) {
-            const int i = tid + q * kThreads;
-            const bool ok = i < t && inv[q] > 0.0 && !((sel >> q) & 1u);
+            const bool ok = at[q] != INT_MAX && inv[q] > 0.0 && !((sel >> q) & 1u);
             const double sc = ok ? fabs(pr[q] - beta[q]) * inv[q] : -1.0;
-            if (sc > bs) { bs = sc; bi = i; }   // atoms rise with q: ties keep the lower index
+            if (sc > bs || (sc == bs && at[q] < bi)) { bs = sc; bi = at[q]; }
         }
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) {
@@ -151,6 +196,9 @@ __global__ __launch_bounds__(kThreads) void k_omp_batch(BatchArgs a)
         __syncthreads();
         const int k = s_pick;
         if (k < 0) break;                    // no candidate left
+#pragma unroll
+        for (int q = 0; q < TPT; ++q)
+            if (at[q] == k) s_p0k = pr[q];   // <a_k, y>, from the thread that holds it
         // ---- support merge: Gram entries of the new atom against Omega and
         // its squared norm (entry it), FP64 dot products, one per wavefront
         {
@@ -184,7 +232,7 @@ __global__ __launch_bounds__(kThreads) void k_omp_batch(BatchArgs a)
                 if (lane < it) sL[it * KX + lane] = wj;
                 if (lane == 0) {
                     sL[it * KX + it] = l;
-                    sz[it] = (p0[k] - zw) / l;
+                    sz[it] = (s_p0k - zw) / l;
                     ssup[it] = k;
                 }
                 wave_sync();
@@ -201,7 +249,9 @@ __global__ __launch_bounds__(kThreads) void k_omp_batch(BatchArgs a)
         }
         __syncthreads();
         if (!s_go) break;                    // dependent atom, or the space is spanned
-        if ((k % kThreads) == tid) sel |= 1u << (k / kThreads);
+#pragma unroll
+        for (int q = 0; q < TPT; ++q)
+            if (at[q] == k) sel |= 1u << q;
         nsel = it + 1;
         // ---- residue in coefficient coordinates: G[:, Omega] alpha
 #pragma unroll
@@ -210,10 +260,8 @@ __global__ __launch_bounds__(kThreads) void k_omp_batch(BatchArgs a)
             const float *row = a.g + (int64_t)ssup[j] * t;
             const double aj = sal[j];
 #pragma unroll
-            for (int q = 0; q < TPT; ++q) {
-                const int i = tid + q * kThreads;
-                if (i < t) beta[q] += (double)row[i] * aj;
-            }
+            for (int q = 0; q < TPT; ++q)
+                if (at[q] != INT_MAX) beta[q] += (double)row[at[q]] * aj;
         }
     }
 
@@ -242,21 +290,27 @@ __global__ void k_to_f64(const float *__restrict__ y, int ys, int m, int64_t nb,
     out[idx] = (double)y[r * ys + c];
 }
 
-template <int TPT, int KX>
-void launch_one(const BatchArgs &a, hipStream_t st)
+template <int TPT, int KX, bool CAND>
+void launch_one(const BatchArgs &a, int scale, hipStream_t st)
 {
     char label[64];
-    snprintf(label, sizeof(label), "omp_batch<f32,t%d,k%d>:full", TPT * kThreads, KX);
-    launch_timed(label, k_omp_batch<TPT, KX>, dim3((unsigned)a.b), dim3(kThreads), 0u, st, a);
+    if (CAND)
+        snprintf(label, sizeof(label), "omp_batch<f32,c%d,k%d>:s%d", TPT * kThreads, KX, scale);
+    else
+        snprintf(label, sizeof(label), "omp_batch<f32,t%d,k%d>:full", TPT * kThreads, KX);
+    launch_timed(label, k_omp_batch<TPT, KX, CAND>, dim3((unsigned)a.b), dim3(kThreads), 0u, st, a);
 }
 
-template <int KX>
-cspd_status by_t(const BatchArgs &a, hipStream_t st)
+// n: atoms (full search) or the most candidates (zero-tree finest scale)
+template <int KX, bool CAND>
+cspd_status by_n(const BatchArgs &a, int n, int scale, hipStream_t st)
 {
-    if (a.t <= 1024) launch_one<4, KX>(a, st);
-    else if (a.t <= 2048) launch_one<8, KX>(a, st);
-    else if (a.t <= 4096) launch_one<16, KX>(a, st);
-    else if (a.t <= 8192) launch_one<32, KX>(a, st);
+    if (CAND && n <= 256) launch_one<1, KX, CAND>(a, scale, st);
+    else if (CAND && n <= 512) launch_one<2, KX, CAND>(a, scale, st);
+    else if (n <= 1024) launch_one<4, KX, CAND>(a, scale, st);
+    else if (n <= 2048) launch_one<8, KX, CAND>(a, scale, st);
+    else if (n <= 4096) launch_one<16, KX, CAND>(a, scale, st);
+    else if (n <= 8192) launch_one<32, KX, CAND>(a, scale, st);
     else return CSPD_E_UNSUPPORTED;
     return hipGetLastError() == hipSuccess ? CSPD_OK : CSPD_E_DEVICE;
 }
@@ -280,12 +334,44 @@ static int64_t batch_chunk(const cspd_plan_s *p)
     return c > 256 ? c : 256;
 }
 
-cspd_status launch_batch(const cspd_plan_s *p, const ScaleArgs &a, hipStream_t st)
+cspd_status launch_batch(const cspd_plan_s *p, const ScaleArgs &a, int max_cand, hipStream_t st)
 {
     using namespace batch_impl;
-    if (!batch_fits(p)) return CSPD_E_UNSUPPORTED;
+    if (!batch_fits(p) || max_cand > kMaxBatchAtoms) return CSPD_E_UNSUPPORTED;
     if (a.b <= 0) return CSPD_OK;
     const ScalePlan &sc = p->sc[p->s - 1];
+    const int kmax = a.kvec ? p->k_max : a.kuni;
+    if (!a.first) {
+        // zero-tree finest scale: candidates = children of the coarse support
+        BatchArgs ba{};
+        ba.b = a.b;
+        ba.g = (const float *)p->bat_g;
+        ba.a64 = (const double *)p->bat_a64;
+        ba.l = sc.l;
+        ba.t = sc.t;
+        ba.rank = a.fold == kDense ? a.m_dense : sc.l;
+        ba.kvec = a.kvec;
+        ba.kuni = a.kuni;
+        ba.kcap = a.sup_count;
+        ba.support = a.sup_out;
+        ba.coef = (float *)a.coef_out;
+        ba.k_used = a.kused_out;
+        ba.xhat = (float *)a.xhat;
+        ba.dh = (const float *)p->d_high;
+        ba.n = a.n;
+        ba.y = (const float *)a.y;
+        ba.y_stride = a.y_stride;
+        ba.v = (const float *)sc.v;
+        ba.lp = sc.lp;
+        ba.prev_sup = a.prev_sup;
+        ba.prev_stride = a.prev_stride;
+        ba.prev_kused = a.prev_kused;
+        ba.q = a.q;
+        const cspd_status rc = kmax <= 16 ? by_n<16, true>(ba, max_cand, a.scale, st)
+                                          : by_n<64, true>(ba, max_cand, a.scale, st);
+        if (rc != CSPD_OK && !has_error()) return set_error(rc, "zero-tree batch kernel launch failed");
+        return rc;
+    }
     const int64_t chunk = batch_chunk(p);
     const int64_t cb = a.b < chunk ? a.b : chunk;
     double *ws = nullptr;
@@ -295,7 +381,6 @@ cspd_status launch_batch(const cspd_plan_s *p, const ScaleArgs &a, hipStream_t s
     double *p0 = ws;
     double *y64 = ws + (size_t)cb * sc.t;
     cspd_status rc = CSPD_OK;
-    int kmax = a.kvec ? p->k_max : a.kuni;
     for (int64_t b0 = 0; b0 < a.b && rc == CSPD_OK; b0 += cb) {
         const int64_t nb = a.b - b0 < cb ? a.b - b0 : cb;
         const int64_t tot = nb * (int64_t)sc.l;
@@ -322,7 +407,7 @@ cspd_status launch_batch(const cspd_plan_s *p, const ScaleArgs &a, hipStream_t s
         ba.xhat = a.xhat ? (float *)a.xhat + b0 * (int64_t)a.n : nullptr;
         ba.dh = (const float *)p->d_high;
         ba.n = a.n;
-        rc = kmax <= 16 ? by_t<16>(ba, st) : by_t<64>(ba, st);
+        rc = kmax <= 16 ? by_n<16, false>(ba, sc.t, a.scale, st) : by_n<64, false>(ba, sc.t, a.scale, st);
         if (rc != CSPD_OK && !has_error()) rc = set_error(rc, "batch OMP kernel launch failed");
     }
     (void)hipFreeAsync(ws, st);

@@ -316,9 +316,11 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
             CSPD_HIP_CHECK(hipGetLastError());
         }
         if (s == S - 1 && p->dtype == CSPD_F32 && P == 1 && !mask && T <= kMaxBatchAtoms &&
-            (p->k_max > kMaxK || T > 4096 || (T > kMaxLongCand && sc.lp > 128))) {
-            // full search in coefficient coordinates: the effective atoms in
-            // FP64 and their Gram matrix (FP64 GEMM, stored FP32)
+            (p->k_max > kMaxK || T > 4096 || (T > kMaxLongCand && sc.lp > 128) || sc.lp > kMaxShortLen)) {
+            // search in coefficient coordinates (full OMP over large
+            // dictionaries or sparsities, and zero-tree OMP's finest scale on
+            // long vectors): the effective atoms in FP64 and their Gram
+            // matrix (FP64 GEMM, stored FP32)
             const size_t ab = sizeof(double) * (size_t)T * l;
             CSPD_HIP_CHECK(hipMalloc(&p->bat_a64, ab));
             p->bytes += (int64_t)ab;
