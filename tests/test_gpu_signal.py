@@ -84,3 +84,51 @@ def test_inpainting_pipeline_stages():
     err = float(np.sqrt(np.mean((img.cpu().numpy() - clean) ** 2)) / np.sqrt(np.mean(clean ** 2)))
     print(f"[pipeline] relative error of the inpainted image {err:.3f}", flush=True)
     assert np.isfinite(err)
+
+
+PAPER_SHAPES = [
+    # name: signal shape, patch, stride, box factors, atoms (coarse, fine)
+    ("rgb24_overlap18", (60, 66, 3), (24, 24, 3), (6, 6, 3), (2, 2, 1), (128, 2048)),
+    ("video_8x8x32", (36, 20, 20), (32, 8, 8), (4, 4, 4), (2, 2, 2), (64, 1024)),
+    ("lightfield_4x4x8x8", (4, 4, 20, 20), (4, 4, 8, 8), (1, 1, 4, 4), (2, 2, 2, 2), (64, 1024)),
+]
+
+
+@pytest.mark.parametrize("name,shape,patch,stride,box,atoms", PAPER_SHAPES)
+def test_denoising_pipeline_at_the_paper_shapes(name, shape, patch, stride, box, atoms):
+    """Denoising of a whole signal at the paper's patch shapes (Section V: 24x24
+    RGB image patches with an overlap of 18, 8x8x32 video patches, 4x4 views
+    of 8x8 pixels): patches -> zero-tree OMP -> averaging, each stage against
+    the oracle on the GPU stage's own input."""
+    torch = G.torch_mod()
+    up, coarse = synth.box_map(patch, box)
+    dims = [int(np.prod(coarse)), int(np.prod(patch))]
+    grid = cspd.patch_grid(shape, patch, stride)
+    n = cspd.cspd_patch_count(grid)
+    w = synth.custom(dims, list(atoms), n, seed=91, k_scales=[4, 8], sigma=0.0, up_maps=[up],
+                     dict_kind="model", dtype="f32")
+    plan = cspd.plan_from_workload(w)
+    clean = S.aggregate(w.x, shape, patch, stride).astype(np.float32)
+    rng = np.random.default_rng(4)
+    sigma = 0.1 * float(np.sqrt(np.mean(clean ** 2)))
+    noisy = (clean + sigma * rng.standard_normal(shape)).astype(np.float32)
+    y, _ = cspd.cspd_extract_patches(grid, torch.from_numpy(noisy).cuda(), want_mask=False)
+    sup, coef, ku, xh = cspd.cspd_omp_cross_scale(plan, y, None, w.k_scales[:-1], None, w.k_scales[-1])
+    img = cspd.cspd_aggregate_patches(grid, xh)
+    torch.cuda.synchronize()
+    yh, xhh = y.cpu().numpy(), xh.cpu().numpy()
+    assert np.array_equal(yh, S.extract(noisy, patch, stride))
+    import dataclasses
+    wp = dataclasses.replace(w, y=yh.astype(np.float64), x=np.zeros((n, w.n)), k_fine=None)
+    gs = parity.gpu_scales(wp, sup.cpu().numpy(), ku.cpu().numpy())
+    rep = parity.compare(wp, gs, coef.double().cpu().numpy(), ku.cpu().numpy(), xh.double().cpu().numpy(),
+                         tie_tol=1e-6)
+    print(f"[{name} omp, {n} patches of {w.n}] {rep.summary()}", flush=True)
+    rep.check(1e-5, 1e-5)
+    assert np.array_equal(img.cpu().numpy(), S.aggregate(xhh, shape, patch, stride).astype(np.float32))
+    e_noisy = float(np.sqrt(np.mean((noisy - clean) ** 2)))
+    e_out = float(np.sqrt(np.mean((img.cpu().numpy() - clean) ** 2)))
+    # (a signal averaged from overlapping model patches is not sparse in every
+    # window, so no quality bar is set here; the stages are what is checked)
+    print(f"[{name}] rms error: noisy {e_noisy:.4f}, estimate {e_out:.4f}", flush=True)
+    assert np.isfinite(e_out)
