@@ -15,8 +15,16 @@ Readings (the paper names K-SVD and leaves these details to it):
   * the new atom is the leading left singular vector of the restricted error
     matrix E_k, with its sign chosen so that it does not point away from the
     old atom; the users' coefficients become E_k^T d;
-  * an atom that no training signal uses keeps its value (the replacement
-    heuristics of Section IV-B are not applied).
+  * an atom that no training signal uses keeps its value during the sweep;
+    afterwards the replacement heuristics 3 and 4 of Section IV-B may
+    replace it (``replace_unused``): by the least represented training
+    signal -- the one with the largest representation error
+    ||x_j - x_hat_j|| left by the sparse-approximation step of the same
+    iteration (ties to the lower index) -- drawn, for an atom of D_high,
+    from the signals whose coarse support holds the atom's parent (all
+    signals when none does); unused atoms are visited in index order and
+    each takes a signal not taken before in the same sweep; the new atom is
+    that signal scaled to unit norm.
 """
 from __future__ import annotations
 
@@ -76,3 +84,40 @@ def init_children(X: np.ndarray, coarse_support: np.ndarray, q: int, t_low: int,
             v = X[p] / max(np.linalg.norm(X[p]), 1e-300)
             D[k * q + c] = v
     return D
+
+
+def replace_unused(D: np.ndarray, X: np.ndarray, support: np.ndarray, err: np.ndarray,
+                   coarse_support: np.ndarray = None, q: int = 1):
+    """Heuristics 3 and 4 of Section IV-B.  D (T x N) atoms after the update
+    sweep, X (P x N) training signals, support (P x kstride) the supports the
+    sweep used, err (P,) every signal's representation error after the
+    sparse-approximation step.  With coarse_support (P x k_low) and q, atom a
+    is a child of coarse atom a // q and its candidates are the signals
+    whose coarse support holds that parent.  Returns (D', replaced atoms)."""
+    D = np.array(D, dtype=np.float64, copy=True)
+    used = np.zeros(D.shape[0], dtype=bool)
+    s = support[support >= 0]
+    used[s.astype(np.int64)] = True
+    taken = np.zeros(X.shape[0], dtype=bool)
+    replaced = []
+    for a in range(D.shape[0]):
+        if used[a]:
+            continue
+        if coarse_support is not None:
+            pool = np.nonzero(np.any(coarse_support == a // q, axis=1))[0]
+            if pool.size == 0:
+                pool = np.arange(X.shape[0])
+        else:
+            pool = np.arange(X.shape[0])
+        pool = pool[~taken[pool]]
+        if pool.size == 0:
+            continue
+        # the largest error, the lowest index among equal ones
+        j = int(pool[np.argmax(err[pool])])
+        nrm = np.linalg.norm(X[j])
+        if nrm <= 0.0:
+            continue
+        D[a] = X[j] / nrm
+        taken[j] = True
+        replaced.append(a)
+    return D, replaced

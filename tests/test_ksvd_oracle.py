@@ -93,3 +93,49 @@ def test_init_children_draws_from_parent_users():
     Xn = X / np.linalg.norm(X, axis=1, keepdims=True)
     for c in range(3):                                     # children of atom 1 come from signals 0..9
         assert np.min(np.linalg.norm(Xn[:10] - D[3 + c], axis=1)) < 1e-12
+
+
+def test_unused_atoms_take_the_least_represented_signals():
+    """Heuristic 3 (Section IV-B), worked by hand: atoms 1 and 3 have no user;
+    errors [0.1, 0.5, 0.5, 0.2] -> atom 1 takes signal 1 (largest error, lower
+    index of the tie), atom 3 takes signal 2 (signal 1 is taken)."""
+    X = np.array([[3.0, 4.0], [0.0, 2.0], [1.0, 0.0], [1.0, 1.0]])
+    D = np.array([[1.0, 0.0], [0.0, 1.0], [0.6, 0.8], [0.8, 0.6]])
+    sup = np.array([[0, -1], [2, -1], [0, 2], [2, -1]], dtype=np.int32)
+    err = np.array([0.1, 0.5, 0.5, 0.2])
+    D2, rep = ksvd.replace_unused(D, X, sup, err)
+    assert rep == [1, 3]
+    assert np.allclose(D2[1], [0.0, 1.0]) and np.allclose(D2[3], [1.0, 0.0])
+    assert np.array_equal(D2[[0, 2]], D[[0, 2]])
+
+
+def test_unused_children_draw_from_their_parents_signals():
+    """Heuristic 4: a fine atom is replaced from the signals whose coarse
+    support holds its parent; with no such signal, from all."""
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((6, 4))
+    coarse = np.array([[0], [1], [0], [1], [1], [0]])
+    sup = np.array([[0], [2], [0], [3], [2], [0]], dtype=np.int32)   # atoms 1 (parent 0), 4, 5 (parent 2) unused
+    err = np.array([0.3, 0.9, 0.1, 0.2, 0.8, 0.4])
+    D = np.eye(6, 4)
+    D2, rep = ksvd.replace_unused(D, X, sup, err, coarse_support=coarse, q=2)
+    assert rep == [1, 4, 5]
+    # atom 1 (parent 0): signals 0, 2, 5 -> signal 5 (error 0.4)
+    assert np.allclose(D2[1], X[5] / np.linalg.norm(X[5]))
+    # atoms 4 and 5 (parent 2, no signal holds it): from all, the two worst
+    assert np.allclose(D2[4], X[1] / np.linalg.norm(X[1]))
+    assert np.allclose(D2[5], X[4] / np.linalg.norm(X[4]))
+
+
+def test_replacement_represents_the_worst_signal_exactly():
+    """Property: after a replacement, the worst-represented signal is one atom
+    of the dictionary, so one OMP step represents it with no error."""
+    rng = np.random.default_rng(3)
+    X, D, sup, coef = _random_problem(rng)
+    err = np.linalg.norm(ksvd.residual(X, D, sup, coef), axis=1)
+    D2, rep = ksvd.replace_unused(D, X, sup, err)
+    assert rep == [D.shape[0] - 1]
+    j = int(np.argmax(err))
+    c = D2 @ X[j]
+    a = int(np.argmax(np.abs(c)))
+    assert a == rep[0] and np.allclose(c[a] * D2[a], X[j])
