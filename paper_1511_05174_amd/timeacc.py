@@ -18,8 +18,9 @@ Section III with model dictionaries: children = the upsampled parent plus
 detail), with white noise added here at the stated input SNR.  In the
 video study the single-scale dictionary of T atoms is the model's fine
 dictionary restricted to T of its atoms (a fixed random choice; T = 8192 is
-all of it) -- or, with ``trained=True``, a K-SVD dictionary of T atoms
-learned on a training set from the same model.  Everything runs on the
+all of it): the library's K-SVD update holds atoms of at most 64
+coordinates, so dictionaries of 2048-coordinate atoms are not learned here.
+The Q study learns its dictionaries (8x8 patches).  Everything runs on the
 device through the C-ABI calls; this module only sequences them and times
 them.
 """
@@ -73,8 +74,7 @@ def _video_model(batch: int, seed: int, t_low: int, t_high: int, k_low: int, k_h
 
 def video_time_accuracy(sizes: Sequence[int] = (256, 512, 1024, 4096, 8192), ks: Sequence[int] = (8, 16, 32, 64),
                         zt: tuple = (6, 8), t_low: int = 512, t_high: int = 8192, batch: int = 1024,
-                        snr_db: float = 15.0, seed: int = 71, steps: int = 3, trained: bool = False,
-                        train_patches: int = 8192, train_iters: int = 3) -> dict:
+                        snr_db: float = 15.0, seed: int = 71, steps: int = 3) -> dict:
     """Single-scale full OMP over T atoms at each K, and zero-tree OMP at
     (K_low, K_high) = zt, on the same noisy 8x8x32 video patches.  Returns a
     dict with the points (ms per call, patches/s, PSNR) and, for every
@@ -88,7 +88,8 @@ def video_time_accuracy(sizes: Sequence[int] = (256, 512, 1024, 4096, 8192), ks:
     y = add_noise(x, snr_db, rng)
     Y = torch.from_numpy(np.ascontiguousarray(y, dtype=np.float32)).to(dev)
     out = {"patches": batch, "shape": "8x8x32 video patches (2048 samples), coarse 4x4x16 (256)",
-           "snr_in_db": snr_db, "psnr_noisy_db": psnr_db(x, y), "dictionaries": "trained" if trained else "model",
+           "snr_in_db": snr_db, "psnr_noisy_db": psnr_db(x, y),
+           "dictionaries": "model (single-scale: T atoms of the fine model dictionary)",
            "zero_tree": None, "single_scale": []}
     # zero-tree OMP over the two-scale model dictionary
     plan = cspd.cspd_plan(w.dims, w.atoms, w.dicts, w.up_maps, "identity", w.m, None, dtype="f32", k_max=16)
@@ -104,21 +105,9 @@ def video_time_accuracy(sizes: Sequence[int] = (256, 512, 1024, 4096, 8192), ks:
     cspd.cspd_plan_destroy(plan)
     # single-scale dictionaries
     perm = np.random.default_rng(seed + 2).permutation(t_high)
-    if trained:
-        from . import train
-
-        wt, _ = _video_model(train_patches, seed + 3, t_low, t_high, zt[0], zt[1])
-        xt = add_noise(wt.x, snr_db, np.random.default_rng(seed + 4))
     kmax = max(ks)
     for T in sizes:
-        if trained:
-            d0 = wt.x[np.random.default_rng(seed + 5).choice(train_patches, size=min(T, train_patches),
-                                                               replace=False)]
-            d0 = d0 / np.maximum(np.linalg.norm(d0, axis=1, keepdims=True), 1e-30)
-            d, _, _ = train.ksvd(xt, d0, zt[1], train_iters)
-            d = d.astype(np.float64)
-        else:
-            d = w.dicts[1][np.sort(perm[:T])]
+        d = w.dicts[1][np.sort(perm[:T])]
         plan = cspd.cspd_plan([w.n], [d.shape[0]], [d], [], "identity", w.n, None, dtype="f32", k_max=kmax)
         for K in ks:
             def full_call(K=K):
@@ -197,11 +186,10 @@ def main(argv: Optional[Sequence[str]] = None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--study", choices=["video", "q"], default="video")
     ap.add_argument("--batch", type=int, default=1024)
-    ap.add_argument("--trained", action="store_true", help="K-SVD single-scale dictionaries (video study)")
     ap.add_argument("--steps", type=int, default=3)
     args = ap.parse_args(argv)
     if args.study == "video":
-        res = video_time_accuracy(batch=args.batch, trained=args.trained, steps=args.steps)
+        res = video_time_accuracy(batch=args.batch, steps=args.steps)
     else:
         res = q_effect()
     print(json.dumps(res))
