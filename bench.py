@@ -153,10 +153,12 @@ def equal_psnr_phase(cspd, w, plan, timed):
     return equal
 
 
-def workloads_phase(cspd, names=("c1", "c3", "c4"), steps: int = 10, warmup: int = 2):
+def workloads_phase(cspd, names=("c1", "c3", "c4", "c4loc", "bayer", "lfca"), steps: int = 10, warmup: int = 2):
     """The other configurations at their full sizes, same timing as the
     headline (inputs resident, one cross-scale call per step, per-kernel
-    durations from the dispatches' own timestamps)."""
+    durations from the dispatches' own timestamps); the structured-operator
+    workloads (location-dependent coded exposure through the per-patch
+    operator call, Bayer demosaicing, coded-aperture light fields) too."""
     import torch
     import synth
     res = {}
@@ -176,10 +178,15 @@ def workloads_phase(cspd, names=("c1", "c3", "c4"), steps: int = 10, warmup: int
         ku = torch.empty((B,), dtype=torch.int32, device=dev)
         xh = torch.empty((B, w.n), dtype=tdt, device=dev)
         stream = torch.cuda.current_stream()
+        ph = None if w.phase is None else torch.from_numpy(np.ascontiguousarray(w.phase, dtype=np.int32)).to(dev)
 
         def step():
-            cspd.cspd_omp_cross_scale(plan, y, mask, ks[:-1], kf, ks[-1], support=sup, coef=coef,
-                                      k_used=ku, xhat=xh, stream=stream)
+            if ph is not None:
+                cspd.cspd_omp_cross_scale_phased(plan, ph, y, mask, ks[:-1], kf, ks[-1], support=sup, coef=coef,
+                                                 k_used=ku, xhat=xh, stream=stream)
+            else:
+                cspd.cspd_omp_cross_scale(plan, y, mask, ks[:-1], kf, ks[-1], support=sup, coef=coef,
+                                          k_used=ku, xhat=xh, stream=stream)
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
@@ -202,7 +209,9 @@ def workloads_phase(cspd, names=("c1", "c3", "c4"), steps: int = 10, warmup: int
         res[name] = {
             "workload": f"{name}: {B} patches, dims {w.dims}, atoms {w.atoms}, K {ks}"
                         + (" (finest K per patch)" if w.k_fine is not None else "")
-                        + f", phi {w.phi_kind}, {w.dtype}",
+                        + f", phi {w.phi_kind}"
+                        + (f" ({int(np.max(w.phase)) + 1} operators chosen per patch)" if w.phase is not None else "")
+                        + f", {w.dtype}",
             "patches_per_s": B / t, "ms_per_call": t * 1e3, "dtype": w.dtype,
             "roofline": {"bound": bound_of(label), "achieved": achieved, "peak": peak,
                          "unit": "TFLOP/s", "frac": None if achieved is None else achieved / peak,
@@ -211,7 +220,7 @@ def workloads_phase(cspd, names=("c1", "c3", "c4"), steps: int = 10, warmup: int
         }
         print(f"[bench] {name}: {B / t / 1e6:.1f} M patches/s, {t * 1e3:.3f} ms/call, dominant {label} "
               f"{avg_ms:.3f} ms", file=sys.stderr, flush=True)
-        del y, mask, kf, sup, coef, ku, xh, plan
+        del y, mask, kf, sup, coef, ku, xh, plan, ph
         torch.cuda.synchronize()
     return res
 

@@ -54,11 +54,73 @@ struct Shared {
 };
 
 template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
+__device__ __forceinline__ T wave_sum(T v);
+
+// Row-local DPP moves (quad xor 1 and 2, half-row mirror, row mirror) sum a
+// value over each row of 16 lanes; permlane16 and permlane32 swaps then add
+// the partner rows.  Every lane of the wavefront must be active (the callers
+// loop over wavefront-uniform bounds); every lane ends with the sum.
+template <int CTRL>
+__device__ __forceinline__ int dpp_row(int v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ float sum_pairs(float v)
+{
+    auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+    v = __int_as_float(r16[0]) + __int_as_float(r16[1]);
+    auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+    return __int_as_float(r32[0]) + __int_as_float(r32[1]);
+}
+
+template <>
+__device__ __forceinline__ float wave_sum<float>(float v)
+{
+    v += __int_as_float(dpp_row<0xB1>(__float_as_int(v)));
+    v += __int_as_float(dpp_row<0x4E>(__float_as_int(v)));
+    v += __int_as_float(dpp_row<0x141>(__float_as_int(v)));
+    v += __int_as_float(dpp_row<0x140>(__float_as_int(v)));
+    return sum_pairs(v);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_row_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_row<CTRL>((int)b), hi = dpp_row<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ void swap_d(double v, bool wide, double &a, double &b)
+{
+    const long long bits = __double_as_longlong(v);
+    int l0, l1, h0, h1;
+    if (wide) {
+        auto rl = __builtin_amdgcn_permlane32_swap((int)bits, (int)bits, false, false);
+        auto rh = __builtin_amdgcn_permlane32_swap((int)(bits >> 32), (int)(bits >> 32), false, false);
+        l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
+    } else {
+        auto rl = __builtin_amdgcn_permlane16_swap((int)bits, (int)bits, false, false);
+        auto rh = __builtin_amdgcn_permlane16_swap((int)(bits >> 32), (int)(bits >> 32), false, false);
+        l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
+    }
+    a = __longlong_as_double(((long long)h0 << 32) | (unsigned)l0);
+    b = __longlong_as_double(((long long)h1 << 32) | (unsigned)l1);
+}
+
+template <>
+__device__ __forceinline__ double wave_sum<double>(double v)
+{
+    v += dpp_row_d<0xB1>(v);
+    v += dpp_row_d<0x4E>(v);
+    v += dpp_row_d<0x141>(v);
+    v += dpp_row_d<0x140>(v);
+    double x, y;
+    swap_d(v, false, x, y);
+    v = x + y;
+    swap_d(v, true, x, y);
+    return x + y;
 }
 
 template <typename T>

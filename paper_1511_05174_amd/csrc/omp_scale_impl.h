@@ -1314,9 +1314,11 @@ void k_omp_scale(ScaleArgs a)
                 for (int j = 0; j < CH; ++j) cur[j] = nxt[j];
             }
         } else {
+            // the patch's operator's table (plans with several operators)
+            const T *gtab = (const T *)a.gram + (int64_t)ph * a.t * a.t;
 #pragma unroll
             for (int s = 0; s < NC; ++s)
-                if (act & (atom[s] != INT_MAX)) gcol[s] = ((const T *)a.gram)[(int64_t)bidx * a.t + atom[s]];
+                if (act & (atom[s] != INT_MAX)) gcol[s] = gtab[(int64_t)bidx * a.t + atom[s]];
         }
 #pragma unroll
         for (int s = 0; s < NC; ++s) {

@@ -180,11 +180,15 @@ cspd_status finish_scale(ScalePlan &sc, const double *a64, const double *w64, bo
         CSPD_HIP_CHECK(hipGetLastError());
     }
     if (want_gram) {
-        size_t gb = sizeof(T) * (size_t)sc.t * sc.t;
+        // one t x t table per operator phase (w64 holds the phases' rows back to back)
+        size_t gb = sizeof(T) * (size_t)sc.t * sc.t * phases;
         CSPD_HIP_CHECK(hipMalloc(&sc.gram, gb));
         bytes += gb;
-        k_gram<T><<<blocks_for((int64_t)sc.t * sc.t, bs), bs, 0, st>>>(w64, sc.t, sc.l, (T *)sc.gram);
-        CSPD_HIP_CHECK(hipGetLastError());
+        for (int ph = 0; ph < phases; ++ph) {
+            k_gram<T><<<blocks_for((int64_t)sc.t * sc.t, bs), bs, 0, st>>>(
+                w64 + (size_t)ph * sc.t * sc.l, sc.t, sc.l, (T *)sc.gram + (size_t)ph * sc.t * sc.t);
+            CSPD_HIP_CHECK(hipGetLastError());
+        }
     }
     return CSPD_OK;
 }
@@ -293,7 +297,11 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
         // Gram matrix, 16-bit copy) do not exist; the kernels that need them
         // are not used
         const bool norms = !mask && P == 1;
-        const bool gram = !mask && P == 1 && T <= kMaxGramAtoms && (s == 0 || s == S - 1) && sc.lp <= kMaxShortLen;
+        // Gram tables: one per operator; with several operators only at the
+        // first scale (a full search there), within 64 MB
+        const bool gram = !mask && T <= kMaxGramAtoms && sc.lp <= kMaxShortLen &&
+                          ((P == 1 && (s == 0 || s == S - 1)) ||
+                           (P > 1 && s == 0 && (int64_t)P * T * T * 4 <= ((int64_t)64 << 20)));
         // 16-bit copies for the reduced-precision proxy: full search at the
         // finest scale, and the first scale's batched contraction under a
         // shared dense operator

@@ -49,16 +49,22 @@ def add_noise(x: np.ndarray, snr_db: float, rng: np.random.Generator) -> np.ndar
     return x + sigma * rng.standard_normal(x.shape)
 
 
-def _timed(fn, steps: int) -> float:
-    """Seconds per call (mean over `steps` calls after one untimed call)."""
+def _timed(fn, steps: int):
+    """Seconds per call (mean over `steps` calls after one untimed call) and
+    each kernel's mean duration in ms (the library's dispatch timestamps)."""
     torch = cspd._torch()
     fn()
     torch.cuda.synchronize()
+    cspd.cspd_profile_reset()
+    cspd.cspd_profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    sec = (time.perf_counter() - t0) / steps
+    cspd.cspd_profile_enable(False)
+    prof = {k: v[1] / max(v[0], 1) for k, v in cspd.cspd_profile_read().items()}
+    return sec, prof
 
 
 def _video_model(batch: int, seed: int, t_low: int, t_high: int, k_low: int, k_high: int):
@@ -98,10 +104,10 @@ def video_time_accuracy(sizes: Sequence[int] = (256, 512, 1024, 4096, 8192), ks:
     def zt_call():
         res["r"] = cspd.cspd_omp_cross_scale(plan, Y, None, [zt[0]], None, zt[1])
 
-    sec = _timed(zt_call, steps)
+    sec, prof = _timed(zt_call, steps)
     xh = res["r"][3].double().cpu().numpy()
     out["zero_tree"] = {"t_low": t_low, "t_high": t_high, "k_low": zt[0], "k_high": zt[1], "ms_per_call": sec * 1e3,
-                        "patches_per_s": batch / sec, "psnr_db": psnr_db(x, xh)}
+                        "patches_per_s": batch / sec, "psnr_db": psnr_db(x, xh), "kernels_ms": prof}
     cspd.cspd_plan_destroy(plan)
     # single-scale dictionaries
     perm = np.random.default_rng(seed + 2).permutation(t_high)
@@ -113,10 +119,20 @@ def video_time_accuracy(sizes: Sequence[int] = (256, 512, 1024, 4096, 8192), ks:
             def full_call(K=K):
                 res["r"] = cspd.cspd_omp_full(plan, Y, None, None, K)
 
-            sec = _timed(full_call, steps)
+            sec, prof = _timed(full_call, steps)
             xh = res["r"][3].double().cpu().numpy()
-            out["single_scale"].append({"atoms": int(d.shape[0]), "k": int(K), "ms_per_call": sec * 1e3,
-                                        "patches_per_s": batch / sec, "psnr_db": psnr_db(x, xh)})
+            pt = {"atoms": int(d.shape[0]), "k": int(K), "ms_per_call": sec * 1e3,
+                  "patches_per_s": batch / sec, "psnr_db": psnr_db(x, xh), "kernels_ms": prof}
+            # coefficient-coordinate kernel: its algorithmic bytes are the
+            # Gram rows of the support, 4 T (1 + ... + K) per patch (the
+            # FP64 correlations and Gram entries are smaller terms)
+            kb = [v for k_, v in prof.items() if k_.startswith("omp_batch")]
+            if kb:
+                by = 4.0 * d.shape[0] * K * (K + 1) / 2 * batch
+                pt["gram_bytes_per_call"] = by
+                pt["gram_gb_per_s"] = by / (kb[0] * 1e-3) / 1e9
+                pt["hbm_frac"] = pt["gram_gb_per_s"] / 8000.0
+            out["single_scale"].append(pt)
         cspd.cspd_plan_destroy(plan)
     z = out["zero_tree"]
     for p in out["single_scale"]:
