@@ -19,7 +19,9 @@
 //   project  L L^T alpha = A_Omega^T y by two FP64 triangular solves;
 //   residue  r = y - A_Omega alpha, summed in FP64 and kept in FP32.
 // The least squares are thus FP64 on the stored (rounded) vectors, as in the
-// FP64 oracle; only the proxy is FP32.
+// FP64 oracle; only the proxy is FP32.  Patches with at most 64 candidates
+// (the finer scales of Algorithm 2) take the Gram mode further down, which
+// reads each candidate once and iterates in coefficient coordinates.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -123,6 +125,80 @@ __device__ __forceinline__ double wave_sum<double>(double v)
     return x + y;
 }
 
+// Measurement of patch b in the scale's coordinates (yhat) and the weight of
+// each coordinate (sqw: the square root of the observed fine samples folded
+// into it; 1 or 0 without blocks); st_y and st_c (n entries each) stage the
+// observed fine samples of block folds.  *count (zeroed here) receives the
+// coordinates of nonzero weight once the caller's next barrier has passed.
+template <typename T>
+__device__ void measure(const ScaleArgs &a, int64_t b, T *yhat, T *sqw, T *st_y, T *st_c, int *count)
+{
+    const int tid = threadIdx.x;
+    const T *y = (const T *)a.y + b * (int64_t)a.y_stride;
+    const int lp = a.lp, l = a.l;
+    const bool fold = a.fold == kFold;
+    const uint8_t *mrow = (fold && a.mask) ? a.mask + b * (int64_t)a.n : nullptr;
+    if (tid == 0) *count = 0;
+    if (!fold) {
+        for (int t = tid; t < lp; t += kThreads) {
+            yhat[t] = t < l ? y[t] : T(0);
+            sqw[t] = t < l ? T(1) : T(0);
+        }
+    } else if (a.blk_ident) {
+        for (int t = tid; t < lp; t += kThreads) {
+            const bool obs = t < l && (mrow ? mrow[t] != 0 : true);
+            yhat[t] = obs ? y[t] : T(0);
+            sqw[t] = obs ? T(1) : T(0);
+        }
+    } else {
+        // blocks of several fine samples: stage the observed samples, then
+        // each coordinate folds its block (sum / sqrt(count), weight sqrt(count))
+        for (int j = tid; j < a.n; j += kThreads) {
+            const bool obs = mrow ? mrow[j] != 0 : true;
+            st_y[j] = obs ? y[j] : T(0);
+            st_c[j] = obs ? T(1) : T(0);
+        }
+        __syncthreads();
+        for (int t = tid; t < lp; t += kThreads) {
+            T cnt = 0, acc = 0;
+            if (t < l) {
+                for (int jj = a.blk_off[t]; jj < a.blk_off[t + 1]; ++jj) {
+                    const int j = a.blk_idx[jj];
+                    cnt += st_c[j];
+                    acc += st_y[j];
+                }
+            }
+            const T sq = sqrt(cnt);
+            yhat[t] = cnt > T(0) ? acc / sq : T(0);
+            sqw[t] = sq;
+        }
+    }
+    __syncthreads();
+    int c = 0;
+    for (int t = tid; t < lp; t += kThreads) c += sqw[t] > T(0);
+    atomicAdd(count, c);
+}
+
+// Candidate atoms of patch b: every atom at the first scale, else the
+// children of the previous scale's support (Algorithm 2), at most cap of
+// them (the launch sizes cap to the largest count).  Returns how many.
+__device__ int candidates(const ScaleArgs &a, int64_t b, int *cand, int cap)
+{
+    const int tid = threadIdx.x;
+    int nc = a.first ? a.t : a.prev_kused[b] * a.q;
+    nc = nc < cap ? nc : cap;
+    if (a.first) {
+        for (int i = tid; i < nc; i += kThreads) cand[i] = i;
+        return nc;
+    }
+    for (int i = tid; i < nc; i += kThreads) {
+        const int pj = i / a.q;
+        const int parent = a.prev_sup[b * (int64_t)a.prev_stride + pj];
+        cand[i] = parent * a.q + (i - pj * a.q);
+    }
+    return nc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
 {
@@ -132,7 +208,6 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
     const int wv = tid >> 6;
     const int64_t b = blockIdx.x;
     if (b >= a.b) return;
-    const T *y = (const T *)a.y + b * (int64_t)a.y_stride;
     // operator of the patch (plans with several); out of range: unsolved
     int ph = a.phase ? a.phase[b] : 0;
     const bool phok = ph >= 0 && ph < a.n_phases;
@@ -140,64 +215,9 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
     const T *v = (const T *)a.v + (int64_t)ph * a.phase_stride;
     const int lp = a.lp, l = a.l;
     const bool fold = a.fold == kFold;
-    const uint8_t *mrow = (fold && a.mask) ? a.mask + b * (int64_t)a.n : nullptr;
 
-    // ---- measurement in the scale's coordinates and its weights ------------
-    if (tid == 0) sh.count = 0;
-    if (!fold) {
-        for (int t = tid; t < lp; t += kThreads) {
-            sh.yhat[t] = t < l ? y[t] : T(0);
-            sh.sqw[t] = t < l ? T(1) : T(0);
-        }
-    } else if (a.blk_ident) {
-        for (int t = tid; t < lp; t += kThreads) {
-            const bool obs = t < l && (mrow ? mrow[t] != 0 : true);
-            sh.yhat[t] = obs ? y[t] : T(0);
-            sh.sqw[t] = obs ? T(1) : T(0);
-        }
-    } else {
-        // blocks of several fine samples: stage the observed samples, then
-        // each coordinate folds its block (sum / sqrt(count), weight sqrt(count))
-        for (int j = tid; j < a.n; j += kThreads) {
-            const bool obs = mrow ? mrow[j] != 0 : true;
-            sh.rw[j] = obs ? y[j] : T(0);
-            sh.tmp[j] = obs ? T(1) : T(0);
-        }
-        __syncthreads();
-        for (int t = tid; t < lp; t += kThreads) {
-            T cnt = 0, acc = 0;
-            if (t < l) {
-                for (int jj = a.blk_off[t]; jj < a.blk_off[t + 1]; ++jj) {
-                    const int j = a.blk_idx[jj];
-                    cnt += sh.tmp[j];
-                    acc += sh.rw[j];
-                }
-            }
-            const T sq = sqrt(cnt);
-            sh.yhat[t] = cnt > T(0) ? acc / sq : T(0);
-            sh.sqw[t] = sq;
-        }
-    }
-    __syncthreads();
-    {
-        int c = 0;
-        for (int t = tid; t < lp; t += kThreads) c += sh.sqw[t] > T(0);
-        atomicAdd(&sh.count, c);
-    }
-    // ---- candidates ------------------------------------------------------
-    int nc = 0;
-    if (a.first) {
-        nc = a.t;
-        for (int i = tid; i < nc; i += kThreads) sh.cand[i] = i;
-    } else {
-        const int kp = a.prev_kused[b];
-        nc = kp * a.q;
-        for (int i = tid; i < nc; i += kThreads) {
-            const int pj = i / a.q;
-            const int parent = a.prev_sup[b * (int64_t)a.prev_stride + pj];
-            sh.cand[i] = parent * a.q + (i - pj * a.q);
-        }
-    }
+    measure(a, b, sh.yhat, sh.sqw, sh.rw, sh.tmp, &sh.count);
+    const int nc = candidates(a, b, sh.cand, kMaxLongCand);
     for (int t = tid; t < lp; t += kThreads) sh.rw[t] = sh.sqw[t] * sh.yhat[t];
     __syncthreads();
     const int rank_bound = fold ? sh.count : a.m_dense;
@@ -351,6 +371,288 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Gram mode: at most kGramCand candidates.  The patch's weighted candidate
+// Gram matrix G = A^T W A (W: the squared coordinate weights) and the
+// correlations h = A^T sqrt(W) yhat (yhat is the folded measurement, which
+// carries the other factor) are formed once, as FP64 sums over the
+// coordinates of nonzero weight only, from the candidates' stored values;
+// the iterations then run in coefficient coordinates (Batch-OMP, Section
+// II-B): the proxy is c = h - G[:, Omega] alpha, the Cholesky row of a new
+// atom reads its entries of G, and no candidate vector is read again.  Each
+// candidate row leaves HBM once instead of once per iteration, and a mask
+// leaves its unobserved coordinates out of the arithmetic.
+//
+// Formation: the observed coordinates are listed in ascending order; chunks
+// of kCh of them are staged in LDS as FP64 weighted values (exact products
+// of the FP32 candidate value and weight), the next chunk's loads in flight
+// while the current one is multiplied.  G is symmetric: its 136 upper 4x4
+// blocks go to wavefronts 0 and 1 (one block per lane) and, for the last 8,
+// to wavefront 2 (eight lanes per block, each taking every eighth
+// coordinate, summed in a fixed order at the end); wavefront 3 forms h.
+// Only the upper triangle is kept (packed rows).
+constexpr int kGramCand = 64;
+constexpr int kGramTri = kGramCand * (kGramCand + 1) / 2;
+constexpr int kCh = 16;
+constexpr int kXld = kGramCand + 2;   // keeps rows 16-byte aligned and spreads the staging stores over banks
+constexpr int kGBlk = kGramCand / 4;  // 4x4 blocks per row of G
+
+template <typename T>
+struct GramShared {
+    T yhat[kMaxLongLen];
+    T sqw[kMaxLongLen];
+    union {
+        T stage[2 * kMaxLongLen];   // block-fold staging (measurement only)
+        double G[kGramTri];         // packed upper triangle of the weighted Gram matrix
+    } u;
+    int idx[kMaxLongLen];           // coordinates of nonzero weight, ascending
+    alignas(16) double X[kCh][kXld];  // staged chunk: weighted candidate values [coordinate][slot]
+    double yw[kCh];                 // yhat at the chunk's coordinates (already folded: one weight factor)
+    double h[kGramCand];            // weighted correlations with the measurement
+    int cand[kGramCand];
+    double L[KX * KX];
+    double z[KX];
+    double alpha[KX];
+    int slot[KX];
+    int sup[KX];
+    int wcnt[kWaves];
+    int count;
+    int nsel;
+};
+
+__device__ __forceinline__ int tri(int i, int j)
+{
+    const int r = i < j ? i : j, c = i < j ? j : i;
+    return r * kGramCand - ((r * (r - 1)) >> 1) + (c - r);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
+{
+    __shared__ GramShared<T> sh;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int64_t b = blockIdx.x;
+    if (b >= a.b) return;
+    int ph = a.phase ? a.phase[b] : 0;
+    const bool phok = ph >= 0 && ph < a.n_phases;
+    ph = phok ? ph : 0;
+    const T *v = (const T *)a.v + (int64_t)ph * a.phase_stride;
+    const int lp = a.lp;
+    const bool fold = a.fold == kFold;
+
+    measure(a, b, sh.yhat, sh.sqw, sh.u.stage, sh.u.stage + kMaxLongLen, &sh.count);
+    const int nc = candidates(a, b, sh.cand, kGramCand);
+
+    // ---- observed coordinates, ascending (each wavefront a contiguous range)
+    const int seg = ((lp + kThreads - 1) / kThreads) * 64;
+    const int lo = wv * seg;
+    {
+        int c = 0;
+        for (int t0 = lo; t0 < lo + seg; t0 += 64) {
+            const int t = t0 + lane;
+            c += __popcll(__ballot(t < lp && sh.sqw[t] > T(0)));
+        }
+        if (lane == 0) sh.wcnt[wv] = c;
+    }
+    __syncthreads();
+    const int rank_bound = fold ? sh.count : a.m_dense;
+    const int kreq = a.kvec ? a.kvec[b] : a.kuni;
+    int K = kreq < nc ? kreq : nc;
+    K = phok ? K : 0;
+    K = K < a.sup_count ? K : a.sup_count;
+    K = K < KX ? K : KX;
+    K = K > 0 ? K : 0;
+    int M = 0, base = 0;
+    for (int w = 0; w < kWaves; ++w) {
+        base += w < wv ? sh.wcnt[w] : 0;
+        M += sh.wcnt[w];
+    }
+    for (int t0 = lo; t0 < lo + seg; t0 += 64) {
+        const int t = t0 + lane;
+        const bool o = t < lp && sh.sqw[t] > T(0);
+        const unsigned long long m = __ballot(o);
+        if (o) sh.idx[base + __popcll(m & ((1ull << lane) - 1ull))] = t;
+        base += __popcll(m);
+    }
+    __syncthreads();
+
+    if (K > 0) {
+        // ---- G and h over the observed coordinates ---------------------------
+        // staging: element e = tid + 256 r is slot e / kCh, chunk coordinate e % kCh
+        constexpr int kPer = kGramCand * kCh / kThreads;
+        const int spp = tid % kCh;
+        const T *rowp[kPer];
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int i = (tid + r * kThreads) / kCh;
+            rowp[r] = i < nc ? v + (int64_t)sh.cand[i] * lp : nullptr;
+        }
+        T pre[kPer];
+        int pt = -1;
+        auto fetch = [&](int p0) {
+            const int p = p0 + spp;
+            pt = p < M ? sh.idx[p] : -1;
+#pragma unroll
+            for (int r = 0; r < kPer; ++r) pre[r] = (pt >= 0 && rowp[r]) ? rowp[r][pt] : T(0);
+        };
+        // block of this lane: wavefronts 0, 1 one upper block each; wavefront 2
+        // eight lanes per block (blocks 128..135)
+        const int ub = wv < 2 ? tid : (wv == 2 ? 2 * 64 + (lane >> 3) : 0);
+        int bi = 0, rem = ub;
+        while (rem >= kGBlk - bi) {
+            rem -= kGBlk - bi;
+            ++bi;
+        }
+        const int bj = bi + rem;
+        const int sub = lane & 7;
+        double acc[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+        double hacc = 0.0;
+
+        fetch(0);
+        for (int p0 = 0; p0 < M; p0 += kCh) {
+            __syncthreads();   // the previous chunk has been consumed
+            {
+                const double w = pt >= 0 ? (double)sh.sqw[pt] : 0.0;
+#pragma unroll
+                for (int r = 0; r < kPer; ++r) sh.X[spp][(tid + r * kThreads) / kCh] = (double)pre[r] * w;
+                if (tid < kCh) sh.yw[tid] = pt >= 0 ? (double)sh.yhat[pt] : 0.0;
+            }
+            __syncthreads();
+            if (p0 + kCh < M) fetch(p0 + kCh);
+            if (wv < 3) {
+                const int step = wv < 2 ? 1 : 8;
+                for (int pp = wv < 2 ? 0 : sub; pp < kCh; pp += step) {
+                    const double *xa = &sh.X[pp][4 * bi];
+                    const double *xb = &sh.X[pp][4 * bj];
+                    double ar[4], bc[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        ar[r] = xa[r];
+                        bc[r] = xb[r];
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc[r][c] = fma(ar[r], bc[c], acc[r][c]);
+                }
+            } else {
+#pragma unroll
+                for (int pp = 0; pp < kCh; ++pp) hacc = fma(sh.X[pp][lane], sh.yw[pp], hacc);
+            }
+        }
+        if (wv == 2) {
+            // the eight lanes of a block: fixed-order pairwise sums
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double x = acc[r][c];
+                    x += __shfl_xor(x, 1);
+                    x += __shfl_xor(x, 2);
+                    x += __shfl_xor(x, 4);
+                    acc[r][c] = x;
+                }
+        }
+        __syncthreads();   // the staging area and the measurement staging are free
+        if (wv < 2 || (wv == 2 && sub == 0)) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int gi = 4 * bi + r, gj = 4 * bj + c;
+                    if (gi <= gj) sh.u.G[tri(gi, gj)] = acc[r][c];
+                }
+        }
+        if (wv == 3) sh.h[lane] = hacc;
+        __syncthreads();
+
+        // ---- iterations in coefficient coordinates (wavefront 0) -------------
+        // Every lane runs the merge and the solves with the same values, so
+        // the factor and coefficients each lane reads back are its own writes;
+        // lane i scores candidate slot i.
+        if (wv == 0) {
+            const int ci = lane < nc ? sh.cand[lane] : -1;
+            const double gii = ci >= 0 ? sh.u.G[tri(lane, lane)] : 0.0;
+            bool live = ci >= 0 && gii > 0.0;
+            const double rn = live ? 1.0 / sqrt(gii) : 0.0;
+            const double hi = sh.h[lane];
+            int n = 0;
+            for (int it = 0; it < K; ++it) {
+                double c = hi;
+                for (int j = 0; j < n; ++j) c -= sh.u.G[tri(lane, sh.slot[j])] * sh.alpha[j];
+                double sc = live ? fabs(c) * rn : -1.0;
+                int at = live ? ci : INT_MAX;
+                int ps = live ? lane : -1;
+                // largest score, lowest atom index on exact ties
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const double os = __shfl_xor(sc, off);
+                    const int oa = __shfl_xor(at, off);
+                    const int op = __shfl_xor(ps, off);
+                    const bool up = os > sc || (os == sc && oa < at);
+                    sc = up ? os : sc;
+                    at = up ? oa : at;
+                    ps = up ? op : ps;
+                }
+                if (ps < 0 || n >= rank_bound) break;   // candidates exhausted, or the support spans the space
+                // Cholesky row of the new atom from its entries of G
+                const double ek = sh.u.G[tri(ps, ps)];
+                double d = ek;
+                for (int i = 0; i < n; ++i) {
+                    double s = sh.u.G[tri(ps, sh.slot[i])];
+                    for (int j = 0; j < i; ++j) s -= sh.L[i * KX + j] * sh.L[n * KX + j];
+                    const double wi = s / sh.L[i * KX + i];
+                    sh.L[n * KX + i] = wi;
+                    d -= wi * wi;
+                }
+                if (!(d > 1e-10 * ek)) break;   // dependent on the support
+                const double lnn = sqrt(d);
+                sh.L[n * KX + n] = lnn;
+                double s = sh.h[ps];
+                for (int j = 0; j < n; ++j) s -= sh.L[n * KX + j] * sh.z[j];
+                sh.z[n] = s / lnn;
+                for (int i = n; i >= 0; --i) {
+                    double u = sh.z[i];
+                    for (int j = i + 1; j <= n; ++j) u -= sh.L[j * KX + i] * sh.alpha[j];
+                    sh.alpha[i] = u / sh.L[i * KX + i];
+                }
+                sh.slot[n] = ps;
+                sh.sup[n] = at;
+                live = live && lane != ps;
+                ++n;
+            }
+            if (lane == 0) sh.nsel = n;
+        }
+    } else if (tid == 0) {
+        sh.nsel = 0;
+    }
+    __syncthreads();
+
+    // ---- outputs -----------------------------------------------------------
+    const int n = sh.nsel;
+    if (tid == 0) a.kused_out[b] = n;
+    int *sup_out = a.sup_out + b * (int64_t)a.sup_stride;
+    for (int i = tid; i < a.sup_count; i += kThreads) sup_out[i] = i < n ? sh.sup[i] : -1;
+    if (!a.last) return;
+    T *coef = (T *)a.coef_out + b * (int64_t)a.sup_stride;
+    for (int i = tid; i < a.sup_count; i += kThreads) coef[i] = i < n ? (T)sh.alpha[i] : T(0);
+    if (a.xhat) {
+        const T *dh = (const T *)a.d_high;
+        T *xh = (T *)a.xhat + b * (int64_t)a.n;
+        for (int j = tid; j < a.n; j += kThreads) {
+            double s = 0.0;
+            for (int i = 0; i < n; ++i) s += sh.alpha[i] * (double)dh[(int64_t)sh.sup[i] * a.n + j];
+            xh[j] = (T)s;
+        }
+    }
+}
+
 }  // namespace long_impl
 
 bool long_fits(const ScaleArgs &a, int max_cand)
@@ -363,14 +665,18 @@ cspd_status launch_long(int dtype, const ScaleArgs &a, int max_cand, hipStream_t
     using namespace long_impl;
     if (a.b <= 0) return CSPD_OK;
     if (!long_fits(a, max_cand)) return CSPD_E_UNSUPPORTED;
+    if (dtype != CSPD_F32) return CSPD_E_UNSUPPORTED;
+    const bool gram = max_cand <= kGramCand;
     char label[96];
     if (a.first && a.last)
-        snprintf(label, sizeof(label), "omp_long<f32,lp%d>:full", a.lp);
+        snprintf(label, sizeof(label), "omp_long<f32,%slp%d>:full", gram ? "gram," : "", a.lp);
     else
-        snprintf(label, sizeof(label), "omp_long<f32,lp%d>:s%d", a.lp, a.scale);
-    if (dtype != CSPD_F32) return CSPD_E_UNSUPPORTED;
+        snprintf(label, sizeof(label), "omp_long<f32,%slp%d>:s%d", gram ? "gram," : "", a.lp, a.scale);
     const dim3 grid((unsigned)a.b), block(kThreads);
-    launch_timed(label, k_omp_long<float>, grid, block, 0, st, a);
+    if (gram)
+        launch_timed(label, k_omp_long_gram<float>, grid, block, 0, st, a);
+    else
+        launch_timed(label, k_omp_long<float>, grid, block, 0, st, a);
     CSPD_HIP_CHECK(hipGetLastError());
     return CSPD_OK;
 }
