@@ -35,12 +35,13 @@ namespace long_impl {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int KX = kMaxK;
+constexpr int kCG = 4;   // candidates a wavefront scores at a time (their loads in flight together)
 
 template <typename T>
 struct Shared {
-    T yhat[kMaxLongLen];     // measurement in the scale's coordinates
-    T sqw[kMaxLongLen];      // per-coordinate weight (square root of observed samples)
-    T rw[kMaxLongLen];       // weighted residual sqw * r
+    alignas(16) T yhat[kMaxLongLen];   // measurement in the scale's coordinates
+    alignas(16) T sqw[kMaxLongLen];    // per-coordinate weight (square root of observed samples)
+    alignas(16) T rw[kMaxLongLen];     // weighted residual sqw * r
     T tmp[kMaxLongLen];      // staging of the fine samples' indicators (block folds)
     int cand[kMaxLongCand];  // atom of each candidate slot; -1 once chosen or unusable
     T inv_nu[kMaxLongCand];  // reciprocal weighted norm of each candidate
@@ -202,6 +203,7 @@ __device__ int candidates(const ScaleArgs &a, int64_t b, int *cand, int cap)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
 {
+    static_assert(sizeof(T) == 4, "the candidate loops read FP32 rows as float4");
     __shared__ Shared<T> sh;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -228,16 +230,30 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
     K = K < KX ? K : KX;
     K = K > 0 ? K : 0;
 
-    // ---- weighted norms of the candidates (one wavefront per candidate) ---
-    for (int i = wv; i < nc; i += kWaves) {
-        const T *vi = v + (int64_t)sh.cand[i] * lp;
-        T s = 0;
-        for (int t = lane; t < lp; t += 64) {
-            const T x = vi[t] * sh.sqw[t];
-            s += x * x;
+    // ---- weighted norms of the candidates (kCG per wavefront at a time) ----
+    const int l4 = (l + 3) >> 2;   // 16-byte groups that hold the used coordinates (rows are padded with zeros)
+    const float4 *sqw4 = reinterpret_cast<const float4 *>(sh.sqw);
+    const float4 *rw4 = reinterpret_cast<const float4 *>(sh.rw);
+    for (int i0 = wv * kCG; i0 < nc; i0 += kWaves * kCG) {
+        const float4 *vp[kCG];
+#pragma unroll
+        for (int c = 0; c < kCG; ++c)
+            vp[c] = reinterpret_cast<const float4 *>(v + (int64_t)(i0 + c < nc ? sh.cand[i0 + c] : 0) * lp);
+        float acc[kCG] = {};
+        for (int t4 = lane; t4 < l4; t4 += 64) {
+            const float4 w = sqw4[t4];
+#pragma unroll
+            for (int c = 0; c < kCG; ++c) {
+                const float4 x = vp[c][t4];
+                const float a0 = x.x * w.x, a1 = x.y * w.y, a2 = x.z * w.z, a3 = x.w * w.w;
+                acc[c] += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+            }
         }
-        s = wave_sum(s);
-        if (lane == 0) sh.inv_nu[i] = s > T(0) ? T(1) / sqrt(s) : T(-1);
+#pragma unroll
+        for (int c = 0; c < kCG; ++c) {
+            const float s = wave_sum(acc[c]);
+            if (lane == 0 && i0 + c < nc) sh.inv_nu[i0 + c] = s > 0.f ? 1.f / sqrtf(s) : -1.f;
+        }
     }
     __syncthreads();
     for (int i = tid; i < nc; i += kThreads)
@@ -250,17 +266,34 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
         // proxy and argmax: each wavefront keeps its best (score, slot)
         T best = T(-1);
         int bslot = -1;
-        for (int i = wv; i < nc; i += kWaves) {
-            const int at = sh.cand[i];
-            if (at < 0) continue;   // wavefront-uniform
-            const T *vi = v + (int64_t)at * lp;
-            T s = 0;
-            for (int t = lane; t < lp; t += 64) s += vi[t] * sh.rw[t];
-            s = wave_sum(s);
-            const T sc = fabs(s) * sh.inv_nu[i];
-            const bool up = bslot < 0 || sc > best || (sc == best && at < sh.cand[bslot]);
-            best = up ? sc : best;
-            bslot = up ? i : bslot;
+        for (int i0 = wv * kCG; i0 < nc; i0 += kWaves * kCG) {
+            int at[kCG];
+            const float4 *vp[kCG];
+#pragma unroll
+            for (int c = 0; c < kCG; ++c) {
+                at[c] = i0 + c < nc ? sh.cand[i0 + c] : -1;
+                vp[c] = reinterpret_cast<const float4 *>(v + (int64_t)(at[c] >= 0 ? at[c] : 0) * lp);
+            }
+            bool any = false;
+#pragma unroll
+            for (int c = 0; c < kCG; ++c) any = any || at[c] >= 0;
+            if (!any) continue;   // wavefront-uniform
+            float acc[kCG] = {};
+            for (int t4 = lane; t4 < l4; t4 += 64) {
+                const float4 r = rw4[t4];
+#pragma unroll
+                for (int c = 0; c < kCG; ++c) {
+                    const float4 x = vp[c][t4];
+                    acc[c] += x.x * r.x + x.y * r.y + x.z * r.z + x.w * r.w;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kCG; ++c) {
+                const float sc = fabsf(wave_sum(acc[c])) * (at[c] >= 0 ? sh.inv_nu[i0 + c] : 0.f);
+                const bool up = at[c] >= 0 && (bslot < 0 || sc > best || (sc == best && at[c] < sh.cand[bslot]));
+                best = up ? sc : best;
+                bslot = up ? i0 + c : bslot;
+            }
         }
         if (lane == 0) {
             sh.wbest[wv] = best;

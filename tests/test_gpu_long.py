@@ -49,6 +49,9 @@ def _kernels(plan, w):
     ("img24", "mask", (64, 512), (3, 6), 257),
     ("vid32", "identity", (64, 1024), (4, 8), 129),
     ("lf", "mask", (64, 512), (4, 8), 200),
+    # 70 candidates at the finest scale (above the Gram mode's 64): the
+    # proxy loop, its candidate groups ragged at the end of the list
+    ("img24", "mask", (64, 640), (7, 6), 173),
 ])
 def test_long_cross(shape, phi_kind, atoms, ks, batch):
     w = long_workload(shape, batch, seed=31, atoms=atoms, ks=ks, phi_kind=phi_kind)
