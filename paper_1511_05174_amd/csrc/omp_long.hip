@@ -419,16 +419,17 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
 // Formation: the observed coordinates are listed in ascending order; chunks
 // of kCh of them are staged in LDS as FP64 weighted values (exact products
 // of the FP32 candidate value and weight), the next chunk's loads in flight
-// while the current one is multiplied.  G is symmetric: its 136 upper 4x4
-// blocks go to wavefronts 0 and 1 (one block per lane) and, for the last 8,
-// to wavefront 2 (eight lanes per block, each taking every eighth
-// coordinate, summed in a fixed order at the end); wavefront 3 forms h.
-// Only the upper triangle is kept (packed rows).
+// while the current one is multiplied.  G is symmetric: its ten upper 16x16
+// tiles are FP64 matrix-core products (16x16x4: one LDS double per lane per
+// tile and step, where 4x4 register blocks on the vector units read eight
+// per sixteen FMAs and waited on LDS), three tiles for each of three
+// wavefronts and one for the fourth, which also forms h.  The roles rotate
+// with the workgroup index.  Only the upper triangle is kept (packed rows).
 constexpr int kGramCand = 64;
 constexpr int kGramTri = kGramCand * (kGramCand + 1) / 2;
 constexpr int kCh = 16;
 constexpr int kXld = kGramCand + 2;   // keeps rows 16-byte aligned and spreads the staging stores over banks
-constexpr int kGBlk = kGramCand / 4;  // 4x4 blocks per row of G
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct GramShared {
@@ -446,7 +447,6 @@ struct GramShared {
     double L[KX * KX];
     double z[KX];
     double alpha[KX];
-    int slot[KX];
     int sup[KX];
     int wcnt[kWaves];
     int count;
@@ -474,6 +474,9 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
     const T *v = (const T *)a.v + (int64_t)ph * a.phase_stride;
     const int lp = a.lp;
     const bool fold = a.fold == kFold;
+    // the wavefronts' roles in the formation rotate with the workgroup, so
+    // that the workgroups sharing a CU do not load the same SIMDs
+    const int role = (wv + (int)(b & 3)) & 3;
 
     measure(a, b, sh.yhat, sh.sqw, sh.u.stage, sh.u.stage + kMaxLongLen, &sh.count);
     const int nc = candidates(a, b, sh.cand, kGramCand);
@@ -530,21 +533,22 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
 #pragma unroll
             for (int r = 0; r < kPer; ++r) pre[r] = (pt >= 0 && rowp[r]) ? rowp[r][pt] : T(0);
         };
-        // block of this lane: wavefronts 0, 1 one upper block each; wavefront 2
-        // eight lanes per block (blocks 128..135)
-        const int ub = wv < 2 ? tid : (wv == 2 ? 2 * 64 + (lane >> 3) : 0);
-        int bi = 0, rem = ub;
-        while (rem >= kGBlk - bi) {
-            rem -= kGBlk - bi;
-            ++bi;
+        // tiles of this wavefront's role: G's ten upper 16x16 tiles, three
+        // each for roles 0-2, one for role 3 (which also forms h).  Tile t
+        // is (ti, tj) = (kTile[role][t] >> 2, kTile[role][t] & 3).
+        constexpr int kTile[4][3] = {{0, 1, 2}, {3, 5, 6}, {7, 10, 11}, {15, 15, 15}};
+        const int ntile = role < 3 ? 3 : 1;
+        int ti[3], tj[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int code = role == 0 ? kTile[0][t] : role == 1 ? kTile[1][t] : role == 2 ? kTile[2][t] : kTile[3][t];
+            ti[t] = code >> 2;
+            tj[t] = code & 3;
         }
-        const int bj = bi + rem;
-        const int sub = lane & 7;
-        double acc[4][4];
+        const int fi = lane & 15, fk = lane >> 4;   // operand lane: row (or column) fi of the tile, coordinate fk
+        d4 acc[3];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+        for (int t = 0; t < 3; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
         double hacc = 0.0;
 
         fetch(0);
@@ -558,67 +562,62 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
             }
             __syncthreads();
             if (p0 + kCh < M) fetch(p0 + kCh);
-            if (wv < 3) {
-                const int step = wv < 2 ? 1 : 8;
-                for (int pp = wv < 2 ? 0 : sub; pp < kCh; pp += step) {
-                    const double *xa = &sh.X[pp][4 * bi];
-                    const double *xb = &sh.X[pp][4 * bj];
-                    double ar[4], bc[4];
+            // G tile (ti, tj) += X[k, 16 ti + 0..15]^T X[k, 16 tj + 0..15] over
+            // the chunk's coordinates, four per matrix-core step
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        ar[r] = xa[r];
-                        bc[r] = xb[r];
-                    }
+            for (int ks = 0; ks < kCh / 4; ++ks) {
+                const double *xr = sh.X[4 * ks + fk];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) acc[r][c] = fma(ar[r], bc[c], acc[r][c]);
+                for (int t = 0; t < 3; ++t) {
+                    if (t < ntile)   // wavefront-uniform
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[16 * ti[t] + fi], xr[16 * tj[t] + fi], acc[t],
+                                                                      0, 0, 0);
                 }
-            } else {
+            }
+            if (role == 3) {
 #pragma unroll
                 for (int pp = 0; pp < kCh; ++pp) hacc = fma(sh.X[pp][lane], sh.yw[pp], hacc);
             }
         }
-        if (wv == 2) {
-            // the eight lanes of a block: fixed-order pairwise sums
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    double x = acc[r][c];
-                    x += __shfl_xor(x, 1);
-                    x += __shfl_xor(x, 2);
-                    x += __shfl_xor(x, 4);
-                    acc[r][c] = x;
-                }
-        }
         __syncthreads();   // the staging area and the measurement staging are free
-        if (wv < 2 || (wv == 2 && sub == 0)) {
+        // result layout of the 16x16 FP64 tile (unlike the FP32 16x16 ones):
+        // register r of lane l holds row 4 r + l / 16 of column l % 16
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+        for (int t = 0; t < 3; ++t) {
+            if (t < ntile) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int gi = 4 * bi + r, gj = 4 * bj + c;
-                    if (gi <= gj) sh.u.G[tri(gi, gj)] = acc[r][c];
+                for (int r = 0; r < 4; ++r) {
+                    const int gi = 16 * ti[t] + 4 * r + fk, gj = 16 * tj[t] + fi;
+                    if (gi <= gj) sh.u.G[tri(gi, gj)] = acc[t][r];
                 }
+            }
         }
-        if (wv == 3) sh.h[lane] = hacc;
+        if (role == 3) sh.h[lane] = hacc;
         __syncthreads();
 
-        // ---- iterations in coefficient coordinates (wavefront 0) -------------
-        // Every lane runs the merge and the solves with the same values, so
-        // the factor and coefficients each lane reads back are its own writes;
-        // lane i scores candidate slot i.
-        if (wv == 0) {
+        // ---- iterations in candidate coordinates (the role-3 wavefront) ------
+        // Lane i keeps, for candidate slot i, u_i = L^-1 G[Omega, i] (the new
+        // rows of the Cholesky factor it would add), its correlation with the
+        // residual c_i = h_i - u_i^T z and its squared pivot e_i = G_ii -
+        // ||u_i||^2, all FP64 in registers (the loop is unrolled, so the row
+        // index is a constant).  A pick appends the chosen lane's
+        // [u_k^T, sqrt(e_k)] to L; every lane then takes one more entry of u_i
+        // (one dot product with u_k and a division) and updates c_i, e_i.
+        // The coefficients are solved once, after the last pick.
+        if (role == 3) {
             const int ci = lane < nc ? sh.cand[lane] : -1;
             const double gii = ci >= 0 ? sh.u.G[tri(lane, lane)] : 0.0;
             bool live = ci >= 0 && gii > 0.0;
             const double rn = live ? 1.0 / sqrt(gii) : 0.0;
-            const double hi = sh.h[lane];
+            double c = sh.h[lane], e = gii;
+            double u[KX];
+#pragma unroll
+            for (int j = 0; j < KX; ++j) u[j] = 0.0;
             int n = 0;
-            for (int it = 0; it < K; ++it) {
-                double c = hi;
-                for (int j = 0; j < n; ++j) c -= sh.u.G[tri(lane, sh.slot[j])] * sh.alpha[j];
+            // no early exit from the unrolled loop: a stop turns the rest off
+#pragma unroll
+            for (int it = 0; it < KX; ++it) {
+                if (n < it || it >= K) continue;
                 double sc = live ? fabs(c) * rn : -1.0;
                 int at = live ? ci : INT_MAX;
                 int ps = live ? lane : -1;
@@ -633,34 +632,40 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
                     at = up ? oa : at;
                     ps = up ? op : ps;
                 }
-                if (ps < 0 || n >= rank_bound) break;   // candidates exhausted, or the support spans the space
-                // Cholesky row of the new atom from its entries of G
-                const double ek = sh.u.G[tri(ps, ps)];
-                double d = ek;
-                for (int i = 0; i < n; ++i) {
-                    double s = sh.u.G[tri(ps, sh.slot[i])];
-                    for (int j = 0; j < i; ++j) s -= sh.L[i * KX + j] * sh.L[n * KX + j];
-                    const double wi = s / sh.L[i * KX + i];
-                    sh.L[n * KX + i] = wi;
-                    d -= wi * wi;
+                if (ps < 0 || it >= rank_bound) continue;   // candidates exhausted, or the support spans the space
+                const double ek = __shfl(e, ps), gkk = __shfl(gii, ps);
+                if (!(ek > 1e-10 * gkk)) continue;          // dependent on the support
+                const double lnn = sqrt(ek);
+                const double zn = __shfl(c, ps) / lnn;
+                double uk[KX];
+#pragma unroll
+                for (int j = 0; j < it; ++j) uk[j] = __shfl(u[j], ps);
+                double dot = 0.0;
+#pragma unroll
+                for (int j = 0; j < it; ++j) dot = fma(uk[j], u[j], dot);
+                const double un = (live ? sh.u.G[tri(lane, ps)] - dot : 0.0) / lnn;
+                u[it] = un;
+                c = fma(-un, zn, c);
+                e = fma(-un, un, e);
+                if (lane == 0) {
+#pragma unroll
+                    for (int j = 0; j < it; ++j) sh.L[it * KX + j] = uk[j];
+                    sh.L[it * KX + it] = lnn;
+                    sh.z[it] = zn;
+                    sh.sup[it] = at;
                 }
-                if (!(d > 1e-10 * ek)) break;   // dependent on the support
-                const double lnn = sqrt(d);
-                sh.L[n * KX + n] = lnn;
-                double s = sh.h[ps];
-                for (int j = 0; j < n; ++j) s -= sh.L[n * KX + j] * sh.z[j];
-                sh.z[n] = s / lnn;
-                for (int i = n; i >= 0; --i) {
-                    double u = sh.z[i];
-                    for (int j = i + 1; j <= n; ++j) u -= sh.L[j * KX + i] * sh.alpha[j];
-                    sh.alpha[i] = u / sh.L[i * KX + i];
-                }
-                sh.slot[n] = ps;
-                sh.sup[n] = at;
                 live = live && lane != ps;
-                ++n;
+                n = it + 1;
             }
-            if (lane == 0) sh.nsel = n;
+            if (lane == 0) {
+                // L^T alpha = z (lane 0 reads back only its own writes)
+                for (int i = n - 1; i >= 0; --i) {
+                    double v2 = sh.z[i];
+                    for (int j = i + 1; j < n; ++j) v2 -= sh.L[j * KX + i] * sh.alpha[j];
+                    sh.alpha[i] = v2 / sh.L[i * KX + i];
+                }
+                sh.nsel = n;
+            }
         }
     } else if (tid == 0) {
         sh.nsel = 0;
