@@ -418,8 +418,9 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
 //
 // Formation: the observed coordinates are listed in ascending order; chunks
 // of kCh of them are staged in LDS as FP64 weighted values (exact products
-// of the FP32 candidate value and weight), the next chunk's loads in flight
-// while the current one is multiplied.  G is symmetric: its ten upper 16x16
+// of the FP32 candidate value and weight), the loads of the next kBuf
+// chunks in flight while the current one is multiplied (the loop waits on
+// gathers from beyond L2, not on arithmetic).  G is symmetric: its ten upper 16x16
 // tiles are FP64 matrix-core products (16x16x4: one LDS double per lane per
 // tile and step, where 4x4 register blocks on the vector units read eight
 // per sixteen FMAs and waited on LDS), three tiles for each of three
@@ -428,6 +429,7 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
 constexpr int kGramCand = 64;
 constexpr int kGramTri = kGramCand * (kGramCand + 1) / 2;
 constexpr int kCh = 16;
+constexpr int kBuf = 3;               // chunks whose loads are in flight
 constexpr int kXld = kGramCand + 2;   // keeps rows 16-byte aligned and spreads the staging stores over banks
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -525,13 +527,11 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
             const int i = (tid + r * kThreads) / kCh;
             rowp[r] = i < nc ? v + (int64_t)sh.cand[i] * lp : nullptr;
         }
-        T pre[kPer];
-        int pt = -1;
-        auto fetch = [&](int p0) {
+        auto fetch_to = [&](T (&buf)[kPer], int &ptv, int p0) {
             const int p = p0 + spp;
-            pt = p < M ? sh.idx[p] : -1;
+            ptv = p < M ? sh.idx[p] : -1;
 #pragma unroll
-            for (int r = 0; r < kPer; ++r) pre[r] = (pt >= 0 && rowp[r]) ? rowp[r][pt] : T(0);
+            for (int r = 0; r < kPer; ++r) buf[r] = (ptv >= 0 && rowp[r]) ? rowp[r][ptv] : T(0);
         };
         // tiles of this wavefront's role: G's ten upper 16x16 tiles, three
         // each for roles 0-2, one for role 3 (which also forms h).  Tile t
@@ -551,17 +551,18 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
         for (int t = 0; t < 3; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
         double hacc = 0.0;
 
-        fetch(0);
-        for (int p0 = 0; p0 < M; p0 += kCh) {
+        // kBuf chunks in flight: each chunk's buffer is refilled with the chunk
+        // kBuf ahead as soon as it has been staged
+        auto run_chunk = [&](T (&buf)[kPer], int &ptv, int p0) {
             __syncthreads();   // the previous chunk has been consumed
             {
-                const double w = pt >= 0 ? (double)sh.sqw[pt] : 0.0;
+                const double w = ptv >= 0 ? (double)sh.sqw[ptv] : 0.0;
 #pragma unroll
-                for (int r = 0; r < kPer; ++r) sh.X[spp][(tid + r * kThreads) / kCh] = (double)pre[r] * w;
-                if (tid < kCh) sh.yw[tid] = pt >= 0 ? (double)sh.yhat[pt] : 0.0;
+                for (int r = 0; r < kPer; ++r) sh.X[spp][(tid + r * kThreads) / kCh] = (double)buf[r] * w;
+                if (tid < kCh) sh.yw[tid] = ptv >= 0 ? (double)sh.yhat[ptv] : 0.0;
             }
             __syncthreads();
-            if (p0 + kCh < M) fetch(p0 + kCh);
+            if (p0 + kBuf * kCh < M) fetch_to(buf, ptv, p0 + kBuf * kCh);
             // G tile (ti, tj) += X[k, 16 ti + 0..15]^T X[k, 16 tj + 0..15] over
             // the chunk's coordinates, four per matrix-core step
 #pragma unroll
@@ -578,6 +579,18 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
 #pragma unroll
                 for (int pp = 0; pp < kCh; ++pp) hacc = fma(sh.X[pp][lane], sh.yw[pp], hacc);
             }
+        };
+        T buf[kBuf][kPer];
+        int ptb[kBuf];
+#pragma unroll
+        for (int q = 0; q < kBuf; ++q) {
+            ptb[q] = -1;
+            if (q * kCh < M) fetch_to(buf[q], ptb[q], q * kCh);
+        }
+        for (int p0 = 0; p0 < M; p0 += kBuf * kCh) {
+#pragma unroll
+            for (int q = 0; q < kBuf; ++q)
+                if (p0 + q * kCh < M) run_chunk(buf[q], ptb[q], p0 + q * kCh);
         }
         __syncthreads();   // the staging area and the measurement staging are free
         // result layout of the 16x16 FP64 tile (unlike the FP32 16x16 ones):
