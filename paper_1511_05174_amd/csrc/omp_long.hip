@@ -35,7 +35,7 @@ namespace long_impl {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int KX = kMaxK;
-constexpr int kCG = 4;   // candidates a wavefront scores at a time (their loads in flight together)
+constexpr int kCG = 8;   // candidates a wavefront scores at a time (their loads in flight together)
 
 template <typename T>
 struct Shared {
