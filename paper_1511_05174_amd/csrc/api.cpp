@@ -129,6 +129,7 @@ void free_plan(cspd_plan_s *p)
         if (sc.nu2) (void)hipFree(sc.nu2);
         if (sc.inv_nu) (void)hipFree(sc.inv_nu);
         if (sc.gram) (void)hipFree(sc.gram);
+        if (sc.vt) (void)hipFree(sc.vt);
         if (sc.blk_off) (void)hipFree(sc.blk_off);
         if (sc.blk_idx) (void)hipFree(sc.blk_idx);
     }
@@ -152,6 +153,7 @@ ScaleArgs base_args(const cspd_plan_s *p, int s, int64_t B, const void *y, const
     a.n = p->n;
     a.v = sc.v;
     a.gram = sc.gram;
+    a.vt = sc.vt;
     a.t = sc.t;
     a.l = sc.l;
     a.lp = sc.lp;

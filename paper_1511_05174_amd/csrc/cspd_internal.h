@@ -85,6 +85,11 @@ struct ScalePlan {
     void *nu2 = nullptr;      // t, squared effective norms (null for mask plans)
     void *inv_nu = nullptr;   // t, FP32 reciprocal effective norms (null for mask plans)
     void *gram = nullptr;     // t x t effective Gram (null unless precomputed)
+    // v transposed (lp x t per operator, coordinate-major): the first scale of
+    // plans with several operators and a Gram table, whose kernels form each
+    // patch's correlations themselves (lanes hold consecutive atoms, so one
+    // coordinate of the lanes' candidates is one contiguous read); else null
+    void *vt = nullptr;
     int *blk_off = nullptr;   // l + 1 (fold only): fine samples of each coarse sample
     int *blk_idx = nullptr;   // N (fold only)
     int blk_ident = 0;        // fold whose blocks are single samples in signal order
@@ -175,6 +180,7 @@ struct ScaleArgs {
     const void *hpre;           // b x t correlations with y (gram mode, first scale), or null;
                                 // for launch_choice: the workspace the GEMM variant writes them to
     const void *nu2;            // t squared effective norms (with hpre)
+    const void *vt;             // lp x t per operator: v coordinate-major, or null
     float gsplit;               // power of two: candidates times it fit FP16 (split Gram)
     const void *vsplit;         // t x lp 32-bit words: the candidates split at plan time, or null
     // per-patch operator (plans with several dense operators): phase[b] picks

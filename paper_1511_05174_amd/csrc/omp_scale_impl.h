@@ -1007,6 +1007,44 @@ void k_omp_scale(ScaleArgs a)
             h[s] = live[s] ? hv : T(0);
             ee[s] = live[s] ? ev : T(0);
         }
+    } else if (a.vt) {
+        // coordinate-major copy (plans with several operators): lane l holds
+        // atoms l, l + 64, ..., so coordinate j of one slot is a contiguous
+        // read across the wavefront (a lane reading its own rows spreads every
+        // load over 64 cache lines)
+        const T *vtp = (const T *)a.vt + (int64_t)ph * a.phase_stride;
+        for (int j = 0; j < lp; ++j) {
+            const T sw = w.sqw[j], yh = w.yhat[j];
+#pragma unroll
+            for (int s = 0; s < NC; ++s) {
+                const T xv = vtp[(int64_t)j * a.t + (live[s] ? atom[s] : 0)] * sw;
+                const T x = live[s] ? xv : T(0);
+                h[s] += x * yh;
+                ee[s] += x * x;
+            }
+        }
+    } else if constexpr (sizeof(T) == 4) {
+        // 16 bytes of each candidate row per load (rows and the LDS record
+        // are 16-byte aligned, lp is a multiple of 4); the sums keep the
+        // coordinate order of the scalar loop below
+        for (int j = 0; j < lp; j += 4) {
+            const float4 sw = *reinterpret_cast<const float4 *>(&w.sqw[j]);
+            const float4 yh = *reinterpret_cast<const float4 *>(&w.yhat[j]);
+#pragma unroll
+            for (int s = 0; s < NC; ++s) {
+                const float4 q = *reinterpret_cast<const float4 *>(src[s] + j);
+                const float x0 = live[s] ? q.x * sw.x : 0.f, x1 = live[s] ? q.y * sw.y : 0.f;
+                const float x2 = live[s] ? q.z * sw.z : 0.f, x3 = live[s] ? q.w * sw.w : 0.f;
+                h[s] += x0 * yh.x;
+                h[s] += x1 * yh.y;
+                h[s] += x2 * yh.z;
+                h[s] += x3 * yh.w;
+                ee[s] += x0 * x0;
+                ee[s] += x1 * x1;
+                ee[s] += x2 * x2;
+                ee[s] += x3 * x3;
+            }
+        }
     } else {
         for (int j = 0; j < lp; ++j) {
             const T sw = w.sqw[j], yh = w.yhat[j];

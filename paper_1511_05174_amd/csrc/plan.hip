@@ -149,6 +149,19 @@ __global__ void k_absmax(const double *__restrict__ a, int64_t n, double *__rest
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// vt[ph][j][i] = v[ph][i][j]: each operator's candidates coordinate-major
+template <typename T>
+__global__ void k_transpose_phases(const T *__restrict__ v, int phases, int t, int lp, T *__restrict__ vt)
+{
+    const int64_t n = (int64_t)phases * t * lp;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int64_t per = (int64_t)t * lp;
+    const int64_t ph = idx / per, rem = idx - ph * per;
+    const int j = (int)(rem / t), i = (int)(rem - (int64_t)j * t);
+    vt[idx] = v[(ph * t + i) * lp + j];
+}
+
 template <typename T>
 cspd_status finish_scale(ScalePlan &sc, const double *a64, const double *w64, bool want_norms,
                          bool want_gram, int want_lo, int phases, hipStream_t st, int64_t &bytes)
@@ -177,6 +190,14 @@ cspd_status finish_scale(ScalePlan &sc, const double *a64, const double *w64, bo
         CSPD_HIP_CHECK(hipMalloc(&sc.inv_nu, sizeof(float) * (size_t)sc.t));
         bytes += sizeof(float) * (size_t)sc.t;
         k_inv_norms<<<blocks_for(sc.t, bs), bs, 0, st>>>(w64, sc.t, sc.l, (float *)sc.inv_nu);
+        CSPD_HIP_CHECK(hipGetLastError());
+    }
+    if (want_gram && phases > 1) {
+        size_t tb = sizeof(T) * (size_t)rows * sc.lp;
+        CSPD_HIP_CHECK(hipMalloc(&sc.vt, tb));
+        bytes += tb;
+        k_transpose_phases<T><<<blocks_for((int64_t)rows * sc.lp, bs), bs, 0, st>>>((const T *)sc.v, phases, sc.t,
+                                                                                      sc.lp, (T *)sc.vt);
         CSPD_HIP_CHECK(hipGetLastError());
     }
     if (want_gram) {
