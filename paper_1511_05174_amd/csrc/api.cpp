@@ -129,7 +129,6 @@ void free_plan(cspd_plan_s *p)
         if (sc.nu2) (void)hipFree(sc.nu2);
         if (sc.inv_nu) (void)hipFree(sc.inv_nu);
         if (sc.gram) (void)hipFree(sc.gram);
-        if (sc.vt) (void)hipFree(sc.vt);
         if (sc.blk_off) (void)hipFree(sc.blk_off);
         if (sc.blk_idx) (void)hipFree(sc.blk_idx);
     }
@@ -153,7 +152,6 @@ ScaleArgs base_args(const cspd_plan_s *p, int s, int64_t B, const void *y, const
     a.n = p->n;
     a.v = sc.v;
     a.gram = sc.gram;
-    a.vt = sc.vt;
     a.t = sc.t;
     a.l = sc.l;
     a.lp = sc.lp;
@@ -263,7 +261,10 @@ size_t hpre_offset(const cspd_plan_s *p, int64_t B, int ksum, bool caller_keeps_
 size_t cross_workspace_bytes(const cspd_plan_s *p, int64_t B, int ksum, bool caller_keeps_supports)
 {
     const size_t off = hpre_offset(p, B, ksum, caller_keeps_supports);
-    return off + (first_gemm_path(p) ? sizeof(float) * (size_t)B * (size_t)p->sc[0].t : 0);
+    if (!first_gemm_path(p)) return off;
+    // the correlations, then (several operators) the grouping of the patches
+    return off + (p->n_phases > 1 ? phase_groups_offset(B, p->sc[0].t) + phase_groups_bytes(B, p->n_phases)
+                                  : sizeof(float) * (size_t)B * (size_t)p->sc[0].t);
 }
 
 // Arguments of scale s of a cross-scale call.
@@ -398,7 +399,7 @@ cspd_status cross_scale_on(cspd_plan_s *p, int64_t B, const void *y, const uint8
 int64_t cross_workspace_per_patch(const cspd_plan_s *p)
 {
     int64_t per = (int64_t)sizeof(int32_t) * (p->s - 1);
-    if (first_gemm_path(p)) per += (int64_t)sizeof(float) * p->sc[0].t;
+    if (first_gemm_path(p)) per += (int64_t)sizeof(float) * p->sc[0].t + (p->n_phases > 1 ? 4 : 0);
     return per;
 }
 }  // namespace cspd

@@ -82,14 +82,9 @@ struct ScalePlan {
     int fold = kFold;
     void *v = nullptr;        // t x lp, atom-contiguous, zero padded, plan dtype
     void *v_lo = nullptr;     // t x lp, 16-bit copy for the reduced-precision proxy (or null)
-    void *nu2 = nullptr;      // t, squared effective norms (null for mask plans)
-    void *inv_nu = nullptr;   // t, FP32 reciprocal effective norms (null for mask plans)
+    void *nu2 = nullptr;      // t per operator, squared effective norms (null for mask plans)
+    void *inv_nu = nullptr;   // t per operator, FP32 reciprocal effective norms (null for mask plans)
     void *gram = nullptr;     // t x t effective Gram (null unless precomputed)
-    // v transposed (lp x t per operator, coordinate-major): the first scale of
-    // plans with several operators and a Gram table, whose kernels form each
-    // patch's correlations themselves (lanes hold consecutive atoms, so one
-    // coordinate of the lanes' candidates is one contiguous read); else null
-    void *vt = nullptr;
     int *blk_off = nullptr;   // l + 1 (fold only): fine samples of each coarse sample
     int *blk_idx = nullptr;   // N (fold only)
     int blk_ident = 0;        // fold whose blocks are single samples in signal order
@@ -180,7 +175,6 @@ struct ScaleArgs {
     const void *hpre;           // b x t correlations with y (gram mode, first scale), or null;
                                 // for launch_choice: the workspace the GEMM variant writes them to
     const void *nu2;            // t squared effective norms (with hpre)
-    const void *vt;             // lp x t per operator: v coordinate-major, or null
     float gsplit;               // power of two: candidates times it fit FP16 (split Gram)
     const void *vsplit;         // t x lp 32-bit words: the candidates split at plan time, or null
     // per-patch operator (plans with several dense operators): phase[b] picks
@@ -228,6 +222,21 @@ int64_t cross_workspace_per_patch(const cspd_plan_s *p);
 // operator on the matrix cores, and whether a scale qualifies.
 bool proxy_gemm_fits(int dtype, const ScaleArgs &a);
 cspd_status launch_proxy_gemm(int dtype, const ScaleArgs &a, float *h, hipStream_t stream);
+// With several operators (a.phase) the GEMM groups the patches by operator
+// first: per-operator counts, cursors, first positions and first tiles
+// (P + 1), and the patch indices listed operator by operator.  The
+// workspace starts phase_groups_offset bytes after the b x t correlations
+// and holds phase_groups_bytes.
+struct PhaseGroups {
+    int *count;
+    int *cursor;
+    int *seg;
+    int *tile;
+    int *perm;
+};
+size_t phase_groups_offset(int64_t B, int t);
+size_t phase_groups_bytes(int64_t B, int P);
+PhaseGroups phase_groups(void *base, int64_t B, int P);
 // Long-vector kernel (one workgroup per patch, FP64 least squares): whether
 // it can run a scale with this many candidates, and its launch.
 bool long_fits(const ScaleArgs &a, int max_cand);

@@ -1003,25 +1003,9 @@ void k_omp_scale(ScaleArgs a)
         for (int s = 0; s < NC; ++s) {
             const int at = live[s] ? atom[s] : 0;
             const T hv = ((const T *)a.hpre)[bb * (int64_t)a.t + at];
-            const T ev = ((const T *)a.nu2)[at];
+            const T ev = ((const T *)a.nu2)[(int64_t)ph * a.t + at];   // the patch's operator's norms
             h[s] = live[s] ? hv : T(0);
             ee[s] = live[s] ? ev : T(0);
-        }
-    } else if (a.vt) {
-        // coordinate-major copy (plans with several operators): lane l holds
-        // atoms l, l + 64, ..., so coordinate j of one slot is a contiguous
-        // read across the wavefront (a lane reading its own rows spreads every
-        // load over 64 cache lines)
-        const T *vtp = (const T *)a.vt + (int64_t)ph * a.phase_stride;
-        for (int j = 0; j < lp; ++j) {
-            const T sw = w.sqw[j], yh = w.yhat[j];
-#pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                const T xv = vtp[(int64_t)j * a.t + (live[s] ? atom[s] : 0)] * sw;
-                const T x = live[s] ? xv : T(0);
-                h[s] += x * yh;
-                ee[s] += x * x;
-            }
         }
     } else if constexpr (sizeof(T) == 4) {
         // 16 bytes of each candidate row per load (rows and the LDS record

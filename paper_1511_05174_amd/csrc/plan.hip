@@ -149,18 +149,6 @@ __global__ void k_absmax(const double *__restrict__ a, int64_t n, double *__rest
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// vt[ph][j][i] = v[ph][i][j]: each operator's candidates coordinate-major
-template <typename T>
-__global__ void k_transpose_phases(const T *__restrict__ v, int phases, int t, int lp, T *__restrict__ vt)
-{
-    const int64_t n = (int64_t)phases * t * lp;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n) return;
-    const int64_t per = (int64_t)t * lp;
-    const int64_t ph = idx / per, rem = idx - ph * per;
-    const int j = (int)(rem / t), i = (int)(rem - (int64_t)j * t);
-    vt[idx] = v[(ph * t + i) * lp + j];
-}
 
 template <typename T>
 cspd_status finish_scale(ScalePlan &sc, const double *a64, const double *w64, bool want_norms,
@@ -183,21 +171,14 @@ cspd_status finish_scale(ScalePlan &sc, const double *a64, const double *w64, bo
         CSPD_HIP_CHECK(hipGetLastError());
     }
     if (want_norms) {
-        CSPD_HIP_CHECK(hipMalloc(&sc.nu2, sizeof(T) * (size_t)sc.t));
-        bytes += sizeof(T) * (size_t)sc.t;
-        k_norms<T><<<blocks_for(sc.t, bs), bs, 0, st>>>(w64, sc.t, sc.l, (T *)sc.nu2);
+        // t entries per operator phase (w64 holds the phases' rows back to back)
+        CSPD_HIP_CHECK(hipMalloc(&sc.nu2, sizeof(T) * (size_t)rows));
+        bytes += sizeof(T) * (size_t)rows;
+        k_norms<T><<<blocks_for(rows, bs), bs, 0, st>>>(w64, rows, sc.l, (T *)sc.nu2);
         CSPD_HIP_CHECK(hipGetLastError());
-        CSPD_HIP_CHECK(hipMalloc(&sc.inv_nu, sizeof(float) * (size_t)sc.t));
-        bytes += sizeof(float) * (size_t)sc.t;
-        k_inv_norms<<<blocks_for(sc.t, bs), bs, 0, st>>>(w64, sc.t, sc.l, (float *)sc.inv_nu);
-        CSPD_HIP_CHECK(hipGetLastError());
-    }
-    if (want_gram && phases > 1) {
-        size_t tb = sizeof(T) * (size_t)rows * sc.lp;
-        CSPD_HIP_CHECK(hipMalloc(&sc.vt, tb));
-        bytes += tb;
-        k_transpose_phases<T><<<blocks_for((int64_t)rows * sc.lp, bs), bs, 0, st>>>((const T *)sc.v, phases, sc.t,
-                                                                                      sc.lp, (T *)sc.vt);
+        CSPD_HIP_CHECK(hipMalloc(&sc.inv_nu, sizeof(float) * (size_t)rows));
+        bytes += sizeof(float) * (size_t)rows;
+        k_inv_norms<<<blocks_for(rows, bs), bs, 0, st>>>(w64, rows, sc.l, (float *)sc.inv_nu);
         CSPD_HIP_CHECK(hipGetLastError());
     }
     if (want_gram) {
@@ -314,15 +295,15 @@ cspd_status plan_effective(cspd_plan_s *p, const cspd_plan_desc *d, hipStream_t 
         }
         sc.gsplit = std::ldexp(1.0f, ex);
         const double *wsrc = dense ? (const double *)a64.p : (const double *)w64.p;
-        // with several operators, the tables shared by all patches (norms,
-        // Gram matrix, 16-bit copy) do not exist; the kernels that need them
-        // are not used
-        const bool norms = !mask && P == 1;
         // Gram tables: one per operator; with several operators only at the
         // first scale (a full search there), within 64 MB
         const bool gram = !mask && T <= kMaxGramAtoms && sc.lp <= kMaxShortLen &&
                           ((P == 1 && (s == 0 || s == S - 1)) ||
                            (P > 1 && s == 0 && (int64_t)P * T * T * 4 <= ((int64_t)64 << 20)));
+        // squared norms: one set per operator, with several operators only
+        // beside the first scale's Gram tables (the batched correlations'
+        // path); the 16-bit copy exists for a shared operator only
+        const bool norms = !mask && (P == 1 || gram);
         // 16-bit copies for the reduced-precision proxy: full search at the
         // finest scale, and the first scale's batched contraction under a
         // shared dense operator

@@ -177,9 +177,159 @@ void k_proxy_gemm_lo(const float *__restrict__ y, int y_stride, int m, int64_t n
     }
 }
 
+// ---- plans with several operators: the batch grouped by operator ----------
+// Each patch's first-scale correlations use its own operator's A_0, so the
+// patches are listed operator by operator (a counting sort of the patch
+// indices) and each wavefront takes up to 32 patches of one operator.  The
+// order of the patches within an operator does not matter: every output is
+// one dot product, summed in the same order whatever the tile holds.
+// Patches whose operator is out of range are left out (they stay unsolved).
+__global__ void k_groups_clear(int *count, int *cursor, int P)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
+        count[i] = 0;
+        cursor[i] = 0;
+    }
+}
+
+// Counts and positions are aggregated per workgroup in LDS first, so a
+// workgroup makes one global atomic per operator it holds (a few thousand
+// in all) instead of one per patch on a handful of counters.
+constexpr int kMaxGroups = 4096;   // operators per plan
+
+__global__ __launch_bounds__(256) void k_groups_count(const int *__restrict__ phase, int64_t nb, int P,
+                                                      int *__restrict__ count)
+{
+    __shared__ int lc[kMaxGroups];
+    for (int i = threadIdx.x; i < P; i += blockDim.x) lc[i] = 0;
+    __syncthreads();
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ph = b < nb ? phase[b] : -1;
+    if (ph >= 0 && ph < P) atomicAdd(&lc[ph], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < P; i += blockDim.x)
+        if (lc[i]) atomicAdd(&count[i], lc[i]);
+}
+
+// one thread (at most 4,096 operators): first position and first tile of
+// each operator's patches
+__global__ void k_groups_scan(const int *__restrict__ count, int P, int *__restrict__ seg, int *__restrict__ tile)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int s = 0, t = 0;
+    for (int i = 0; i < P; ++i) {
+        seg[i] = s;
+        tile[i] = t;
+        s += count[i];
+        t += (count[i] + 31) / 32;
+    }
+    seg[P] = s;
+    tile[P] = t;
+}
+
+__global__ __launch_bounds__(256) void k_groups_scatter(const int *__restrict__ phase, int64_t nb, int P,
+                                                        const int *__restrict__ seg, int *__restrict__ cursor,
+                                                        int *__restrict__ perm)
+{
+    __shared__ int lc[kMaxGroups];
+    __shared__ int base[kMaxGroups];
+    for (int i = threadIdx.x; i < P; i += blockDim.x) lc[i] = 0;
+    __syncthreads();
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ph = b < nb ? phase[b] : -1;
+    const bool ok = ph >= 0 && ph < P;
+    const int rank = ok ? atomicAdd(&lc[ph], 1) : 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < P; i += blockDim.x)
+        if (lc[i]) base[i] = atomicAdd(&cursor[i], lc[i]);
+    __syncthreads();
+    if (ok) perm[seg[ph] + base[ph] + rank] = (int)b;
+}
+
+// k_proxy_gemm over the grouped batch: wavefront w takes tile w (32 patches
+// of one operator, the last tile of an operator ragged)
+template <int LP>
+__global__ __launch_bounds__(64 * W)
+void k_proxy_gemm_groups(const float *__restrict__ y, int y_stride, int m, const float *__restrict__ v, int lp,
+                         int t, int64_t phase_stride, int P, const int *__restrict__ seg,
+                         const int *__restrict__ tile, const int *__restrict__ perm, float *__restrict__ h)
+{
+    constexpr int LH = LP / 2;
+    typedef float acc_t __attribute__((ext_vector_type(16)));
+    const int lane = threadIdx.x & 63;
+    const int hh = lane >> 5;
+    const int col = lane & 31;
+    const int w = blockIdx.x * W + (threadIdx.x >> 6);
+    if (w >= tile[P]) return;   // the whole wavefront leaves together
+    // operator of tile w: the largest ph with tile[ph] <= w (empty operators
+    // share their bound with the next one)
+    int lo = 0, hi = P;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile[mid] <= w) lo = mid;
+        else hi = mid;
+    }
+    const int ph = lo;
+    const int first = seg[ph] + (w - tile[ph]) * 32;
+    const int nrow = seg[ph + 1] - first < 32 ? seg[ph + 1] - first : 32;
+    const int64_t prow = perm[first + (col < nrow ? col : 0)];
+    const float *yr = y + prow * (int64_t)y_stride;
+    float ya[LH];
+#pragma unroll
+    for (int j = 0; j < LH; ++j) {
+        const int c = hh * LH + j;
+        const float val = yr[c < m ? c : 0];
+        ya[j] = (c < m && col < nrow) ? val : 0.f;
+    }
+    const float *vph = v + (int64_t)ph * phase_stride;
+    for (int a0 = 0; a0 < t; a0 += 32) {
+        const int at = a0 + col < t ? a0 + col : t - 1;
+        const float *vr = vph + (int64_t)at * lp + hh * LH;
+        float vb[LH];
+#pragma unroll
+        for (int j = 0; j < LH; j += 4) {
+            const float4 q = *reinterpret_cast<const float4 *>(vr + j);
+            vb[j] = q.x; vb[j + 1] = q.y; vb[j + 2] = q.z; vb[j + 3] = q.w;
+        }
+        acc_t acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+        for (int j = 0; j < LH; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ya[j], vb[j], acc, 0, 0, 0);
+        if (a0 + col < t) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int rr = 8 * (r >> 2) + 4 * hh + (r & 3);
+                if (rr < nrow) h[(int64_t)perm[first + rr] * t + a0 + col] = acc[r];
+            }
+        }
+    }
+}
+
+template <int LP>
+cspd_status launch_groups(const ScaleArgs &a, float *h, hipStream_t st)
+{
+    const int P = a.n_phases;
+    const PhaseGroups g = phase_groups((char *)h + phase_groups_offset(a.b, a.t), a.b, P);
+    const int bs = 256;
+    const unsigned gb = (unsigned)((a.b + bs - 1) / bs);
+    hipLaunchKernelGGL(k_groups_clear, dim3((unsigned)((P + bs - 1) / bs)), dim3(bs), 0, st, g.count, g.cursor, P);
+    hipLaunchKernelGGL(k_groups_count, dim3(gb), dim3(bs), 0, st, a.phase, a.b, P, g.count);
+    hipLaunchKernelGGL(k_groups_scan, dim3(1), dim3(64), 0, st, g.count, P, g.seg, g.tile);
+    hipLaunchKernelGGL(k_groups_scatter, dim3(gb), dim3(bs), 0, st, a.phase, a.b, P, g.seg, g.cursor, g.perm);
+    // at most ceil(B / 32) full tiles plus one ragged tile per operator
+    const int64_t waves = (a.b + 31) / 32 + P;
+    const unsigned grid = (unsigned)((waves + W - 1) / W);
+    launch_timed("proxy_gemm<f32,groups>:s0", k_proxy_gemm_groups<LP>, dim3(grid), dim3(64 * W), 0u, st,
+                 (const float *)a.y, a.y_stride, a.m_dense, (const float *)a.v, a.lp, a.t, a.phase_stride, P,
+                 (const int *)g.seg, (const int *)g.tile, (const int *)g.perm, h);
+    return hipGetLastError() == hipSuccess ? CSPD_OK : CSPD_E_DEVICE;
+}
+
 template <int LP>
 cspd_status launch(const ScaleArgs &a, float *h, hipStream_t st)
 {
+    if (a.phase && a.n_phases > 1) return launch_groups<LP>(a, h, st);
     const int64_t waves = (a.b + 31) / 32;
     const unsigned grid = (unsigned)((waves + W - 1) / W);
     if (a.hre > 0 && a.vlo) {
@@ -197,6 +347,34 @@ cspd_status launch(const ScaleArgs &a, float *h, hipStream_t st)
 }
 
 }  // namespace gemm_impl
+
+size_t phase_groups_offset(int64_t B, int t)
+{
+    return ((size_t)B * (size_t)t * sizeof(float) + 255) / 256 * 256;
+}
+
+size_t phase_groups_bytes(int64_t B, int P)
+{
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    return 2 * al(sizeof(int) * (size_t)P) + 2 * al(sizeof(int) * (size_t)(P + 1)) + al(sizeof(int) * (size_t)B);
+}
+
+PhaseGroups phase_groups(void *base, int64_t B, int P)
+{
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    char *c = (char *)base;
+    PhaseGroups g;
+    g.count = (int *)c;
+    c += al(sizeof(int) * (size_t)P);
+    g.cursor = (int *)c;
+    c += al(sizeof(int) * (size_t)P);
+    g.seg = (int *)c;
+    c += al(sizeof(int) * (size_t)(P + 1));
+    g.tile = (int *)c;
+    c += al(sizeof(int) * (size_t)(P + 1));
+    g.perm = (int *)c;
+    return g;
+}
 
 bool proxy_gemm_fits(int dtype, const ScaleArgs &a)
 {

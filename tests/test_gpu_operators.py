@@ -76,6 +76,34 @@ def test_phased_out_of_range_and_misuse():
         cspd.cspd_omp_cross_scale_phased(plan, None, y, mask, w.k_scales[:-1], kf, w.k_scales[-1])
 
 
+def test_coded_exposure_grouping_skewed():
+    """The first scale's correlations come from one GEMM over the batch
+    grouped by operator: operators with no patch, one operator holding most
+    of them (ragged last tile), a single-patch batch; against the oracle."""
+    w = synth.make("c4loc", batch=700)
+    rng = np.random.default_rng(12)
+    ph = np.where(rng.random(w.batch) < 0.7, 3, rng.integers(4, 16, size=w.batch)).astype(np.int32)
+    ph[ph == 5] = 6                             # operators 0, 1, 2 and 5 unused
+    w2 = synth.subset(w, np.arange(w.batch))
+    w2.phase = ph
+    plan = cspd.plan_from_workload(w2)
+    # (the measurements were taken with other operators: any y serves parity)
+    for sub in (w2, synth.subset(w2, np.array([17]))):
+        out = run_phased(plan, sub)
+        ks = sub.k_scales
+        wo = G.with_y(sub, out["y64"])
+        sup = parity.gpu_scales(sub, out["support"], out["k_used"], out["support_coarse"], ks[:-1])
+        rep = parity.compare(wo, sup, out["coef"], out["k_used"], out["xhat"], k_scales=ks,
+                             tie_tol=TOL["f32"]["tie"])
+        print(f"[coded exposure, skewed operators, B={sub.batch}] {rep.summary()}", flush=True)
+        rep.check(TOL["f32"]["coef"], TOL["f32"]["xhat"])
+    cspd.cspd_profile_reset()
+    cspd.cspd_profile_enable(True)
+    run_phased(plan, w2)
+    cspd.cspd_profile_enable(False)
+    assert "proxy_gemm<f32,groups>:s0" in cspd.cspd_profile_read()
+
+
 def test_bayer_demosaicing():
     w = synth.make("bayer", batch=300)
     # each patch observes one colour per pixel
