@@ -223,13 +223,11 @@ int64_t cross_workspace_per_patch(const cspd_plan_s *p);
 bool proxy_gemm_fits(int dtype, const ScaleArgs &a);
 cspd_status launch_proxy_gemm(int dtype, const ScaleArgs &a, float *h, hipStream_t stream);
 // With several operators (a.phase) the GEMM groups the patches by operator
-// first: per-operator counts, cursors, first positions and first tiles
-// (P + 1), and the patch indices listed operator by operator.  The
-// workspace starts phase_groups_offset bytes after the b x t correlations
-// and holds phase_groups_bytes.
+// first: each operator's first position and first tile (P + 1 entries),
+// and the patch indices listed operator by operator.  The workspace starts
+// phase_groups_offset bytes after the b x t correlations and holds
+// phase_groups_bytes.
 struct PhaseGroups {
-    int *count;
-    int *cursor;
     int *seg;
     int *tile;
     int *perm;

@@ -26,6 +26,8 @@
 // re-scores its candidates in FP32 before each pick.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "cspd_internal.h"
 
 namespace cspd {
@@ -184,66 +186,43 @@ void k_proxy_gemm_lo(const float *__restrict__ y, int y_stride, int m, int64_t n
 // order of the patches within an operator does not matter: every output is
 // one dot product, summed in the same order whatever the tile holds.
 // Patches whose operator is out of range are left out (they stay unsolved).
-__global__ void k_groups_clear(int *count, int *cursor, int P)
-{
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
-        count[i] = 0;
-        cursor[i] = 0;
-    }
-}
-
-// Counts and positions are aggregated per workgroup in LDS first, so a
-// workgroup makes one global atomic per operator it holds (a few thousand
-// in all) instead of one per patch on a handful of counters.
+// One workgroup lists the whole batch: operator counts in LDS, their prefix
+// sums (first position and first tile of each operator), then each patch
+// index written at its operator's next position (LDS cursors).  One launch,
+// no global counters to clear; the batch is read twice, 1,024 patches a step.
 constexpr int kMaxGroups = 4096;   // operators per plan
+constexpr int kGroupThreads = 1024;
 
-__global__ __launch_bounds__(256) void k_groups_count(const int *__restrict__ phase, int64_t nb, int P,
-                                                      int *__restrict__ count)
+__global__ __launch_bounds__(kGroupThreads) void k_groups(const int *__restrict__ phase, int64_t nb, int P,
+                                                          int *__restrict__ seg, int *__restrict__ tile,
+                                                          int *__restrict__ perm)
 {
-    __shared__ int lc[kMaxGroups];
-    for (int i = threadIdx.x; i < P; i += blockDim.x) lc[i] = 0;
+    __shared__ int cnt[kMaxGroups];
+    __shared__ int cur[kMaxGroups];
+    for (int i = threadIdx.x; i < P; i += kGroupThreads) cnt[i] = 0;
     __syncthreads();
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int ph = b < nb ? phase[b] : -1;
-    if (ph >= 0 && ph < P) atomicAdd(&lc[ph], 1);
-    __syncthreads();
-    for (int i = threadIdx.x; i < P; i += blockDim.x)
-        if (lc[i]) atomicAdd(&count[i], lc[i]);
-}
-
-// one thread (at most 4,096 operators): first position and first tile of
-// each operator's patches
-__global__ void k_groups_scan(const int *__restrict__ count, int P, int *__restrict__ seg, int *__restrict__ tile)
-{
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    int s = 0, t = 0;
-    for (int i = 0; i < P; ++i) {
-        seg[i] = s;
-        tile[i] = t;
-        s += count[i];
-        t += (count[i] + 31) / 32;
+    for (int64_t b = threadIdx.x; b < nb; b += kGroupThreads) {
+        const int ph = phase[b];
+        if (ph >= 0 && ph < P) atomicAdd(&cnt[ph], 1);
     }
-    seg[P] = s;
-    tile[P] = t;
-}
-
-__global__ __launch_bounds__(256) void k_groups_scatter(const int *__restrict__ phase, int64_t nb, int P,
-                                                        const int *__restrict__ seg, int *__restrict__ cursor,
-                                                        int *__restrict__ perm)
-{
-    __shared__ int lc[kMaxGroups];
-    __shared__ int base[kMaxGroups];
-    for (int i = threadIdx.x; i < P; i += blockDim.x) lc[i] = 0;
     __syncthreads();
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int ph = b < nb ? phase[b] : -1;
-    const bool ok = ph >= 0 && ph < P;
-    const int rank = ok ? atomicAdd(&lc[ph], 1) : 0;
+    if (threadIdx.x == 0) {
+        int s = 0, t = 0;
+        for (int i = 0; i < P; ++i) {
+            seg[i] = s;
+            tile[i] = t;
+            cur[i] = s;
+            s += cnt[i];
+            t += (cnt[i] + 31) / 32;
+        }
+        seg[P] = s;
+        tile[P] = t;
+    }
     __syncthreads();
-    for (int i = threadIdx.x; i < P; i += blockDim.x)
-        if (lc[i]) base[i] = atomicAdd(&cursor[i], lc[i]);
-    __syncthreads();
-    if (ok) perm[seg[ph] + base[ph] + rank] = (int)b;
+    for (int64_t b = threadIdx.x; b < nb; b += kGroupThreads) {
+        const int ph = phase[b];
+        if (ph >= 0 && ph < P) perm[atomicAdd(&cur[ph], 1)] = (int)b;
+    }
 }
 
 // k_proxy_gemm over the grouped batch: wavefront w takes tile w (32 patches
@@ -310,13 +289,9 @@ template <int LP>
 cspd_status launch_groups(const ScaleArgs &a, float *h, hipStream_t st)
 {
     const int P = a.n_phases;
+    if (a.b >= (int64_t)INT_MAX || P > kMaxGroups) return CSPD_E_UNSUPPORTED;   // patch indices are 32-bit
     const PhaseGroups g = phase_groups((char *)h + phase_groups_offset(a.b, a.t), a.b, P);
-    const int bs = 256;
-    const unsigned gb = (unsigned)((a.b + bs - 1) / bs);
-    hipLaunchKernelGGL(k_groups_clear, dim3((unsigned)((P + bs - 1) / bs)), dim3(bs), 0, st, g.count, g.cursor, P);
-    hipLaunchKernelGGL(k_groups_count, dim3(gb), dim3(bs), 0, st, a.phase, a.b, P, g.count);
-    hipLaunchKernelGGL(k_groups_scan, dim3(1), dim3(64), 0, st, g.count, P, g.seg, g.tile);
-    hipLaunchKernelGGL(k_groups_scatter, dim3(gb), dim3(bs), 0, st, a.phase, a.b, P, g.seg, g.cursor, g.perm);
+    hipLaunchKernelGGL(k_groups, dim3(1), dim3(kGroupThreads), 0, st, a.phase, a.b, P, g.seg, g.tile, g.perm);
     // at most ceil(B / 32) full tiles plus one ragged tile per operator
     const int64_t waves = (a.b + 31) / 32 + P;
     const unsigned grid = (unsigned)((waves + W - 1) / W);
@@ -356,7 +331,7 @@ size_t phase_groups_offset(int64_t B, int t)
 size_t phase_groups_bytes(int64_t B, int P)
 {
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    return 2 * al(sizeof(int) * (size_t)P) + 2 * al(sizeof(int) * (size_t)(P + 1)) + al(sizeof(int) * (size_t)B);
+    return 2 * al(sizeof(int) * (size_t)(P + 1)) + al(sizeof(int) * (size_t)B);
 }
 
 PhaseGroups phase_groups(void *base, int64_t B, int P)
@@ -364,10 +339,6 @@ PhaseGroups phase_groups(void *base, int64_t B, int P)
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     char *c = (char *)base;
     PhaseGroups g;
-    g.count = (int *)c;
-    c += al(sizeof(int) * (size_t)P);
-    g.cursor = (int *)c;
-    c += al(sizeof(int) * (size_t)P);
     g.seg = (int *)c;
     c += al(sizeof(int) * (size_t)(P + 1));
     g.tile = (int *)c;
