@@ -8,7 +8,7 @@ coarse scale, D_high 64 x 1024, D_low 16 x 128, Q = 8, K = (4, 8), per-patch
 50 % pixel masks, FP32).  The same batch is also solved with full OMP over
 D_high for comparison, and the FP64 oracle is timed on the host cores.
 
-Prints one JSON line.  --gpus above 1 is refused: this build measures one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -985,7 +985,7 @@ def main():
     if full is not None and not args.no_sweep and w.n_scales == 2:
         equal = equal_psnr_phase(cspd, w, plan, timed)
         if args.workload == "c2":
-            # the same sweep on the survey's model dictionaries (child detail 1)
+            # the same sweep on the unmodified model dictionaries (child detail 1)
             import synth as _s
             w1 = _s.make("c2", detail=1.0)
             equal_d1 = equal_psnr_phase(cspd, w1, cspd.plan_from_workload(w1), timed)

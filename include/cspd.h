@@ -56,7 +56,7 @@ enum {
     CSPD_E_BUSY = -5,        /* serving: the job has not finished yet */
     CSPD_E_NOTFOUND = -6,    /* serving: unknown job id */
     CSPD_E_CAPACITY = -7,    /* serving: the job can never fit the HBM budget */
-    CSPD_E_UNSUPPORTED = -8  /* a shape this build has no kernel for */
+    CSPD_E_UNSUPPORTED = -8  /* a shape the library has no kernel for */
 };
 
 /* Measurement operator Phi (Section III-C). */
