@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -139,6 +140,30 @@ void free_plan(cspd_plan_s *p)
 }
 
 size_t elem_size(const cspd_plan_s *p) { return p->dtype == CSPD_F64 ? sizeof(double) : sizeof(float); }
+
+// The calls take their workspace from the device's default stream-ordered
+// pool (hipMallocAsync) and give it back at the end of the call.  By default
+// the pool returns freed memory to the device at once, so every call would
+// map its workspace afresh; a release threshold of kPoolKeepBytes keeps up
+// to that much freed memory in the pool between calls.  Set once per device
+// at the first plan on it, and only raised, never lowered.
+constexpr uint64_t kPoolKeepBytes = (uint64_t)2 << 30;
+
+void keep_workspace_pool(int device)
+{
+    static std::mutex mu;
+    static bool done[64] = {};
+    std::lock_guard<std::mutex> g(mu);
+    if (device < 0 || device >= 64 || done[device]) return;
+    done[device] = true;
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, device) != hipSuccess || !pool) return;
+    uint64_t cur = 0;
+    if (hipMemPoolGetAttribute(pool, hipMemPoolAttrReleaseThreshold, &cur) == hipSuccess && cur >= kPoolKeepBytes)
+        return;
+    uint64_t thr = kPoolKeepBytes;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+}
 
 // Arguments common to every scale of one call.
 ScaleArgs base_args(const cspd_plan_s *p, int s, int64_t B, const void *y, const uint8_t *mask)
@@ -435,6 +460,7 @@ cspd_status cspd_plan(const cspd_plan_desc *d, cspd_plan_t *out)
         DeviceGuard g(d->device);
         if (!g.ok) return set_error(CSPD_E_DEVICE, "hipSetDevice(%d) failed", d->device);
         noalloc_setup(d->device);
+        keep_workspace_pool(d->device);
         cspd_plan_s *p = new (std::nothrow) cspd_plan_s();
         if (!p) return set_error(CSPD_E_NOMEM, "host allocation failed");
         p->s = d->n_scales;
