@@ -132,7 +132,11 @@ typedef struct cspd_graph_s *cspd_graph_t;
  * and compute on the device the effective dictionaries A_s = Phi U D_s
  * (Section III-C, (P_low) / (P_high)) with their column norms, plus the
  * block tables of U.  Blocks until the plan is resident.  The plan owns all
- * of its device memory; release it with cspd_plan_destroy.
+ * of its device memory; release it with cspd_plan_destroy.  The compute
+ * calls take their workspace from the device's default stream-ordered memory
+ * pool and free it at the end of the call; the first plan on a device raises
+ * that pool's release threshold to 2 GiB (never lowers it), so that freed
+ * workspace stays in the pool between calls instead of being mapped afresh.
  * Errors: E_INVALID, E_SHAPE (among others: atoms[s] not a multiple of
  * atoms[s-1], or 2^22 or more children per atom), E_NOMEM, E_DEVICE.
  */
