@@ -21,7 +21,7 @@
 // The least squares are thus FP64 on the stored (rounded) vectors, as in the
 // FP64 oracle; only the proxy is FP32.  Patches with at most 64 candidates
 // (the finer scales of Algorithm 2) take the Gram mode further down, which
-// reads each candidate once and iterates in coefficient coordinates.
+// reads each candidate once and iterates on the candidates' Gram matrix.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -410,9 +410,11 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
 // correlations h = A^T sqrt(W) yhat (yhat is the folded measurement, which
 // carries the other factor) are formed once, as FP64 sums over the
 // coordinates of nonzero weight only, from the candidates' stored values;
-// the iterations then run in coefficient coordinates (Batch-OMP, Section
-// II-B): the proxy is c = h - G[:, Omega] alpha, the Cholesky row of a new
-// atom reads its entries of G, and no candidate vector is read again.  Each
+// Algorithm 1's steps then run on G and h alone (a precomputed Gram matrix,
+// the usual way to speed up OMP when candidates are reused; not a step the
+// paper prescribes): the proxy is c = h - G[:, Omega] alpha, the Cholesky row
+// of a new atom reads its entries of G, and no candidate vector is read
+// again.  Each
 // candidate row leaves HBM once instead of once per iteration, and a mask
 // leaves its unobserved coordinates out of the arithmetic.
 //
