@@ -673,7 +673,7 @@ def pipeline_phase(cspd, w, ks, reps: int = 5):
 
 
 def learning_phase(cspd, w, iters: int = 3):
-    """Section IV on the workload's 65,536 clean patches: cross-scale
+    """Section III-E on the workload's 65,536 clean patches: cross-scale
     learning (K-SVD on the down-sampled set for D_low, then K-SVD with
     zero-tree OMP for D_high: T 128 / 1024, K 4 / 8) against plain K-SVD of a
     1024-atom dictionary with full OMP (K 8).  Per-iteration time of the
@@ -1015,7 +1015,7 @@ def main():
         pipeline = pipeline_phase(cspd, w, ks)
         print(f"[bench] pipeline: {json.dumps(pipeline)}", file=sys.stderr, flush=True)
 
-    # ---- dictionary learning (Section IV): cross-scale vs plain K-SVD
+    # ---- dictionary learning (Section III-E): cross-scale vs plain K-SVD
     learning = None
     if not args.no_learning and args.workload == "c2":
         learning = learning_phase(cspd, w)

@@ -105,7 +105,7 @@ enum { CSPD_CORR_NATIVE = 0, CSPD_CORR_BF16_RESCORE = 1, CSPD_CORR_F16_RESCORE =
  *              and every patch is measured with one of them, chosen per call
  *              (cspd_omp_cross_scale_phased): location-dependent measurement
  *              such as a coded-exposure shutter pattern whose tile differs
- *              with the patch position (Section V, videos).  1 <= P <= 4096.
+ *              with the patch position (Section IV, videos).  1 <= P <= 4096.
  */
 typedef struct cspd_plan_desc {
     int32_t n_scales;
@@ -290,7 +290,7 @@ cspd_status cspd_set_tuned_kernel(cspd_plan_t plan, int32_t scale, int32_t bucke
 
 /* ---------------------------------------------------------------------- */
 /* Whole signals: overlapping patches in, averaged estimates out.           */
-/* (Section V processes images, videos and light fields as overlapping     */
+/* (Section IV processes images, videos and light fields as overlapping     */
 /* patches; the grid and the averaging below are this library's reading.)  */
 /* ---------------------------------------------------------------------- */
 
@@ -338,7 +338,7 @@ cspd_status cspd_aggregate_patches(const cspd_patch_grid *grid, const float *est
                                    void *hip_stream);
 
 /* ---------------------------------------------------------------------- */
-/* Learning the dictionaries (Section IV-A): the K-SVD dictionary update.  */
+/* Learning the dictionaries (Section III-E): the K-SVD dictionary update.  */
 /* ---------------------------------------------------------------------- */
 
 /*

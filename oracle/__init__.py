@@ -167,5 +167,5 @@ def omp_full(w, **kw):
 
 
 def snr_db(x: np.ndarray, xhat: np.ndarray) -> float:
-    """Batch SNR 20 log10(||X|| / ||X - Xhat||) (Section V-A's definition)."""
+    """Batch SNR 20 log10(||X|| / ||X - Xhat||) (Section IV-A's definition)."""
     return float(20.0 * np.log10(np.linalg.norm(x) / np.linalg.norm(x - xhat)))

@@ -1,5 +1,5 @@
 """Dictionary update of K-SVD as used to learn the cross-scale dictionaries
-(Section IV-A: K-SVD on the down-sampled training set for D_low, then the
+(Section III-E: K-SVD on the down-sampled training set for D_low, then the
 same update with the sparse-approximation step restricted to the children of
 the coarse support for D_high) -- test infrastructure only.
 
@@ -7,7 +7,7 @@ Plain numpy, FP64, one atom after another in index order so that it can be
 checked by eye against the algorithm.  It shares no code with the HIP
 library.  The sparse-approximation step itself is the OMP oracle
 (``oracle.omp``); this module only holds the dictionary update and the
-initialisation heuristic of Section IV-B.
+initialisation heuristic of Section III-G.
 
 Readings (the paper names K-SVD and leaves these details to it):
   * atoms are updated in index order; each update uses the coefficients and
@@ -16,7 +16,7 @@ Readings (the paper names K-SVD and leaves these details to it):
     matrix E_k, with its sign chosen so that it does not point away from the
     old atom; the users' coefficients become E_k^T d;
   * an atom that no training signal uses keeps its value during the sweep;
-    afterwards the replacement heuristics 3 and 4 of Section IV-B may
+    afterwards the replacement heuristics 3 and 4 of Section III-G may
     replace it (``replace_unused``): by the least represented training
     signal -- the one with the largest representation error
     ||x_j - x_hat_j|| left by the sparse-approximation step of the same
@@ -69,7 +69,7 @@ def update(X: np.ndarray, D: np.ndarray, support: np.ndarray, coef: np.ndarray):
 
 
 def init_children(X: np.ndarray, coarse_support: np.ndarray, q: int, t_low: int, rng) -> np.ndarray:
-    """Initial D_high (Section IV-B, heuristic 2): the Q children of coarse
+    """Initial D_high (Section III-G, heuristic 2): the Q children of coarse
     atom k are distinct training signals drawn at random from those whose
     coarse support contains k (unit norm); when fewer exist, from all."""
     n = X.shape[1]
@@ -88,7 +88,7 @@ def init_children(X: np.ndarray, coarse_support: np.ndarray, q: int, t_low: int,
 
 def replace_unused(D: np.ndarray, X: np.ndarray, support: np.ndarray, err: np.ndarray,
                    coarse_support: np.ndarray = None, q: int = 1):
-    """Heuristics 3 and 4 of Section IV-B.  D (T x N) atoms after the update
+    """Heuristics 3 and 4 of Section III-G.  D (T x N) atoms after the update
     sweep, X (P x N) training signals, support (P x kstride) the supports the
     sweep used, err (P,) every signal's representation error after the
     sparse-approximation step.  With coarse_support (P x k_low) and q, atom a

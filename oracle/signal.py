@@ -1,4 +1,4 @@
-"""Whole-signal patch processing around the OMP hot path (Section V): cut a
+"""Whole-signal patch processing around the OMP hot path (Section IV): cut a
 signal (image, video, light field) into overlapping patches, and put patch
 estimates back together by averaging every estimate that covers a sample.
 

@@ -1,4 +1,4 @@
-// Dictionary update of K-SVD (Section IV-A: the cross-scale dictionaries are
+// Dictionary update of K-SVD (Section III-E: the cross-scale dictionaries are
 // learned by K-SVD on the down-sampled training set, then by the same update
 // with the sparse-approximation step restricted to the children of the
 // coarse support).  The sparse-approximation step is the library's OMP; this

@@ -1,7 +1,7 @@
 // Full-dictionary OMP (Algorithm 1) over a large shared dictionary in
 // coefficient coordinates, for dictionaries beyond the per-patch kernels
 // (up to 8192 atoms of any length, sparsity up to 64): the work of the
-// paper's single-scale comparators (Section II-C and Section V's time versus
+// paper's single-scale comparators (Section II-C and Section IV's time versus
 // accuracy study).
 //
 // With A the shared effective dictionary (Phi D, or D under the identity),

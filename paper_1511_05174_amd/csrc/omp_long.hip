@@ -1,6 +1,6 @@
 // Per-patch OMP over long candidate vectors (more than 256 coordinates, up
 // to 2048): the paper's 24x24 RGB image patches, 8x8x32 video patches and
-// 4x4x8x8 light-field patches (Section V), at any scale of the cross-scale
+// 4x4x8x8 light-field patches (Section IV), at any scale of the cross-scale
 // model (Algorithm 2) or over every atom (Algorithm 1).
 //
 // One workgroup of 256 threads owns one patch and runs Algorithm 1 in the

@@ -1,4 +1,4 @@
-// Whole-signal patch processing around the OMP calls (Section V): cut a
+// Whole-signal patch processing around the OMP calls (Section IV): cut a
 // signal of up to 4 axes into overlapping patches (with their masks), and
 // put patch estimates back together as the mean of every estimate that
 // covers a sample.

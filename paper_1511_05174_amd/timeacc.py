@@ -5,11 +5,11 @@ The paper's evaluation method, at this library's speed:
   * dictionary size (Section II-C): full OMP (Algorithm 1) over single-scale
     dictionaries of T atoms at sparsity K -- time per patch against
     reconstruction PSNR, one curve per T as K grows;
-  * time versus accuracy (Section V, video denoising): the same
+  * time versus accuracy (Section IV, video denoising): the same
     single-scale points against zero-tree OMP (Algorithm 2) with K_low = 6
     and K_high = 8 over a two-scale dictionary of 512 / 8192 atoms, on
     8x8x32 video patches (coarse scale 4x4x16) at 15 dB input SNR;
-  * the effect of Q = T_high / T_low (Section IV, parameter selection):
+  * the effect of Q = T_high / T_low (Section III-F, parameter selection):
     cross-scale dictionaries trained for several (T_low, Q) on one training
     set, denoising PSNR on held-out patches.
 

@@ -1,4 +1,4 @@
-"""Learning cross-scale dictionaries (Section IV) with the library's kernels.
+"""Learning cross-scale dictionaries (Section III-E) with the library's kernels.
 
 Step 1: K-SVD on the down-sampled training set gives D_low (and, as a
 by-product, the coarse supports).  Step 2: K-SVD whose sparse-approximation
@@ -8,7 +8,7 @@ runs on ``cspd_omp_full`` / ``cspd_omp_cross_scale`` and the dictionary
 update on ``cspd_ksvd_update``; this module only sequences them (and builds
 the plans, which take host FP64 dictionaries).
 
-Initialisation (Section IV-B, heuristics 1 and 2): D_low from randomly
+Initialisation (Section III-G, heuristics 1 and 2): D_low from randomly
 picked training signals; the children of coarse atom k from randomly picked
 training signals whose coarse support holds k (all signals when fewer than Q
 do).  Replacement (heuristics 3 and 4): after each update sweep an atom that
@@ -128,7 +128,7 @@ def ksvd_step(X, xf: np.ndarray, D, k: int, replace: bool = True):
 
 def cross_scale_step(X, xf: np.ndarray, d_low: np.ndarray, D, up_map: np.ndarray, n_low: int, q: int,
                      k_low: int, k_high: int, replace: bool = True):
-    """One iteration of step 2 (Section IV-A): zero-tree OMP of the signals
+    """One iteration of step 2 (Section III-E): zero-tree OMP of the signals
     X (device, FP32; xf the same values in FP64 on the host) over D_low and
     D_high = D (device rows, updated in place or replaced), the K-SVD update
     sweep, then heuristic 4.  Returns (D, stats) with the supports, the
@@ -163,7 +163,7 @@ def cross_scale_step(X, xf: np.ndarray, d_low: np.ndarray, D, up_map: np.ndarray
 def cross_scale(x: np.ndarray, up_map: np.ndarray, n_low: int, t_low: int, q: int, k_low: int, k_high: int,
                 iters_low: int, iters_high: int, seed: int = 0, timings: Optional[dict] = None,
                 replace: bool = True):
-    """Section IV-A, steps 1 and 2.  Returns (D_low, D_high) as (T, N) atom
+    """Section III-E, steps 1 and 2.  Returns (D_low, D_high) as (T, N) atom
     rows; `timings` gets per-iteration (coding_s, update_s) lists under
     'low' and 'high' and the replaced atoms under 'replaced_low' and
     'replaced_high'."""

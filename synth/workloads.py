@@ -5,7 +5,7 @@ measurement operator, sparse codes, clean signals, noise and masks.  It holds
 none of the method's arithmetic (no correlation, selection or least squares);
 both the FP64 oracle and the HIP path consume the arrays it returns.
 
-Shapes follow the experiments of Section V of the paper (8x8 image patches,
+Shapes follow the experiments of Section IV of the paper (8x8 image patches,
 8x8x8 video patches, 5x5x4x4 light-field patches; fine dictionaries of up to
 4096 atoms, coarse ones of 64-256) and the cross-scale model of Section III-A:
 fine atom j is a child of coarse atom floor(j / Q) (the 0-based form of the
@@ -199,7 +199,7 @@ def synthesize(rng_coef, rng_noise, dict_f, support, phi_kind, phi, mask, sigma)
     return x, y
 
 
-# ---- structured measurement operators (Section V's acquisition models) ----
+# ---- structured measurement operators (Section IV's acquisition models) ----
 
 def bayer_mask(h: int, w: int) -> np.ndarray:
     """RGGB colour-filter array over an (h, w, 3) image: red at (even, even),

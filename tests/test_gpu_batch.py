@@ -1,7 +1,7 @@
 """Full OMP in coefficient coordinates (Gram matrix precomputed, correlations
 from one FP64 library GEMM) against the FP64 oracle (MI355X only): the
 single-scale comparators of the paper's dictionary-size and time versus
-accuracy studies (Section II-C, Section V) -- up to 8192 atoms, vectors of
+accuracy studies (Section II-C, Section IV) -- up to 8192 atoms, vectors of
 2048 coordinates (8x8x32 video patches), sparsity up to 64.  The batch is
 small so that the oracle (Householder QR at every step) finishes in seconds.
 """

@@ -70,7 +70,7 @@ def test_update_small_atoms_and_heavy_users():
 
 
 def test_cross_scale_learning_step():
-    """Step 2 of Section IV-A on a small training set: zero-tree OMP with the
+    """Step 2 of Section III-E on a small training set: zero-tree OMP with the
     current fine dictionary, then the update; the update is checked against
     the oracle on the GPU's own supports and coefficients."""
     torch = G.torch_mod()

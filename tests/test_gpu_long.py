@@ -1,5 +1,5 @@
 """Long candidate vectors (more than 256 coordinates) against the FP64 oracle
-(MI355X only): the patch shapes of the paper's experiments (Section V) --
+(MI355X only): the patch shapes of the paper's experiments (Section IV) --
 24x24 image patches over 12x12, 8x8x32 video patches over 4x4x16, 4x4x8x8
 light-field patches over 2x2x4x4 -- under the identity, a per-patch pixel
 mask and a shared dense operator, zero-tree OMP and full OMP.  Under a

@@ -1,4 +1,4 @@
-"""Structured measurement operators of the paper's experiments (Section V)
+"""Structured measurement operators of the paper's experiments (Section IV)
 against the FP64 oracle (MI355X only):
 
   * location-dependent coded exposure (videos): a per-pixel shutter tile

@@ -96,7 +96,7 @@ PAPER_SHAPES = [
 
 @pytest.mark.parametrize("name,shape,patch,stride,box,atoms", PAPER_SHAPES)
 def test_denoising_pipeline_at_the_paper_shapes(name, shape, patch, stride, box, atoms):
-    """Denoising of a whole signal at the paper's patch shapes (Section V: 24x24
+    """Denoising of a whole signal at the paper's patch shapes (Section IV: 24x24
     RGB image patches with an overlap of 18, 8x8x32 video patches, 4x4 views
     of 8x8 pixels): patches -> zero-tree OMP -> averaging, each stage against
     the oracle on the GPU stage's own input."""

@@ -1,4 +1,4 @@
-"""Learning cross-scale dictionaries with the library (Section IV; MI355X
+"""Learning cross-scale dictionaries with the library (Section III-E; MI355X
 only): the sequence of zero-tree OMP and K-SVD updates runs, keeps unit
 atoms, and lowers the representation error of the training set."""
 import numpy as np

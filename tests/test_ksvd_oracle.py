@@ -96,7 +96,7 @@ def test_init_children_draws_from_parent_users():
 
 
 def test_unused_atoms_take_the_least_represented_signals():
-    """Heuristic 3 (Section IV-B), worked by hand: atoms 1 and 3 have no user;
+    """Heuristic 3 (Section III-G), worked by hand: atoms 1 and 3 have no user;
     errors [0.1, 0.5, 0.5, 0.2] -> atom 1 takes signal 1 (largest error, lower
     index of the tie), atom 3 takes signal 2 (signal 1 is taken)."""
     X = np.array([[3.0, 4.0], [0.0, 2.0], [1.0, 0.0], [1.0, 1.0]])
