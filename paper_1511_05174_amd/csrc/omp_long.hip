@@ -37,14 +37,15 @@ constexpr int kWaves = kThreads / 64;
 constexpr int KX = kMaxK;
 constexpr int kCG = 8;   // candidates a wavefront scores at a time (their loads in flight together)
 
-template <typename T>
+// LMAX coordinates and CMAX candidates at most: the launch picks the smallest
+// instance that holds the scale, since LDS bounds the workgroups per CU
+template <typename T, int LMAX, int CMAX>
 struct Shared {
-    alignas(16) T yhat[kMaxLongLen];   // measurement in the scale's coordinates
-    alignas(16) T sqw[kMaxLongLen];    // per-coordinate weight (square root of observed samples)
-    alignas(16) T rw[kMaxLongLen];     // weighted residual sqw * r
-    T tmp[kMaxLongLen];      // staging of the fine samples' indicators (block folds)
-    int cand[kMaxLongCand];  // atom of each candidate slot; -1 once chosen or unusable
-    T inv_nu[kMaxLongCand];  // reciprocal weighted norm of each candidate
+    alignas(16) T yhat[LMAX];   // measurement in the scale's coordinates
+    alignas(16) T sqw[LMAX];    // per-coordinate weight (square root of observed samples)
+    alignas(16) T rw[LMAX];     // weighted residual sqw * r
+    int cand[CMAX];             // atom of each candidate slot; -1 once chosen or unusable
+    T inv_nu[CMAX];             // reciprocal weighted norm of each candidate
     double L[KX * KX];       // Cholesky factor of the support's Gram matrix (row-major)
     double z[KX];
     double alpha[KX];
@@ -129,7 +130,7 @@ __device__ __forceinline__ double wave_sum<double>(double v)
 // Measurement of patch b in the scale's coordinates (yhat) and the weight of
 // each coordinate (sqw: the square root of the observed fine samples folded
 // into it; 1 or 0 without blocks); st_y and st_c (n entries each) stage the
-// observed fine samples of block folds.  *count (zeroed here) receives the
+// observed fine samples of block folds, or are null to read them in place.  *count (zeroed here) receives the
 // coordinates of nonzero weight once the caller's next barrier has passed.
 template <typename T>
 __device__ void measure(const ScaleArgs &a, int64_t b, T *yhat, T *sqw, T *st_y, T *st_c, int *count)
@@ -150,6 +151,23 @@ __device__ void measure(const ScaleArgs &a, int64_t b, T *yhat, T *sqw, T *st_y,
             const bool obs = t < l && (mrow ? mrow[t] != 0 : true);
             yhat[t] = obs ? y[t] : T(0);
             sqw[t] = obs ? T(1) : T(0);
+        }
+    } else if (!st_y) {
+        // blocks of several fine samples, read in place: each coordinate
+        // folds its block (sum / sqrt(count), weight sqrt(count))
+        for (int t = tid; t < lp; t += kThreads) {
+            T cnt = 0, acc = 0;
+            if (t < l) {
+                for (int jj = a.blk_off[t]; jj < a.blk_off[t + 1]; ++jj) {
+                    const int j = a.blk_idx[jj];
+                    const bool obs = mrow ? mrow[j] != 0 : true;
+                    cnt += obs ? T(1) : T(0);
+                    acc += obs ? y[j] : T(0);
+                }
+            }
+            const T sq = sqrt(cnt);
+            yhat[t] = cnt > T(0) ? acc / sq : T(0);
+            sqw[t] = sq;
         }
     } else {
         // blocks of several fine samples: stage the observed samples, then
@@ -200,11 +218,11 @@ __device__ int candidates(const ScaleArgs &a, int64_t b, int *cand, int cap)
     return nc;
 }
 
-template <typename T>
+template <typename T, int LMAX, int CMAX>
 __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
 {
     static_assert(sizeof(T) == 4, "the candidate loops read FP32 rows as float4");
-    __shared__ Shared<T> sh;
+    __shared__ Shared<T, LMAX, CMAX> sh;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
@@ -218,8 +236,8 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
     const int lp = a.lp, l = a.l;
     const bool fold = a.fold == kFold;
 
-    measure(a, b, sh.yhat, sh.sqw, sh.rw, sh.tmp, &sh.count);
-    const int nc = candidates(a, b, sh.cand, kMaxLongCand);
+    measure(a, b, sh.yhat, sh.sqw, (T *)nullptr, (T *)nullptr, &sh.count);
+    const int nc = candidates(a, b, sh.cand, CMAX);
     for (int t = tid; t < lp; t += kThreads) sh.rw[t] = sh.sqw[t] * sh.yhat[t];
     __syncthreads();
     const int rank_bound = fold ? sh.count : a.m_dense;
@@ -728,8 +746,10 @@ cspd_status launch_long(int dtype, const ScaleArgs &a, int max_cand, hipStream_t
     const dim3 grid((unsigned)a.b), block(kThreads);
     if (gram)
         launch_timed(label, k_omp_long_gram<float>, grid, block, 0, st, a);
+    else if (a.lp <= 512 && max_cand <= 256)
+        launch_timed(label, k_omp_long<float, 512, 256>, grid, block, 0, st, a);
     else
-        launch_timed(label, k_omp_long<float>, grid, block, 0, st, a);
+        launch_timed(label, k_omp_long<float, kMaxLongLen, kMaxLongCand>, grid, block, 0, st, a);
     CSPD_HIP_CHECK(hipGetLastError());
     return CSPD_OK;
 }
