@@ -218,7 +218,7 @@ __device__ int candidates(const ScaleArgs &a, int64_t b, int *cand, int cap)
     return nc;
 }
 
-template <typename T, int LMAX, int CMAX>
+template <typename T, int LMAX, int CMAX, int CG>
 __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
 {
     static_assert(sizeof(T) == 4, "the candidate loops read FP32 rows as float4");
@@ -248,27 +248,27 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
     K = K < KX ? K : KX;
     K = K > 0 ? K : 0;
 
-    // ---- weighted norms of the candidates (kCG per wavefront at a time) ----
+    // ---- weighted norms of the candidates (CG per wavefront at a time) ----
     const int l4 = (l + 3) >> 2;   // 16-byte groups that hold the used coordinates (rows are padded with zeros)
     const float4 *sqw4 = reinterpret_cast<const float4 *>(sh.sqw);
     const float4 *rw4 = reinterpret_cast<const float4 *>(sh.rw);
-    for (int i0 = wv * kCG; i0 < nc; i0 += kWaves * kCG) {
-        const float4 *vp[kCG];
+    for (int i0 = wv * CG; i0 < nc; i0 += kWaves * CG) {
+        const float4 *vp[CG];
 #pragma unroll
-        for (int c = 0; c < kCG; ++c)
+        for (int c = 0; c < CG; ++c)
             vp[c] = reinterpret_cast<const float4 *>(v + (int64_t)(i0 + c < nc ? sh.cand[i0 + c] : 0) * lp);
-        float acc[kCG] = {};
+        float acc[CG] = {};
         for (int t4 = lane; t4 < l4; t4 += 64) {
             const float4 w = sqw4[t4];
 #pragma unroll
-            for (int c = 0; c < kCG; ++c) {
+            for (int c = 0; c < CG; ++c) {
                 const float4 x = vp[c][t4];
                 const float a0 = x.x * w.x, a1 = x.y * w.y, a2 = x.z * w.z, a3 = x.w * w.w;
                 acc[c] += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
             }
         }
 #pragma unroll
-        for (int c = 0; c < kCG; ++c) {
+        for (int c = 0; c < CG; ++c) {
             const float s = wave_sum(acc[c]);
             if (lane == 0 && i0 + c < nc) sh.inv_nu[i0 + c] = s > 0.f ? 1.f / sqrtf(s) : -1.f;
         }
@@ -284,29 +284,29 @@ __global__ __launch_bounds__(kThreads) void k_omp_long(ScaleArgs a)
         // proxy and argmax: each wavefront keeps its best (score, slot)
         T best = T(-1);
         int bslot = -1;
-        for (int i0 = wv * kCG; i0 < nc; i0 += kWaves * kCG) {
-            int at[kCG];
-            const float4 *vp[kCG];
+        for (int i0 = wv * CG; i0 < nc; i0 += kWaves * CG) {
+            int at[CG];
+            const float4 *vp[CG];
 #pragma unroll
-            for (int c = 0; c < kCG; ++c) {
+            for (int c = 0; c < CG; ++c) {
                 at[c] = i0 + c < nc ? sh.cand[i0 + c] : -1;
                 vp[c] = reinterpret_cast<const float4 *>(v + (int64_t)(at[c] >= 0 ? at[c] : 0) * lp);
             }
             bool any = false;
 #pragma unroll
-            for (int c = 0; c < kCG; ++c) any = any || at[c] >= 0;
+            for (int c = 0; c < CG; ++c) any = any || at[c] >= 0;
             if (!any) continue;   // wavefront-uniform
-            float acc[kCG] = {};
+            float acc[CG] = {};
             for (int t4 = lane; t4 < l4; t4 += 64) {
                 const float4 r = rw4[t4];
 #pragma unroll
-                for (int c = 0; c < kCG; ++c) {
+                for (int c = 0; c < CG; ++c) {
                     const float4 x = vp[c][t4];
                     acc[c] += x.x * r.x + x.y * r.y + x.z * r.z + x.w * r.w;
                 }
             }
 #pragma unroll
-            for (int c = 0; c < kCG; ++c) {
+            for (int c = 0; c < CG; ++c) {
                 const float sc = fabsf(wave_sum(acc[c])) * (at[c] >= 0 ? sh.inv_nu[i0 + c] : 0.f);
                 const bool up = at[c] >= 0 && (bslot < 0 || sc > best || (sc == best && at[c] < sh.cand[bslot]));
                 best = up ? sc : best;
@@ -747,9 +747,9 @@ cspd_status launch_long(int dtype, const ScaleArgs &a, int max_cand, hipStream_t
     if (gram)
         launch_timed(label, k_omp_long_gram<float>, grid, block, 0, st, a);
     else if (a.lp <= 512 && max_cand <= 256)
-        launch_timed(label, k_omp_long<float, 512, 256>, grid, block, 0, st, a);
+        launch_timed(label, k_omp_long<float, 512, 256, 4>, grid, block, 0, st, a);
     else
-        launch_timed(label, k_omp_long<float, kMaxLongLen, kMaxLongCand>, grid, block, 0, st, a);
+        launch_timed(label, k_omp_long<float, kMaxLongLen, kMaxLongCand, kCG>, grid, block, 0, st, a);
     CSPD_HIP_CHECK(hipGetLastError());
     return CSPD_OK;
 }
