@@ -453,18 +453,29 @@ constexpr int kBuf = 3;               // chunks whose loads are in flight
 constexpr int kXld = kGramCand + 2;   // keeps rows 16-byte aligned and spreads the staging stores over banks
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// LDS by phase: the measurement and weights live until the list of
+// observed coordinates is built, then their space holds the staged chunks;
+// the list (16-bit coordinates, weights, measurement) lives through the
+// formation, then its space holds the packed Gram matrix.
 template <typename T>
 struct GramShared {
-    T yhat[kMaxLongLen];
-    T sqw[kMaxLongLen];
     union {
-        T stage[2 * kMaxLongLen];   // block-fold staging (measurement only)
-        double G[kGramTri];         // packed upper triangle of the weighted Gram matrix
-    } u;
-    int idx[kMaxLongLen];           // coordinates of nonzero weight, ascending
-    alignas(16) double X[kCh][kXld];  // staged chunk: weighted candidate values [coordinate][slot]
-    double yw[kCh];                 // yhat at the chunk's coordinates (already folded: one weight factor)
-    double h[kGramCand];            // weighted correlations with the measurement
+        struct {
+            T yhat[kMaxLongLen];
+            T sqw[kMaxLongLen];
+        } m;                            // measurement in the scale's coordinates and weights
+        double X[kCh][kXld];            // staged chunk: weighted candidate values [coordinate][slot]
+    } a;
+    union {
+        struct {
+            unsigned short idx[kMaxLongLen];   // coordinates of nonzero weight, ascending
+            T wc[kMaxLongLen];                 // their weights
+            T yc[kMaxLongLen];                 // their measurement values
+        } c;
+        double G[kGramTri];             // packed upper triangle of the weighted Gram matrix
+    } b;
+    double yw[kCh];                     // yhat at the chunk's coordinates (already folded: one weight factor)
+    double h[kGramCand];                // weighted correlations with the measurement
     int cand[kGramCand];
     double L[KX * KX];
     double z[KX];
@@ -500,7 +511,7 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
     // that the workgroups sharing a CU do not load the same SIMDs
     const int role = (wv + (int)(b & 3)) & 3;
 
-    measure(a, b, sh.yhat, sh.sqw, sh.u.stage, sh.u.stage + kMaxLongLen, &sh.count);
+    measure(a, b, sh.a.m.yhat, sh.a.m.sqw, (T *)nullptr, (T *)nullptr, &sh.count);
     const int nc = candidates(a, b, sh.cand, kGramCand);
 
     // ---- observed coordinates, ascending (each wavefront a contiguous range)
@@ -510,7 +521,7 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
         int c = 0;
         for (int t0 = lo; t0 < lo + seg; t0 += 64) {
             const int t = t0 + lane;
-            c += __popcll(__ballot(t < lp && sh.sqw[t] > T(0)));
+            c += __popcll(__ballot(t < lp && sh.a.m.sqw[t] > T(0)));
         }
         if (lane == 0) sh.wcnt[wv] = c;
     }
@@ -529,9 +540,14 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
     }
     for (int t0 = lo; t0 < lo + seg; t0 += 64) {
         const int t = t0 + lane;
-        const bool o = t < lp && sh.sqw[t] > T(0);
+        const bool o = t < lp && sh.a.m.sqw[t] > T(0);
         const unsigned long long m = __ballot(o);
-        if (o) sh.idx[base + __popcll(m & ((1ull << lane) - 1ull))] = t;
+        if (o) {
+            const int p = base + __popcll(m & ((1ull << lane) - 1ull));
+            sh.b.c.idx[p] = (unsigned short)t;
+            sh.b.c.wc[p] = sh.a.m.sqw[t];
+            sh.b.c.yc[p] = sh.a.m.yhat[t];
+        }
         base += __popcll(m);
     }
     __syncthreads();
@@ -549,9 +565,10 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
         }
         auto fetch_to = [&](T (&buf)[kPer], int &ptv, int p0) {
             const int p = p0 + spp;
-            ptv = p < M ? sh.idx[p] : -1;
+            ptv = p < M ? p : -1;   // position in the list of observed coordinates
+            const int t = ptv >= 0 ? (int)sh.b.c.idx[ptv] : 0;
 #pragma unroll
-            for (int r = 0; r < kPer; ++r) buf[r] = (ptv >= 0 && rowp[r]) ? rowp[r][ptv] : T(0);
+            for (int r = 0; r < kPer; ++r) buf[r] = (ptv >= 0 && rowp[r]) ? rowp[r][t] : T(0);
         };
         // tiles of this wavefront's role: G's ten upper 16x16 tiles, three
         // each for roles 0-2, one for role 3 (which also forms h).  Tile t
@@ -576,10 +593,10 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
         auto run_chunk = [&](T (&buf)[kPer], int &ptv, int p0) {
             __syncthreads();   // the previous chunk has been consumed
             {
-                const double w = ptv >= 0 ? (double)sh.sqw[ptv] : 0.0;
+                const double w = ptv >= 0 ? (double)sh.b.c.wc[ptv] : 0.0;
 #pragma unroll
-                for (int r = 0; r < kPer; ++r) sh.X[spp][(tid + r * kThreads) / kCh] = (double)buf[r] * w;
-                if (tid < kCh) sh.yw[tid] = ptv >= 0 ? (double)sh.yhat[ptv] : 0.0;
+                for (int r = 0; r < kPer; ++r) sh.a.X[spp][(tid + r * kThreads) / kCh] = (double)buf[r] * w;
+                if (tid < kCh) sh.yw[tid] = ptv >= 0 ? (double)sh.b.c.yc[ptv] : 0.0;
             }
             __syncthreads();
             if (p0 + kBuf * kCh < M) fetch_to(buf, ptv, p0 + kBuf * kCh);
@@ -587,7 +604,7 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
             // the chunk's coordinates, four per matrix-core step
 #pragma unroll
             for (int ks = 0; ks < kCh / 4; ++ks) {
-                const double *xr = sh.X[4 * ks + fk];
+                const double *xr = sh.a.X[4 * ks + fk];
 #pragma unroll
                 for (int t = 0; t < 3; ++t) {
                     if (t < ntile)   // wavefront-uniform
@@ -597,7 +614,7 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
             }
             if (role == 3) {
 #pragma unroll
-                for (int pp = 0; pp < kCh; ++pp) hacc = fma(sh.X[pp][lane], sh.yw[pp], hacc);
+                for (int pp = 0; pp < kCh; ++pp) hacc = fma(sh.a.X[pp][lane], sh.yw[pp], hacc);
             }
         };
         T buf[kBuf][kPer];
@@ -621,7 +638,7 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int gi = 16 * ti[t] + 4 * r + fk, gj = 16 * tj[t] + fi;
-                    if (gi <= gj) sh.u.G[tri(gi, gj)] = acc[t][r];
+                    if (gi <= gj) sh.b.G[tri(gi, gj)] = acc[t][r];
                 }
             }
         }
@@ -639,7 +656,7 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
         // The coefficients are solved once, after the last pick.
         if (role == 3) {
             const int ci = lane < nc ? sh.cand[lane] : -1;
-            const double gii = ci >= 0 ? sh.u.G[tri(lane, lane)] : 0.0;
+            const double gii = ci >= 0 ? sh.b.G[tri(lane, lane)] : 0.0;
             bool live = ci >= 0 && gii > 0.0;
             const double rn = live ? 1.0 / sqrt(gii) : 0.0;
             double c = sh.h[lane], e = gii;
@@ -676,7 +693,7 @@ __global__ __launch_bounds__(kThreads) void k_omp_long_gram(ScaleArgs a)
                 double dot = 0.0;
 #pragma unroll
                 for (int j = 0; j < it; ++j) dot = fma(uk[j], u[j], dot);
-                const double un = (live ? sh.u.G[tri(lane, ps)] - dot : 0.0) / lnn;
+                const double un = (live ? sh.b.G[tri(lane, ps)] - dot : 0.0) / lnn;
                 u[it] = un;
                 c = fma(-un, zn, c);
                 e = fma(-un, un, e);
