@@ -104,6 +104,27 @@ def test_coded_exposure_grouping_skewed():
     assert "proxy_gemm<f32,groups>:s0" in cspd.cspd_profile_read()
 
 
+def test_many_operators_grouping():
+    """64 operators (four sign-flipped copies of the 16 coded-exposure
+    shifts) over 900 patches: most operators hold a handful of patches, so
+    almost every tile of the grouped first-scale GEMM is ragged; against the
+    oracle."""
+    import dataclasses
+    w = synth.make("c4loc", batch=900)
+    rng = np.random.default_rng(21)
+    phis = np.concatenate([w.phi * rng.choice([-1.0, 1.0], size=(1, 1, w.phi.shape[2])) for _ in range(4)])
+    ph = rng.integers(0, phis.shape[0], size=w.batch).astype(np.int32)
+    w2 = dataclasses.replace(w, phi=phis, phase=ph)
+    plan = cspd.plan_from_workload(w2)
+    out = run_phased(plan, w2)
+    ks = w2.k_scales
+    wo = G.with_y(w2, out["y64"])
+    sup = parity.gpu_scales(w2, out["support"], out["k_used"], out["support_coarse"], ks[:-1])
+    rep = parity.compare(wo, sup, out["coef"], out["k_used"], out["xhat"], k_scales=ks, tie_tol=TOL["f32"]["tie"])
+    print(f"[64 operators, B={w2.batch}] {rep.summary()}", flush=True)
+    rep.check(TOL["f32"]["coef"], TOL["f32"]["xhat"])
+
+
 def test_bayer_demosaicing():
     w = synth.make("bayer", batch=300)
     # each patch observes one colour per pixel
