@@ -87,3 +87,35 @@ def test_long_ragged_sparsity_and_capped_candidates():
     import dataclasses
     w = dataclasses.replace(w, k_fine=kf)
     check_cross(w)
+
+
+def test_long_vectors_several_operators():
+    """Three dense operators of 512 measurements over 1,024-sample light-field
+    patches, one per patch: every scale's effective vectors have 512
+    coordinates, so the long-vector kernel runs each patch on its own
+    operator's candidates (the Gram mode at the first scale's 32 atoms, the
+    proxy loop above 64 candidates)."""
+    import dataclasses
+    from test_gpu_operators import run_phased
+    import parity
+    from test_gpu_parity import TOL
+    w = long_workload("lf", 150, seed=35, atoms=(32, 512), ks=(5, 8), phi_kind="dense", m=512)
+    rng = np.random.default_rng(8)
+    phis = np.stack([w.phi * rng.choice([-1.0, 1.0], size=(1, w.phi.shape[1])) for _ in range(3)])
+    ph = rng.integers(0, 3, size=w.batch).astype(np.int32)
+    w2 = dataclasses.replace(w, phi=phis, phase=ph)
+    plan = cspd.plan_from_workload(w2)
+    out = run_phased(plan, w2)
+    ks = w2.k_scales
+    wo = G.with_y(w2, out["y64"])
+    sup = parity.gpu_scales(w2, out["support"], out["k_used"], out["support_coarse"], ks[:-1])
+    rep = parity.compare(wo, sup, out["coef"], out["k_used"], out["xhat"], k_scales=ks, tie_tol=TOL["f32"]["tie"])
+    print(f"[3 operators, 512 measurements, B={w2.batch}] {rep.summary()}", flush=True)
+    rep.check(TOL["f32"]["coef"], TOL["f32"]["xhat"])
+    cspd.cspd_profile_reset()
+    cspd.cspd_profile_enable(True)
+    run_phased(plan, w2)
+    cspd.cspd_profile_enable(False)
+    labels = sorted(cspd.cspd_profile_read())
+    assert any(l.startswith("omp_long<f32,gram,") and l.endswith(":s0") for l in labels), labels
+    assert any(l.startswith("omp_long<f32,lp") and l.endswith(":s1") for l in labels), labels
