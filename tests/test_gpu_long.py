@@ -52,6 +52,9 @@ def _kernels(plan, w):
     # 70 candidates at the finest scale (above the Gram mode's 64): the
     # proxy loop, its candidate groups ragged at the end of the list
     ("img24", "mask", (64, 640), (7, 6), 173),
+    # 128 first-scale candidates over 2x2 blocks of a random mask (blocks
+    # with nothing observed weigh 0): the proxy loop's small instance
+    ("img24", "mask", (128, 1024), (3, 6), 150),
 ])
 def test_long_cross(shape, phi_kind, atoms, ks, batch):
     w = long_workload(shape, batch, seed=31, atoms=atoms, ks=ks, phi_kind=phi_kind)
