@@ -125,6 +125,23 @@ def test_many_operators_grouping():
     rep.check(TOL["f32"]["coef"], TOL["f32"]["xhat"])
 
 
+def test_coded_exposure_full_size_sampled():
+    """The bench's location-dependent coded-exposure batch (32,768 patches,
+    16 operators: about 64 tiles per operator in the grouped GEMM); 256
+    sampled patches against the oracle."""
+    w = synth.make("c4loc")
+    plan = cspd.plan_from_workload(w)
+    out = run_phased(plan, w)
+    idx = np.random.default_rng(4).choice(w.batch, 256, replace=False)
+    ws = G.with_y(synth.subset(w, idx), out["y64"][idx])
+    ks = w.k_scales
+    sup = parity.gpu_scales(ws, out["support"][idx], out["k_used"][idx], out["support_coarse"][idx], ks[:-1])
+    rep = parity.compare(ws, sup, out["coef"][idx], out["k_used"][idx], out["xhat"][idx], k_scales=ks,
+                         tie_tol=TOL["f32"]["tie"])
+    print(f"[coded exposure full-size sampled] {rep.summary()}", flush=True)
+    rep.check(TOL["f32"]["coef"], TOL["f32"]["xhat"])
+
+
 def test_bayer_demosaicing():
     w = synth.make("bayer", batch=300)
     # each patch observes one colour per pixel
