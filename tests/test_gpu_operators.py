@@ -150,6 +150,23 @@ def test_bayer_demosaicing():
     check_cross(w)
 
 
+def test_bayer_full_size_sampled():
+    """The bench's Bayer batch (4,096 patches of 24x24x3 through the CFA:
+    the long kernel's proxy loop and Gram mode in their launch
+    configuration); 128 sampled patches against the oracle."""
+    w = synth.make("bayer")
+    plan = cspd.plan_from_workload(w)
+    out = G.run_cross(plan, w)
+    idx = np.random.default_rng(6).choice(w.batch, 128, replace=False)
+    ws = G.with_y(synth.subset(w, idx), out["y64"][idx])
+    ks = w.k_scales
+    sup = parity.gpu_scales(ws, out["support"][idx], out["k_used"][idx], out["support_coarse"][idx], ks[:-1])
+    rep = parity.compare(ws, sup, out["coef"][idx], out["k_used"][idx], out["xhat"][idx], k_scales=ks,
+                         tie_tol=TOL["f32"]["tie"])
+    print(f"[Bayer full-size sampled] {rep.summary()}", flush=True)
+    rep.check(TOL["f32"]["coef"], TOL["f32"]["xhat"])
+
+
 def test_coded_aperture_light_field():
     w = synth.make("lfca", batch=2000)
     assert w.phi.shape == (128, 1024)
